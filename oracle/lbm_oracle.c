@@ -1,0 +1,515 @@
+/*
+ * lbm_oracle.c -- plain FP64 CPU oracle for the growing-tissue D2Q9 lattice
+ * Boltzmann method of arXiv 2303.02210.  TEST INFRASTRUCTURE ONLY (see the
+ * header): the product path never calls this code.
+ *
+ * The update is the paper's Appendix A algorithm, steps 1-7, applied to every
+ * site of the live window, followed by the front heights, the width w(t) and
+ * the rear-wall rule of Appendix A's last paragraph.  The paper works on the
+ * triangular D2Q7 lattice; this oracle uses the square D2Q9 lattice with the
+ * textbook weights (4/9, 1/9, 1/36) and sound speed c_s^2 = 1/3, so the
+ * steady state of Eq. 3 reads w_i rho (1 + 3 e.u* + 9/2 (e.u*)^2 - 3/2 |u*|^2)
+ * and the zero-sum noise of Eq. 4 subtracts the mean over 9 directions.
+ *
+ * Direction numbering: 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE.
+ * Reverse pairs: 1<->3, 2<->4, 5<->7, 6<->8.  x is periodic (columns), y is
+ * the growth axis (rows); the rear wall sits half a lattice unit below the
+ * first live row.
+ *
+ * Compile with -ffp-contract=off: every product and sum below is rounded on
+ * its own, in the order written.
+ */
+#include "lbm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ----------------------------------------------------------------------- */
+/* Lattice                                                                   */
+/* ----------------------------------------------------------------------- */
+static const int32_t CX[9]  = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int32_t CY[9]  = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int32_t OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+static double weight(int i)
+{
+    if (i == 0) return 4.0 / 9.0;
+    if (i <= 4) return 1.0 / 9.0;
+    return 1.0 / 36.0;
+}
+
+void orc_lattice(int32_t cx[9], int32_t cy[9], int32_t opp[9], double w[9])
+{
+    for (int i = 0; i < 9; ++i) {
+        cx[i] = CX[i];
+        cy[i] = CY[i];
+        opp[i] = OPP[i];
+        w[i] = weight(i);
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Philox4x32-10, from its definition in Salmon et al., SC'11: each round    */
+/* multiplies counter words 0 and 2 by two fixed odd constants, swaps the    */
+/* halves and xors in the key; the key is bumped by two Weyl constants       */
+/* between rounds.                                                           */
+/* ----------------------------------------------------------------------- */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Random streams: the fourth counter word is 4*stream + call. */
+enum { STREAM_NOISE = 0, STREAM_INIT = 1 };
+
+static double u24(uint32_t k24)
+{
+    /* (k + 1/2) 2^-24: exact in double, strictly inside (0, 1) */
+    return ((double)k24 + 0.5) * (1.0 / 16777216.0);
+}
+
+void orc_noise_bits(uint32_t seed, uint32_t replica, int64_t t, int32_t x,
+                    int64_t y_abs, uint32_t k_out[9])
+{
+    uint32_t key[2] = {seed, replica};
+    uint32_t ctr[4] = {(uint32_t)x, (uint32_t)y_abs, (uint32_t)t, 4u * STREAM_NOISE + 0u};
+    uint32_t a[4], b[4];
+    orc_philox4x32_10(ctr, key, a);
+    ctr[3] = 4u * STREAM_NOISE + 1u;
+    orc_philox4x32_10(ctr, key, b);
+    /* eight draws from the top 24 bits of the eight words ... */
+    for (int i = 0; i < 4; ++i) {
+        k_out[i] = a[i] >> 8;
+        k_out[4 + i] = b[i] >> 8;
+    }
+    /* ... and the ninth from the low bytes of the first three words */
+    k_out[8] = ((a[0] & 0xFFu) << 16) | ((a[1] & 0xFFu) << 8) | (a[2] & 0xFFu);
+}
+
+void orc_noise_uniforms(uint32_t seed, uint32_t replica, int64_t t, int32_t x,
+                        int64_t y_abs, double u_out[9])
+{
+    uint32_t k[9];
+    orc_noise_bits(seed, replica, t, x, y_abs, k);
+    for (int i = 0; i < 9; ++i) u_out[i] = u24(k[i]);
+}
+
+double orc_init_uniform(uint32_t seed, uint32_t replica, int32_t x, int64_t y_abs)
+{
+    uint32_t key[2] = {seed, replica};
+    uint32_t ctr[4] = {(uint32_t)x, (uint32_t)y_abs, 0u, 4u * STREAM_INIT + 0u};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    return u24(r[0] >> 8);
+}
+
+/* ----------------------------------------------------------------------- */
+/* Eq. 3 on D2Q9                                                             */
+/* ----------------------------------------------------------------------- */
+void orc_fss(double rho, double ux, double uy, double out[9])
+{
+    double usq = ux * ux + uy * uy;
+    for (int i = 0; i < 9; ++i) {
+        /* e_i . u*, written as a sum of the signed velocity components */
+        double cu;
+        if (CX[i] == 0 && CY[i] == 0) cu = 0.0;
+        else if (CY[i] == 0) cu = (CX[i] > 0) ? ux : -ux;
+        else if (CX[i] == 0) cu = (CY[i] > 0) ? uy : -uy;
+        else cu = ((CX[i] > 0) ? ux : -ux) + ((CY[i] > 0) ? uy : -uy);
+        double wr = weight(i) * rho;
+        out[i] = wr * (((1.0 + 3.0 * cu) + 4.5 * (cu * cu)) - 1.5 * usq);
+    }
+}
+
+/* ----------------------------------------------------------------------- */
+/* Window storage                                                            */
+/* ----------------------------------------------------------------------- */
+struct orc_state {
+    orc_params p;
+    double    *f;      /* [9][H][L]; window row j holds absolute row y_wall + j */
+    double    *fn;     /* next populations                                       */
+    int32_t   *h;      /* [L] front heights (absolute rows)                      */
+    int64_t    t;
+    int64_t    y_wall;
+    int64_t    h_hi;
+    double     mass, src_total, fix_total, retired, hbar, W;
+    uint32_t   status;
+};
+
+static size_t idx(const orc_params *p, int i, int32_t j, int32_t x)
+{
+    return ((size_t)i * (size_t)p->H + (size_t)j) * (size_t)p->L + (size_t)x;
+}
+
+static int params_valid(const orc_params *p)
+{
+    if (p->L < 1 || p->H < 2) return 0;
+    if (!(p->tau > 0.5)) return 0;
+    if (!(p->rho_c > 0.0)) return 0;
+    if (!(p->sigma >= 0.0) || !(p->growth_rate >= 0.0)) return 0;
+    if (!(p->mu >= 0.0 && p->mu <= 1.0)) return 0;
+    if (!(p->init_amp >= 0.0 && p->init_amp < 1.0)) return 0;
+    if (!(p->rho_init >= 0.0)) return 0;
+    if (p->init_rows < 0 || p->init_rows > p->H) return 0;
+    if (p->growth != ORC_GROWTH_NONE && p->growth != ORC_GROWTH_BULK) return 0;
+    if (p->region < ORC_REGION_ALL || p->region > ORC_REGION_REAR_BAND) return 0;
+    if (p->region != ORC_REGION_ALL && p->region_width < 0) return 0;
+    if (p->ybc < ORC_Y_WALL_FIXED || p->ybc > ORC_Y_PERIODIC) return 0;
+    if (p->ybc == ORC_Y_WALL_FOLLOW && (p->wall_min_gap < 0 || !(p->wall_w_factor >= 0.0))) return 0;
+    return 1;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Step 1: streaming, pulled to the receiving site                           */
+/* ----------------------------------------------------------------------- */
+void orc_pull_site(const orc_params *p, const double *f, int32_t x, int32_t j, double fstar[9])
+{
+    for (int i = 0; i < 9; ++i) {
+        int32_t xs = ((x - CX[i]) % p->L + p->L) % p->L;   /* periodic in x */
+        int32_t js = j - CY[i];
+        if (p->ybc == ORC_Y_PERIODIC) {
+            js = (js % p->H + p->H) % p->H;
+            fstar[i] = f[idx(p, i, js, xs)];
+        } else if (js < 0) {
+            /* rear wall, half a unit below row 0: what left this site
+             * towards the wall comes straight back (bounce-back) */
+            fstar[i] = f[idx(p, OPP[i], j, x)];
+        } else if (js >= p->H) {
+            /* nothing lies beyond the top of the window */
+            fstar[i] = 0.0;
+        } else {
+            fstar[i] = f[idx(p, i, js, xs)];
+        }
+    }
+}
+
+static int in_region(const orc_params *p, int64_t y_abs, int32_t h_prev_x, int64_t y_wall)
+{
+    if (p->region == ORC_REGION_FRONT_BAND)
+        return y_abs >= (int64_t)h_prev_x - (int64_t)p->region_width;
+    if (p->region == ORC_REGION_REAR_BAND)
+        return y_abs < y_wall + (int64_t)p->region_width;
+    return 1;
+}
+
+static double sum9(const double v[9])
+{
+    double s = v[0];
+    for (int i = 1; i < 9; ++i) s = s + v[i];
+    return s;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Steps 2-7 at one site                                                     */
+/* ----------------------------------------------------------------------- */
+int orc_update_site(const orc_params *p, const double fstar_in[9], int64_t t,
+                    int32_t x, int64_t y_abs, int32_t h_prev_x, int64_t y_wall,
+                    int force, double out[9], double *S_out, double *dfix_out)
+{
+    double fs[9];
+    for (int i = 0; i < 9; ++i) fs[i] = fstar_in[i];
+    *S_out = 0.0;
+    *dfix_out = 0.0;
+
+    /* step 2: density and momentum of the streamed populations (Eq. 1) */
+    double rho_star = sum9(fs);
+    double jx = ((((fs[1] - fs[3]) + fs[5]) - fs[6]) - fs[7]) + fs[8];
+    double jy = ((((fs[2] - fs[4]) + fs[5]) + fs[6]) - fs[7]) - fs[8];
+
+    /* step 5's test, taken on the streamed density: tissue or void */
+    int tissue = (force < 0) ? (rho_star >= p->rho_c) : (force > 0);
+
+    if (!tissue) {
+        /* step 5, second case: reverse every direction (bounce-back front) */
+        for (int i = 0; i < 9; ++i) out[i] = fs[OPP[i]];
+        return 0;
+    }
+
+    /* step 3: mass from proliferation, in expectation: S = g rho* shared
+     * equally by the eight moving directions (pairs of opposite directions
+     * receive equal amounts, so no momentum is added) */
+    double S = 0.0;
+    if (p->growth == ORC_GROWTH_BULK && in_region(p, y_abs, h_prev_x, y_wall))
+        S = p->growth_rate * rho_star;
+    double s8 = S * 0.125;
+    for (int i = 1; i < 9; ++i) fs[i] = fs[i] + s8;
+    double rho = rho_star + S;
+    *S_out = S;
+
+    /* step 4: u* = (1 - mu) u and the steady state of Eq. 3 */
+    double kmu = 1.0 - p->mu;
+    double ux = (jx / rho) * kmu;
+    double uy = (jy / rho) * kmu;
+    double fss[9];
+    orc_fss(rho, ux, uy, fss);
+
+    /* step 5, first case: relax towards the steady state (Eq. 2) */
+    double omega = 1.0 / p->tau;
+    for (int i = 0; i < 9; ++i) out[i] = fs[i] - omega * (fs[i] - fss[i]);
+
+    /* step 6: zero-sum uniform noise of Eq. 4, only where rho > rho_c */
+    if (rho > p->rho_c && p->sigma > 0.0) {
+        double u[9], eta[9];
+        orc_noise_uniforms(p->seed, p->replica, t, x, y_abs, u);
+        for (int i = 0; i < 9; ++i) eta[i] = p->sigma * (2.0 * u[i] - 1.0);
+        double m = sum9(eta) / 9.0;
+        for (int i = 0; i < 9; ++i) out[i] = out[i] + (eta[i] - m);
+    }
+
+    /* step 7: remove negative populations */
+    int any_negative = 0;
+    for (int i = 0; i < 9; ++i) if (out[i] < 0.0) any_negative = 1;
+    if (any_negative) {
+        double before = sum9(out);
+        if (out[0] < 0.0) {
+            /* zero the rest population, then rescale all nine so that the
+             * site keeps the density it had before the zeroing */
+            double rho_pre = sum9(out);
+            out[0] = 0.0;
+            double rest = sum9(out);
+            if (rest > 0.0) {
+                double r = rho_pre / rest;
+                for (int i = 0; i < 9; ++i) out[i] = out[i] * r;
+            }
+        }
+        for (int i = 1; i < 9; ++i) {
+            if (out[i] < 0.0) {
+                /* the magnitude goes to the reverse direction */
+                out[OPP[i]] = out[OPP[i]] + (-out[i]);
+                out[i] = 0.0;
+            }
+        }
+        *dfix_out = sum9(out) - before;
+    }
+    return 1;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Diagnostics: h(x), its mean and the width w(t)                            */
+/* ----------------------------------------------------------------------- */
+static void width_of(const orc_state *s, double *hbar, double *W)
+{
+    const int32_t L = s->p.L;
+    double sum = 0.0;
+    for (int32_t x = 0; x < L; ++x) sum += (double)s->h[x];
+    double mean = sum / (double)L;
+    double ss = 0.0;
+    for (int32_t x = 0; x < L; ++x) {
+        double d = (double)s->h[x] - mean;
+        ss += d * d;
+    }
+    *hbar = mean;
+    *W = sqrt(ss / (double)L);
+}
+
+static double window_mass(const orc_state *s)
+{
+    const orc_params *p = &s->p;
+    double m = 0.0;
+    for (int32_t j = 0; j < p->H; ++j)
+        for (int32_t x = 0; x < p->L; ++x) {
+            double v[9];
+            for (int i = 0; i < 9; ++i) v[i] = s->f[idx(p, i, j, x)];
+            m += sum9(v);
+        }
+    return m;
+}
+
+static void check_front(orc_state *s)
+{
+    const orc_params *p = &s->p;
+    int64_t hmax = s->h[0];
+    for (int32_t x = 1; x < p->L; ++x) if (s->h[x] > hmax) hmax = s->h[x];
+    if (hmax > s->h_hi) s->h_hi = hmax;
+    if (p->ybc != ORC_Y_PERIODIC && hmax >= s->y_wall + (int64_t)p->H)
+        s->status |= ORC_ST_DOMAIN_FULL;
+    if (!isfinite(s->mass)) s->status |= ORC_ST_NONFINITE;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Life cycle                                                                */
+/* ----------------------------------------------------------------------- */
+size_t orc_state_bytes(const orc_params *p)
+{
+    return 2u * 9u * (size_t)p->L * (size_t)p->H * sizeof(double) + (size_t)p->L * sizeof(int32_t);
+}
+
+orc_state *orc_create(const orc_params *p)
+{
+    if (!p || !params_valid(p)) return NULL;
+    orc_state *s = (orc_state *)calloc(1, sizeof(orc_state));
+    if (!s) return NULL;
+    s->p = *p;
+    size_t n = 9u * (size_t)p->L * (size_t)p->H;
+    s->f = (double *)calloc(n, sizeof(double));
+    s->fn = (double *)calloc(n, sizeof(double));
+    s->h = (int32_t *)calloc((size_t)p->L, sizeof(int32_t));
+    if (!s->f || !s->fn || !s->h) { orc_destroy(s); return NULL; }
+
+    /* Appendix A initialisation: u = 0, rho uniform around rho_init in the
+     * first init_rows rows, f_i = f_i^SS(rho, 0); empty above */
+    for (int32_t j = 0; j < p->init_rows; ++j)
+        for (int32_t x = 0; x < p->L; ++x) {
+            double U = orc_init_uniform(p->seed, p->replica, x, j);
+            double rho = p->rho_init * (1.0 + p->init_amp * (2.0 * U - 1.0));
+            double fss[9];
+            orc_fss(rho, 0.0, 0.0, fss);
+            for (int i = 0; i < 9; ++i) s->f[idx(p, i, j, x)] = fss[i];
+        }
+    s->t = 0;
+    s->y_wall = 0;
+    /* initial front: one above the highest site whose density reaches rho_c */
+    for (int32_t x = 0; x < p->L; ++x) {
+        int32_t hx = 0;
+        for (int32_t j = 0; j < p->H; ++j) {
+            double v[9];
+            for (int i = 0; i < 9; ++i) v[i] = s->f[idx(p, i, j, x)];
+            if (sum9(v) >= p->rho_c) hx = j + 1;
+        }
+        s->h[x] = hx;
+    }
+    s->h_hi = 0;
+    s->mass = window_mass(s);
+    width_of(s, &s->hbar, &s->W);
+    check_front(s);
+    return s;
+}
+
+void orc_destroy(orc_state *s)
+{
+    if (!s) return;
+    free(s->f);
+    free(s->fn);
+    free(s->h);
+    free(s);
+}
+
+/* Rear wall of the active portion (Appendix A, last paragraph): after a step,
+ * the wall moves up to at least max(gap, factor * w) below the mean front;
+ * rows it passes leave the simulation and their mass is booked as retired. */
+static void advance_wall(orc_state *s)
+{
+    const orc_params *p = &s->p;
+    double gap = s->W * p->wall_w_factor;
+    if (gap < (double)p->wall_min_gap) gap = (double)p->wall_min_gap;
+    int64_t target = (int64_t)floor(s->hbar - gap);
+    if (target <= s->y_wall) return;
+    int64_t k = target - s->y_wall;
+    if (k >= p->H) k = p->H - 1;
+    double gone = 0.0;
+    for (int32_t j = 0; j < (int32_t)k; ++j)
+        for (int32_t x = 0; x < p->L; ++x) {
+            double v[9];
+            for (int i = 0; i < 9; ++i) v[i] = s->f[idx(p, i, j, x)];
+            gone += sum9(v);
+        }
+    for (int i = 0; i < 9; ++i)
+        for (int32_t j = 0; j < p->H; ++j)
+            for (int32_t x = 0; x < p->L; ++x) {
+                int32_t src = j + (int32_t)k;
+                s->f[idx(p, i, j, x)] = (src < p->H) ? s->f[idx(p, i, src, x)] : 0.0;
+            }
+    s->y_wall += k;
+    s->retired += gone;
+    s->mass = s->mass - gone;
+    /* columns with no tissue left in the window sit at the wall */
+    for (int32_t x = 0; x < p->L; ++x)
+        if (s->h[x] < s->y_wall) s->h[x] = (int32_t)s->y_wall;
+}
+
+int orc_step(orc_state *s, int64_t nsteps)
+{
+    const orc_params *p = &s->p;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        if (s->status & ORC_ST_DOMAIN_FULL) return -4;
+        double src = 0.0, fix = 0.0;
+        int32_t *h_new = (int32_t *)malloc((size_t)p->L * sizeof(int32_t));
+        for (int32_t x = 0; x < p->L; ++x) h_new[x] = (int32_t)s->y_wall;
+        for (int32_t j = 0; j < p->H; ++j) {
+            int64_t y_abs = s->y_wall + j;
+            for (int32_t x = 0; x < p->L; ++x) {
+                double fstar[9], out[9], S, dfix;
+                orc_pull_site(p, s->f, x, j, fstar);
+                int tissue = orc_update_site(p, fstar, s->t, x, y_abs, s->h[x],
+                                             s->y_wall, -1, out, &S, &dfix);
+                for (int i = 0; i < 9; ++i) s->fn[idx(p, i, j, x)] = out[i];
+                src += S;
+                fix += dfix;
+                if (tissue && y_abs + 1 > h_new[x]) h_new[x] = (int32_t)(y_abs + 1);
+            }
+        }
+        double *tmp = s->f; s->f = s->fn; s->fn = tmp;
+        memcpy(s->h, h_new, (size_t)p->L * sizeof(int32_t));
+        free(h_new);
+        s->t += 1;
+        s->src_total += src;
+        s->fix_total += fix;
+        s->mass = window_mass(s);
+        width_of(s, &s->hbar, &s->W);
+        if (p->ybc == ORC_Y_WALL_FOLLOW) {
+            advance_wall(s);
+            width_of(s, &s->hbar, &s->W);
+        }
+        check_front(s);
+    }
+    return (s->status & ORC_ST_DOMAIN_FULL) ? -4 : 0;
+}
+
+void orc_diagnostics(const orc_state *s, orc_diag *d)
+{
+    d->mass = s->mass;
+    d->src_total = s->src_total;
+    d->fix_total = s->fix_total;
+    d->retired = s->retired;
+    d->hbar = s->hbar;
+    d->W = s->W;
+    d->step = s->t;
+    d->y_wall = s->y_wall;
+    d->h_hi = s->h_hi;
+    d->status = s->status;
+}
+
+void orc_front_heights(const orc_state *s, int32_t *h_out)
+{
+    memcpy(h_out, s->h, (size_t)s->p.L * sizeof(int32_t));
+}
+
+void orc_get_populations(const orc_state *s, double *f_out)
+{
+    memcpy(f_out, s->f, 9u * (size_t)s->p.L * (size_t)s->p.H * sizeof(double));
+}
+
+void orc_set_populations(orc_state *s, const double *f_in)
+{
+    memcpy(s->f, f_in, 9u * (size_t)s->p.L * (size_t)s->p.H * sizeof(double));
+    s->mass = window_mass(s);
+}
+
+void orc_set_front_heights(orc_state *s, const int32_t *h_in)
+{
+    memcpy(s->h, h_in, (size_t)s->p.L * sizeof(int32_t));
+    width_of(s, &s->hbar, &s->W);
+}

@@ -1,0 +1,118 @@
+/*
+ * lbm_oracle.h -- plain FP64 CPU oracle for the growing-tissue D2Q9 lattice
+ * Boltzmann method (Killeen, Partridge, Bertrand, Lee, "Modeling growing
+ * confluent tissues using a lattice Boltzmann method", arXiv 2303.02210).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code is the slow, obviously correct
+ * reference the GPU library is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never calls it.  It shares no code, header, table or helper
+ * with the HIP library: every constant below is restated here from the paper
+ * (and from the textbook D2Q9 lattice the paper cites for its equilibrium).
+ *
+ * Everything is double precision and evaluated in one fixed order (the order
+ * each formula is written in), with no fused multiply-add.
+ */
+#ifndef LBM_ORACLE_H
+#define LBM_ORACLE_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* growth law (Sec. II, mass injection between streaming and redistribution) */
+enum { ORC_GROWTH_NONE = 0, ORC_GROWTH_BULK = 1 };
+/* proliferating region: everywhere, a band of width ell below the front, or a
+ * band of width d above the rear wall (Appendix B) */
+enum { ORC_REGION_ALL = 0, ORC_REGION_FRONT_BAND = 1, ORC_REGION_REAR_BAND = 2 };
+/* boundary along the growth axis: fixed bounce-back rear wall, rear wall that
+ * follows the front (Appendix A, last paragraph), or periodic (test mode) */
+enum { ORC_Y_WALL_FIXED = 0, ORC_Y_WALL_FOLLOW = 1, ORC_Y_PERIODIC = 2 };
+/* status bits */
+enum { ORC_ST_DOMAIN_FULL = 1u, ORC_ST_NONFINITE = 2u };
+
+typedef struct {
+    int32_t  L, H;           /* columns (periodic x), rows (growth axis y)   */
+    double   tau;            /* relaxation time, Eq. 2                        */
+    double   mu;             /* friction, u* = (1 - mu) u, below Eq. 3        */
+    double   rho_c;          /* threshold density, Appendix A step 5          */
+    double   rho_init;       /* initial mean density, Appendix A              */
+    double   init_amp;       /* rho ~ U[(1-a), (1+a)] rho_init (paper: 0.1)   */
+    int32_t  init_rows;      /* tissue initially fills rows [0, init_rows)    */
+    int32_t  growth;         /* ORC_GROWTH_*                                  */
+    double   growth_rate;    /* g, mass added per unit tissue mass per step   */
+    int32_t  region;         /* ORC_REGION_*                                  */
+    int32_t  region_width;   /* ell (front band) or d (rear band)             */
+    double   sigma;          /* noise amplitude, Eq. 4                        */
+    int32_t  ybc;            /* ORC_Y_*                                       */
+    int32_t  wall_min_gap;   /* rear wall kept >= max(gap, factor*w) behind   */
+    double   wall_w_factor;  /*   the mean front height (Appendix A)          */
+    uint32_t seed;           /* Philox key word 0                             */
+    uint32_t replica;        /* Philox key word 1                             */
+} orc_params;
+
+typedef struct {
+    double   mass;           /* total mass of the live window after the step */
+    double   src_total;      /* cumulative injected mass                      */
+    double   fix_total;      /* cumulative mass change of the negative fix    */
+    double   retired;        /* cumulative mass in rows the rear wall left    */
+    double   hbar, W;        /* mean and standard deviation of h(x)           */
+    int64_t  step;           /* steps taken                                   */
+    int64_t  y_wall;         /* absolute row of the first live row            */
+    int64_t  h_hi;           /* largest front height seen so far              */
+    uint32_t status;         /* ORC_ST_* bits                                 */
+} orc_diag;
+
+typedef struct orc_state orc_state;
+
+/* Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* The nine noise draws of one site: 24-bit integers k_0..k_8, and the
+ * uniforms U_i = (k_i + 1/2) 2^-24 on (0, 1). */
+void orc_noise_bits(uint32_t seed, uint32_t replica, int64_t t, int32_t x,
+                    int64_t y_abs, uint32_t k_out[9]);
+void orc_noise_uniforms(uint32_t seed, uint32_t replica, int64_t t, int32_t x,
+                        int64_t y_abs, double u_out[9]);
+/* Uniform of the initial-density draw at (x, y). */
+double orc_init_uniform(uint32_t seed, uint32_t replica, int32_t x, int64_t y_abs);
+
+/* Lattice constants as used by the oracle (for the closed-form pins). */
+void orc_lattice(int32_t cx[9], int32_t cy[9], int32_t opp[9], double w[9]);
+
+/* Eq. 3 with D2Q9 coefficients: steady-state populations for rho and the
+ * (already friction-damped) velocity u*. */
+void orc_fss(double rho, double ux_star, double uy_star, double out[9]);
+
+/* Stream (Appendix A step 1) for one site: f*_i(x, j) pulled from the window
+ * f[9][H][L] (j = row inside the window). */
+void orc_pull_site(const orc_params *p, const double *f, int32_t x, int32_t j,
+                   double fstar[9]);
+
+/* Steps 2-7 of Appendix A at one site, given its streamed populations.
+ * force: -1 classify by density, 0 force the void branch, 1 force tissue.
+ * Returns 1 if the site was classified tissue.  S_out: injected mass,
+ * dfix_out: mass change of the negative-value fix. */
+int orc_update_site(const orc_params *p, const double fstar[9], int64_t t,
+                    int32_t x, int64_t y_abs, int32_t h_prev_x, int64_t y_wall,
+                    int force, double out[9], double *S_out, double *dfix_out);
+
+size_t     orc_state_bytes(const orc_params *p);
+orc_state *orc_create(const orc_params *p);        /* NULL if p invalid */
+int        orc_step(orc_state *s, int64_t nsteps); /* 0, or -4 domain full */
+void       orc_destroy(orc_state *s);
+void       orc_diagnostics(const orc_state *s, orc_diag *out);
+void       orc_front_heights(const orc_state *s, int32_t *h_out);
+/* populations of the live window, [9][H][L], window row j = y_wall + j */
+void       orc_get_populations(const orc_state *s, double *f_out);
+void       orc_set_populations(orc_state *s, const double *f_in);
+/* replace h (used as h_prev by the front band) */
+void       orc_set_front_heights(orc_state *s, const int32_t *h_in);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
