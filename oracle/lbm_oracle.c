@@ -310,19 +310,24 @@ int orc_update_site(const orc_params *p, const double fstar_in[9], int64_t t,
 /* ----------------------------------------------------------------------- */
 /* Diagnostics: h(x), its mean and the width w(t)                            */
 /* ----------------------------------------------------------------------- */
+/* w(t) of Sec. III: the population standard deviation of h over the L
+ * columns.  Heights are integers, so the sums are taken exactly in integers
+ * (relative to the wall row, which leaves the variance unchanged):
+ *   hbar = y_wall + S1 / L,   w = sqrt(L S2 - S1^2) / L,
+ * with S1 = sum d, S2 = sum d^2, d = h - y_wall.  This makes both results
+ * independent of summation order. */
 static void width_of(const orc_state *s, double *hbar, double *W)
 {
     const int32_t L = s->p.L;
-    double sum = 0.0;
-    for (int32_t x = 0; x < L; ++x) sum += (double)s->h[x];
-    double mean = sum / (double)L;
-    double ss = 0.0;
+    int64_t S1 = 0, S2 = 0;
     for (int32_t x = 0; x < L; ++x) {
-        double d = (double)s->h[x] - mean;
-        ss += d * d;
+        int64_t d = (int64_t)s->h[x] - s->y_wall;
+        S1 += d;
+        S2 += d * d;
     }
-    *hbar = mean;
-    *W = sqrt(ss / (double)L);
+    int64_t num = (int64_t)L * S2 - S1 * S1;
+    *hbar = (double)s->y_wall + (double)S1 / (double)L;
+    *W = sqrt((double)num) / (double)L;
 }
 
 static double window_mass(const orc_state *s)
@@ -512,4 +517,9 @@ void orc_set_front_heights(orc_state *s, const int32_t *h_in)
 {
     memcpy(s->h, h_in, (size_t)s->p.L * sizeof(int32_t));
     width_of(s, &s->hbar, &s->W);
+}
+
+void orc_set_step(orc_state *s, int64_t t)
+{
+    s->t = t;
 }

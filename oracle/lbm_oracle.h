@@ -111,6 +111,8 @@ void       orc_get_populations(const orc_state *s, double *f_out);
 void       orc_set_populations(orc_state *s, const double *f_in);
 /* replace h (used as h_prev by the front band) */
 void       orc_set_front_heights(orc_state *s, const int32_t *h_in);
+/* set the step counter (the noise of the next step is drawn at counter t) */
+void       orc_set_step(orc_state *s, int64_t t);
 
 #ifdef __cplusplus
 }

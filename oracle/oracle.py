@@ -101,6 +101,7 @@ def lib():
         L.orc_get_populations.argtypes = [ctypes.c_void_p, dp]
         L.orc_set_populations.argtypes = [ctypes.c_void_p, dp]
         L.orc_set_front_heights.argtypes = [ctypes.c_void_p, i32p]
+        L.orc_set_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
     return _lib
 
 
@@ -247,3 +248,6 @@ class Oracle:
         a = np.ascontiguousarray(f, dtype=np.float64)
         assert a.shape == (9, self.H, self.L)
         lib().orc_set_populations(self._h, _ptr(a, ctypes.c_double))
+
+    def set_step(self, t: int) -> None:
+        lib().orc_set_step(self._h, int(t))

@@ -549,3 +549,15 @@ def test_negative_fix_closed_form():
         assert np.all(out >= 0)
         assert np.isclose(dfix, out.sum() - eq.sum(), rtol=1e-10, atol=1e-15)
     assert n_rest_fix >= 2
+
+
+def test_width_is_population_std_of_heights():
+    # w(t) of Sec. III with the 1/L normalisation: numpy's population std
+    c = dict(si.SMALL_FP64, sigma=2e-2, tau=0.8)
+    o = orc.Oracle(c)
+    for _ in range(5):
+        o.step(40)
+        h = o.front_heights().astype(float)
+        d = o.diagnostics()
+        assert abs(d["hbar"] - h.mean()) <= 1e-12 * h.mean()
+        assert abs(d["W"] - h.std()) <= 1e-12 * max(h.std(), 1.0)
