@@ -1,0 +1,240 @@
+/*
+ * lbmgrow.h -- C ABI of the MI355X (gfx950) growing-tissue lattice Boltzmann
+ * library.
+ *
+ * The method is the lattice Boltzmann model of a growing tissue of Killeen,
+ * Partridge, Bertrand and Lee (arXiv 2303.02210), run on the square D2Q9
+ * lattice: per step and per site, stream, take moments (Eq. 1), add the
+ * proliferation mass, relax towards the friction-damped steady state (Eqs. 2
+ * and 3) or -- below the threshold density -- reverse every direction (the
+ * two-step bounce-back front of Sec. II), add zero-sum noise (Eq. 4) and
+ * remove negative populations (Appendix A, steps 1-7).  Per column the
+ * library keeps the interface height h(x, t) used for the width w(t) of
+ * Sec. III, and optionally moves the rear wall with the front (Appendix A).
+ *
+ * Conventions shared by every call:
+ *   - Lattice: x = column, periodic, 0 <= x < L; y = row along the growth
+ *     direction.  Directions: 0 rest, 1 E(+x), 2 N(+y), 3 W, 4 S, 5 NE, 6 NW,
+ *     7 SW, 8 SE; reverse pairs 1-3, 2-4, 5-7, 6-8.
+ *   - Populations on the host are float64 arrays [9][H][L] (direction,
+ *     window row, column); window row j is absolute row y_wall + j.
+ *   - Device memory is never allocated by the library: the caller passes one
+ *     device workspace of at least lbm_workspace_bytes() bytes that must stay
+ *     valid until lbm_destroy.  Every device operation is enqueued on the
+ *     caller's HIP stream.
+ *   - Every call returns LBM_OK (0) or a negative lbm_status.  Calls marked
+ *     "synchronizes" wait for the stream; others only enqueue work.  Faults
+ *     found on the device (front reached the top row, non-finite mass) are
+ *     latched in a device status word and returned by the next synchronizing
+ *     call; after any error a handle only accepts lbm_destroy,
+ *     lbm_diagnostics and lbm_last_error (everything else: LBM_E_STATE).
+ *   - Handles are not thread-safe; distinct handles are independent.
+ */
+#ifndef LBMGROW_H
+#define LBMGROW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1u
+
+typedef struct lbm_handle lbm_handle;
+typedef struct lbm_batch lbm_batch;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_E_INVALID = -1,      /* bad argument or parameter                     */
+    LBM_E_NOMEM = -2,        /* workspace or host buffer too small            */
+    LBM_E_DEVICE = -3,       /* a HIP runtime call failed                     */
+    LBM_E_DOMAIN_FULL = -4,  /* the front reached the last row of the window  */
+    LBM_E_NONFINITE = -5,    /* total mass became NaN or infinite             */
+    LBM_E_UNSUPPORTED = -6,  /* valid request this build does not implement   */
+    LBM_E_STATE = -7         /* handle is in an error state                   */
+} lbm_status;
+
+/* Storage / arithmetic of the populations. */
+typedef enum {
+    LBM_FP64 = 0,            /* float64 storage and arithmetic                */
+    LBM_FP32 = 1,            /* float32 storage and arithmetic                */
+    LBM_FP16_OFFSET = 2,     /* float16 of f_i - W_i, float32 arithmetic      */
+    LBM_BF16_OFFSET = 3      /* bfloat16 of f_i - W_i, float32 arithmetic     */
+} lbm_precision;
+
+/* Growth law (Sec. II, mass injection between streaming and redistribution). */
+typedef enum {
+    LBM_GROWTH_NONE = 0,
+    LBM_GROWTH_BULK = 1      /* every tissue site of the region gains g rho*  */
+} lbm_growth;
+
+/* Proliferating region. */
+typedef enum {
+    LBM_REGION_ALL = 0,        /* all tissue sites                              */
+    LBM_REGION_FRONT_BAND = 1, /* tissue with y >= h_prev(x) - region_width     */
+    LBM_REGION_REAR_BAND = 2   /* tissue with y <  y_wall + region_width (App. B) */
+} lbm_region;
+
+/* Boundary along the growth axis. */
+typedef enum {
+    LBM_Y_WALL_FIXED = 0,    /* bounce-back wall below row 0, empty above top */
+    LBM_Y_WALL_FOLLOW = 1,   /* wall follows the front (Appendix A)           */
+    LBM_Y_PERIODIC = 2       /* periodic rows (test mode)                     */
+} lbm_ybc;
+
+/* lbm_params.flags */
+#define LBM_FLAG_WINDOW 1u   /* sweep only rows that can hold mass: rows at or
+                                below the highest front seen plus one (the rest
+                                are exactly zero); results are unchanged      */
+
+/*
+ * Model and run parameters.  Set abi_version = LBM_ABI_VERSION and
+ * struct_size = sizeof(lbm_params).
+ *   L, H          columns (periodic) and rows of the live window; L >= 2,
+ *                 H >= 4, L * H * 9 populations must fit the workspace.
+ *   precision     lbm_precision.
+ *   tau           relaxation time of Eq. 2, tau > 1/2.
+ *   mu            friction: the steady state uses u* = (1 - mu) u (below
+ *                 Eq. 3); 0 <= mu <= 1.
+ *   rho_c         threshold density of the bounce-back front (Appendix A,
+ *                 step 5); rho_c > 0.
+ *   rho_init, init_amp, init_rows
+ *                 initial state (Appendix A): rows [0, init_rows) at rest with
+ *                 rho uniform on [(1 - a), (1 + a)] rho_init, a = init_amp in
+ *                 [0, 1); rows above empty.
+ *   growth, growth_rate
+ *                 lbm_growth and the rate g >= 0 (mass per unit tissue mass per
+ *                 step; Sec. II).
+ *   region, region_width
+ *                 lbm_region and its width (>= 0).
+ *   sigma         noise amplitude of Eq. 4, sigma >= 0.
+ *   ybc           lbm_ybc.
+ *   wall_min_gap, wall_w_factor
+ *                 follow mode: after each step the wall moves up to
+ *                 floor(hbar - max(wall_min_gap, wall_w_factor * w)) (Appendix
+ *                 A uses 50 and 10).
+ *   rho_ref       offset base of the 16-bit storages: populations are stored
+ *                 as f_i - W_i with W_i = w_i rho_ref rounded to the storage
+ *                 type, so that an empty site decodes to exactly 0.
+ *   seed, replica Philox4x32-10 key words of all random draws.
+ *   flags         LBM_FLAG_* bits.
+ */
+typedef struct {
+    uint32_t abi_version;
+    uint32_t struct_size;
+    int32_t  L, H;
+    int32_t  precision;
+    int32_t  growth;
+    double   tau, mu, rho_c;
+    double   rho_init, init_amp;
+    int32_t  init_rows;
+    int32_t  region;
+    double   growth_rate;
+    int32_t  region_width;
+    int32_t  ybc;
+    double   sigma;
+    int32_t  wall_min_gap;
+    int32_t  flags;
+    double   wall_w_factor;
+    double   rho_ref;
+    uint32_t seed, replica;
+} lbm_params;
+
+/* Diagnostics after the last enqueued step (all reductions in float64). */
+typedef struct {
+    double   mass;        /* total mass in the live window                    */
+    double   src_total;   /* mass injected by growth since creation           */
+    double   fix_total;   /* mass added by the negative-population fix        */
+    double   retired;     /* mass in rows the rear wall has left behind       */
+    double   hbar, W;     /* mean and standard deviation of h(x) (Sec. III)   */
+    int64_t  step;        /* steps taken                                      */
+    int64_t  y_wall;      /* absolute row of window row 0                     */
+    int64_t  h_hi;        /* highest front height seen since creation         */
+    uint32_t status;      /* LBM_ST_* bits latched on the device              */
+    uint32_t reserved;
+} lbm_diag;
+
+#define LBM_ST_DOMAIN_FULL 1u
+#define LBM_ST_NONFINITE   2u
+
+/* Library version string, e.g. "lbmgrow 1.0 gfx950". */
+const char *lbm_version(void);
+
+/* Device workspace size for p; 0 if p is invalid. */
+size_t lbm_workspace_bytes(const lbm_params *p);
+
+/*
+ * Create a simulation in dev_ws (device pointer, ws_bytes >= the size above,
+ * 256-byte aligned) on hip_stream (a hipStream_t; NULL = the null stream).
+ * Enqueues the initial state of Appendix A.  The handle is host memory owned
+ * by the library until lbm_destroy.  Errors: LBM_E_INVALID (parameters,
+ * null/unaligned pointers), LBM_E_NOMEM (ws_bytes too small), LBM_E_DEVICE.
+ */
+int lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *hip_stream,
+               lbm_handle **out);
+
+/* Enqueue nsteps >= 0 steps (Appendix A steps 1-7 on every site, then the
+ * front heights and, in follow mode, the wall).  Does not synchronize. */
+int lbm_step(lbm_handle *h, int64_t nsteps);
+
+/* Copy h(x) of the current state (L int32, absolute rows) to host_h and the
+ * step count to *step_out (may be NULL).  Synchronizes; returns a latched
+ * device fault if there is one. */
+int lbm_front_heights(lbm_handle *h, int32_t *host_h, int64_t *step_out);
+
+/* Enqueue a copy of h(x) of the current state into dst (L int32; device
+ * memory or pinned host memory).  Does not synchronize: the caller
+ * synchronizes the stream before reading dst. */
+int lbm_front_heights_async(lbm_handle *h, int32_t *dst);
+
+/* Fill *out.  Synchronizes. */
+int lbm_diagnostics(lbm_handle *h, lbm_diag *out);
+
+/* Populations of the live window decoded to float64 [9][H][L].
+ * Synchronizes. */
+int lbm_get_populations(lbm_handle *h, double *host_f);
+
+/* Replace the populations (encoded to the storage type with round to nearest
+ * even).  Front heights are left unchanged.  Synchronizes. */
+int lbm_set_populations(lbm_handle *h, const double *host_f);
+
+/* Replace h(x) (L int32, absolute rows), e.g. as h_prev of the front band.
+ * Synchronizes. */
+int lbm_set_front_heights(lbm_handle *h, const int32_t *host_h);
+
+/* Checkpoint: size of the host blob, save, and restore into a handle created
+ * with the same parameters.  A restored run continues bit for bit like the
+ * uninterrupted one (all draws are keyed by step and site).  Synchronize. */
+size_t lbm_state_bytes(const lbm_handle *h);
+int lbm_get_state(lbm_handle *h, void *host_blob, size_t bytes);
+int lbm_set_state(lbm_handle *h, const void *host_blob, size_t bytes);
+
+/* Human-readable description of the last error on h (never NULL). */
+const char *lbm_last_error(const lbm_handle *h);
+
+/* Release the handle.  Never frees the workspace.  Does not synchronize. */
+int lbm_destroy(lbm_handle *h);
+
+/*
+ * Batches: many handles of any size and precision advanced together, one
+ * kernel launch per precision per step over a flattened table of tiles, so
+ * that small lattices share the GPU.  Every handle keeps its own workspace,
+ * state and status; results are bit for bit those of lbm_step on the
+ * handle alone.  All handles must use the batch's stream.
+ *   lbm_batch_create     empty batch on hip_stream.
+ *   lbm_batch_add/remove membership changes (take effect at the next step).
+ *   lbm_batch_step       nsteps steps of every member.  Does not synchronize.
+ *   lbm_batch_destroy    releases the batch, not its handles.
+ */
+int lbm_batch_create(void *hip_stream, lbm_batch **out);
+int lbm_batch_add(lbm_batch *b, lbm_handle *h);
+int lbm_batch_remove(lbm_batch *b, lbm_handle *h);
+int lbm_batch_step(lbm_batch *b, int64_t nsteps);
+int lbm_batch_destroy(lbm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBMGROW_H */

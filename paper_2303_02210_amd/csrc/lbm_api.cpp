@@ -1,0 +1,789 @@
+// lbm_api.cpp -- C ABI of the gfx950 growing-tissue lattice Boltzmann library
+// (declared in include/lbmgrow.h): parameter checks, workspace layout, launch
+// configuration, host<->device transfers and error latching.
+#include "lbmgrow.h"
+#include "lbm_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace lbm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// D2Q9 weights (rest, axes, diagonals).
+const double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                      1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+// ---- host float16 / bfloat16 conversions, round to nearest even --------------
+uint16_t f32_to_f16(float f)
+{
+    uint32_t x;
+    std::memcpy(&x, &f, 4);
+    const uint32_t sign = (x >> 16) & 0x8000u;
+    const uint32_t ax = x & 0x7FFFFFFFu;
+    if (ax >= 0x7F800000u) return (uint16_t)(sign | (ax > 0x7F800000u ? 0x7E00u : 0x7C00u));
+    if (ax >= 0x477FF000u) return (uint16_t)(sign | 0x7C00u);      // rounds to infinity
+    if (ax < 0x38800000u) {                                         // below 2^-14: subnormal
+        float af;
+        std::memcpy(&af, &ax, 4);
+        const long r = std::lrintf(af * 16777216.0f);                 // multiples of 2^-24
+        return (uint16_t)(sign | (uint32_t)r);
+    }
+    const uint32_t e = (ax >> 23) - 127u + 15u;
+    const uint32_t m = ax & 0x7FFFFFu;
+    uint32_t h = (e << 10) | (m >> 13);
+    const uint32_t rem = m & 0x1FFFu;
+    if (rem > 0x1000u || (rem == 0x1000u && (h & 1u))) h += 1u;
+    return (uint16_t)(sign | h);
+}
+
+float f16_to_f32(uint16_t h)
+{
+    const uint32_t sign = (uint32_t)(h & 0x8000u) << 16;
+    const uint32_t e = (h >> 10) & 0x1Fu;
+    const uint32_t m = h & 0x3FFu;
+    uint32_t x;
+    if (e == 0) {
+        const float v = (float)m * (1.0f / 16777216.0f);
+        std::memcpy(&x, &v, 4);
+        x |= sign;
+    } else if (e == 31) {
+        x = sign | 0x7F800000u | (m << 13);
+    } else {
+        x = sign | ((e - 15u + 127u) << 23) | (m << 13);
+    }
+    float f;
+    std::memcpy(&f, &x, 4);
+    return f;
+}
+
+uint16_t f32_to_bf16(float f)
+{
+    uint32_t x;
+    std::memcpy(&x, &f, 4);
+    if ((x & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((x >> 16) | 0x40u);
+    x += 0x7FFFu + ((x >> 16) & 1u);
+    return (uint16_t)(x >> 16);
+}
+
+float bf16_to_f32(uint16_t b)
+{
+    const uint32_t x = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &x, 4);
+    return f;
+}
+
+size_t elem_bytes(int prec)
+{
+    switch (prec) {
+    case LBM_FP64: return 8;
+    case LBM_FP32: return 4;
+    default: return 2;
+    }
+}
+
+// Storage offset W_i = w_i rho_ref rounded to the storage type (0 when the
+// storage holds f_i itself).
+double offset_base(int prec, int i, double rho_ref)
+{
+    const float v = (float)(kW[i] * rho_ref);
+    if (prec == LBM_FP16_OFFSET) return (double)f16_to_f32(f32_to_f16(v));
+    if (prec == LBM_BF16_OFFSET) return (double)bf16_to_f32(f32_to_bf16(v));
+    return 0.0;
+}
+
+struct Layout {
+    size_t esize = 0;
+    int64_t lp = 0;          // padded width (whole tiles)
+    Tiles tl{};
+    size_t nelem = 0;        // population elements per buffer
+    size_t fbytes = 0;
+    size_t off_f[2] = {0, 0};
+    size_t off_h[3] = {0, 0, 0};
+    size_t off_colmax = 0, off_partials = 0, off_state = 0, off_diag = 0;
+    size_t total = 0;
+    int nt = 256, ty = 16, gx = 1, gy = 1, nblocks = 1, rb = 2;
+    bool vec = false;   // vector kernel: vb bytes (cpt columns) per thread
+    int cpt = 1, vb = 16, wpe = 4;
+};
+
+bool params_ok(const lbm_params *p, std::string *why)
+{
+    auto bad = [&](const char *m) {
+        if (why) *why = m;
+        return false;
+    };
+    if (!p) return bad("null params");
+    if (p->abi_version != LBM_ABI_VERSION) return bad("abi_version mismatch");
+    if (p->struct_size != sizeof(lbm_params)) return bad("struct_size mismatch");
+    if (p->L < 2 || p->H < 4) return bad("L must be >= 2 and H >= 4");
+    if ((int64_t)p->L * (int64_t)p->H * 9 > (int64_t)1 << 31) return bad("lattice too large");
+    if (p->precision < LBM_FP64 || p->precision > LBM_BF16_OFFSET) return bad("bad precision");
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return bad("tau must be > 1/2");
+    if (!(p->mu >= 0.0 && p->mu <= 1.0)) return bad("mu must be in [0, 1]");
+    if (!(p->rho_c > 0.0) || !std::isfinite(p->rho_c)) return bad("rho_c must be > 0");
+    if (!(p->rho_init >= 0.0) || !std::isfinite(p->rho_init)) return bad("rho_init must be >= 0");
+    if (!(p->init_amp >= 0.0 && p->init_amp < 1.0)) return bad("init_amp must be in [0, 1)");
+    if (p->init_rows < 0 || p->init_rows > p->H) return bad("init_rows out of range");
+    if (p->growth != LBM_GROWTH_NONE && p->growth != LBM_GROWTH_BULK) return bad("bad growth");
+    if (!(p->growth_rate >= 0.0) || !std::isfinite(p->growth_rate)) return bad("growth_rate must be >= 0");
+    if (p->region < LBM_REGION_ALL || p->region > LBM_REGION_REAR_BAND) return bad("bad region");
+    if (p->region_width < 0) return bad("region_width must be >= 0");
+    if (!(p->sigma >= 0.0) || !std::isfinite(p->sigma)) return bad("sigma must be >= 0");
+    if (p->ybc < LBM_Y_WALL_FIXED || p->ybc > LBM_Y_PERIODIC) return bad("bad ybc");
+    if (p->ybc == LBM_Y_WALL_FOLLOW && (p->wall_min_gap < 0 || !(p->wall_w_factor >= 0.0)))
+        return bad("bad wall follow parameters");
+    if ((p->flags & ~LBM_FLAG_WINDOW) != 0) return bad("unknown flags");
+    if ((p->flags & LBM_FLAG_WINDOW) && p->ybc == LBM_Y_PERIODIC)
+        return bad("the sweep window needs a rear wall");
+    if ((p->precision == LBM_FP16_OFFSET || p->precision == LBM_BF16_OFFSET) &&
+        (!(p->rho_ref >= 0.0) || !std::isfinite(p->rho_ref)))
+        return bad("rho_ref must be >= 0");
+    return true;
+}
+
+int pick_ty(int gx, int H, int pref)
+{
+    if (const char *e = std::getenv("LBMGROW_TY")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 256) return v;
+    }
+    // rows per thread: the preferred count, fewer if that would leave the
+    // device with under 2048 blocks (8 per CU)
+    int t = pref;
+    while (t > 1 && (int64_t)gx * ((H + t - 1) / t) < 2048) t /= 2;
+    return t;
+}
+
+Layout make_layout(const lbm_params *p)
+{
+    Layout l;
+    l.esize = elem_bytes(p->precision);
+    // tile width: the largest of 256, 128, 64 columns that divides the width
+    // rounded up to 64 (no padding beyond that)
+    const int64_t l64 = (int64_t)align_up((size_t)p->L, 64);
+    int tws = (l64 % 256 == 0) ? 8 : ((l64 % 128 == 0) ? 7 : 6);
+    if (const char *e = std::getenv("LBMGROW_TW")) {
+        const int v = std::atoi(e);
+        if (v == 64 || v == 128 || v == 256) tws = v == 64 ? 6 : (v == 128 ? 7 : 8);
+    }
+    l.lp = (int64_t)align_up((size_t)p->L, (size_t)1 << tws);
+    l.tl.tws = tws;
+    l.tl.rs = 9 * l.lp;
+    l.nelem = (size_t)l.tl.rs * (size_t)p->H;
+    l.fbytes = align_up(l.nelem * l.esize, kAlign);
+    // vector kernel when the columns split evenly into lanes; bytes per lane
+    // and rows per thread as measured best on MI355X for a 4096 x 4096
+    // lattice: float64 16 B / 1 row, float32 4 B / 2 rows, 16-bit 8 B / 4 rows
+    l.vb = l.esize == 8 ? 16 : (l.esize == 4 ? 4 : 8);
+    const int ty_pref = l.esize == 8 ? 1 : (l.esize == 4 ? 2 : 4);
+    if (const char *e = std::getenv("LBMGROW_VB")) {
+        const int v = std::atoi(e);
+        l.vb = (v == 4 || v == 8) ? v : 16;
+    }
+    if ((size_t)l.vb < l.esize) l.vb = (int)l.esize;
+    if (const char *e = std::getenv("LBMGROW_WPE")) l.wpe = std::atoi(e);
+    const int V = (int)(l.vb / l.esize);
+    l.vec = (p->L % V) == 0;
+    if (const char *e = std::getenv("LBMGROW_KERNEL"))
+        if (std::strcmp(e, "scalar") == 0) l.vec = false;
+    l.cpt = l.vec ? V : 1;
+    const int lanes = (p->L + l.cpt - 1) / l.cpt;
+    l.nt = lanes <= 64 ? 64 : (lanes <= 128 ? 128 : 256);
+    l.gx = (lanes + l.nt - 1) / l.nt;
+    l.ty = pick_ty(l.gx, p->H, l.vec ? ty_pref : 2);
+    l.gy = (p->H + l.ty - 1) / l.ty;
+    l.rb = 2;
+    if (const char *e = std::getenv("LBMGROW_RB")) l.rb = std::atoi(e);
+    l.nblocks = l.gx * l.gy;
+    size_t o = 0;
+    l.off_f[0] = o; o += l.fbytes;
+    l.off_f[1] = o; o += l.fbytes;
+    const size_t hb = align_up((size_t)p->L * 4, kAlign);
+    for (int k = 0; k < 3; ++k) { l.off_h[k] = o; o += hb; }
+    l.off_colmax = o; o += hb;
+    l.off_partials = o; o += align_up((size_t)l.nblocks * 4 * 8, kAlign);
+    l.off_state = o; o += align_up(sizeof(DevState), kAlign);
+    l.off_diag = o; o += align_up(sizeof(DiagOut), kAlign);
+    l.total = o;
+    return l;
+}
+
+}  // namespace
+
+struct lbm_handle {
+    lbm_params p{};
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Layout lay;
+    int cur = 0;
+    int64_t t = 0;
+    int mode = kModeFixed;
+    bool device_driven = false;
+    int err = LBM_OK;
+    std::string msg = "no error";
+    double Wd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+
+    template <class T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+    void *fbuf(int k) const { return ws + lay.off_f[k]; }
+    int32_t *hslot(int64_t step) const { return at<int32_t>(lay.off_h[step % 3]); }
+    int32_t *colmax() const { return at<int32_t>(lay.off_colmax); }
+    double *partials() const { return at<double>(lay.off_partials); }
+    DevState *st() const { return at<DevState>(lay.off_state); }
+    DiagOut *diag() const { return at<DiagOut>(lay.off_diag); }
+
+    int fail(int code, const std::string &m)
+    {
+        if (err == LBM_OK) {
+            err = code;
+            msg = m;
+        }
+        return code;
+    }
+    int hip(hipError_t e, const char *what)
+    {
+        if (e == hipSuccess) return LBM_OK;
+        return fail(LBM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+};
+
+namespace {
+
+template <class S>
+int do_init(lbm_handle *h)
+{
+    using R = typename Real<S>::type;
+    const lbm_params &p = h->p;
+    const Layout &l = h->lay;
+    hipStream_t s = h->stream;
+    int rc;
+    // zero both population buffers' bookkeeping and every small array
+    if ((rc = h->hip(launch_fill_i32(h->hslot(0), (int64_t)(l.off_partials - l.off_h[0]) / 4, 0, s),
+                     "fill")))
+        return rc;
+    if ((rc = h->hip(launch_fill_f64(h->partials(), (int64_t)l.nblocks * 4, 0.0, s), "fill")))
+        return rc;
+    if ((rc = h->hip(launch_state_set(h->st(), 0, p.H, p.H, 0, s), "state")))
+        return rc;
+    InitArgs<S> a{};
+    a.f = reinterpret_cast<S *>(h->fbuf(0));
+    a.h0 = h->hslot(0);
+    a.colmax = h->colmax();
+    a.partials = h->partials();
+    a.L = p.L;
+    a.H = p.H;
+    a.ty = l.ty;
+    a.tl = l.tl;
+    a.init_rows = p.init_rows;
+    a.cpt = l.cpt;
+    a.seed = p.seed;
+    a.replica = p.replica;
+    a.rho_init = p.rho_init;
+    a.init_amp = p.init_amp;
+    a.rho_c = p.rho_c;
+    for (int i = 0; i < 9; ++i) {
+        a.w[i] = kW[i];
+        a.Wd[i] = (R)h->Wd[i];
+    }
+    if ((rc = h->hip(launch_init<S>(a, dim3(l.gx, l.gy), l.nt, s), "init kernel"))) return rc;
+    h->cur = 0;
+    h->t = 0;
+    // empty second buffer: rows never written read as empty through the
+    // device window bookkeeping, but clear it so snapshots are clean
+    return h->hip(hipMemsetAsync(h->fbuf(1), 0, l.fbytes, s), "clear");
+}
+
+template <class S>
+int do_step(lbm_handle *h, int64_t n)
+{
+    using R = typename Real<S>::type;
+    const lbm_params &p = h->p;
+    const Layout &l = h->lay;
+    StepArgs<S> a{};
+    a.partials = h->partials();
+    a.colmax = h->colmax();
+    a.st = h->st();
+    a.L = p.L;
+    a.H = p.H;
+    a.ty = l.ty;
+    a.tl = l.tl;
+    a.mode = h->mode;
+    a.growth = p.growth;
+    a.region = p.region;
+    a.region_width = p.region_width;
+    a.noise = p.sigma > 0.0;
+    a.seed = p.seed;
+    a.replica = p.replica;
+    a.omega = (R)(1.0 / p.tau);
+    a.kmu = (R)(1.0 - p.mu);
+    a.rho_c = (R)p.rho_c;
+    a.g = (R)p.growth_rate;
+    a.sigma = (R)p.sigma;
+    for (int i = 0; i < 9; ++i) {
+        a.w[i] = (R)kW[i];
+        a.Wd[i] = (R)h->Wd[i];
+    }
+    FinalizeArgs<S> fa{};
+    fa.st = h->st();
+    fa.colmax = h->colmax();
+    fa.L = p.L;
+    fa.H = p.H;
+    fa.tl = l.tl;
+    fa.follow = p.ybc == LBM_Y_WALL_FOLLOW;
+    fa.window = (p.flags & LBM_FLAG_WINDOW) != 0;
+    fa.min_gap = p.wall_min_gap;
+    fa.w_factor = p.wall_w_factor;
+    for (int i = 0; i < 9; ++i) fa.Wd[i] = (R)h->Wd[i];
+
+    const dim3 grid(l.gx, l.gy);
+    for (int64_t k = 0; k < n; ++k) {
+        a.fin = reinterpret_cast<const S *>(h->fbuf(h->cur));
+        a.fout = reinterpret_cast<S *>(h->fbuf(h->cur ^ 1));
+        a.h_prev = h->hslot(h->t);
+        a.h_next = h->hslot(h->t + 1);
+        a.h_clear = h->device_driven ? nullptr : h->hslot(h->t + 2);
+        a.t = (uint32_t)h->t;
+        int rc = h->hip(l.vec ? launch_step_vec<S>(a, grid, l.nt, l.vb, l.wpe, h->stream)
+                              : launch_step<S>(a, grid, l.nt, l.rb, h->stream),
+                        "step kernel");
+        if (rc) return rc;
+        if (h->device_driven) {
+            fa.f = a.fout;
+            fa.h_next = h->hslot(h->t + 1);
+            fa.h_clear = h->hslot(h->t + 2);
+            rc = h->hip(launch_finalize<S>(fa, h->stream), "finalize kernel");
+            if (rc) return rc;
+        }
+        h->cur ^= 1;
+        h->t += 1;
+    }
+    return LBM_OK;
+}
+
+template <class S>
+int do_mass(lbm_handle *h)
+{
+    using R = typename Real<S>::type;
+    MassArgs<S> a{};
+    a.f = reinterpret_cast<const S *>(h->fbuf(h->cur));
+    a.partials = h->partials();
+    a.st = h->st();
+    a.L = h->p.L;
+    a.H = h->p.H;
+    a.ty = h->lay.ty;
+    a.cpt = h->lay.cpt;
+    a.tl = h->lay.tl;
+    for (int i = 0; i < 9; ++i) a.Wd[i] = (R)h->Wd[i];
+    return h->hip(launch_mass<S>(a, dim3(h->lay.gx, h->lay.gy), h->lay.nt, h->stream),
+                  "mass kernel");
+}
+
+#define LBM_DISPATCH(prec, fn, ...)                                   \
+    ((prec) == LBM_FP64   ? fn<double>(__VA_ARGS__)                    \
+     : (prec) == LBM_FP32 ? fn<float>(__VA_ARGS__)                     \
+     : (prec) == LBM_FP16_OFFSET ? fn<__half>(__VA_ARGS__)             \
+                                 : fn<__hip_bfloat16>(__VA_ARGS__))
+
+int usable(lbm_handle *h)
+{
+    if (!h) return LBM_E_INVALID;
+    if (h->err != LBM_OK) return LBM_E_STATE;
+    return LBM_OK;
+}
+
+int sync_and_check(lbm_handle *h)
+{
+    uint32_t status = 0;
+    int rc = h->hip(hipMemcpyAsync(&status, &h->st()->status, sizeof(status),
+                                   hipMemcpyDeviceToHost, h->stream),
+                    "status copy");
+    if (rc) return rc;
+    if ((rc = h->hip(hipStreamSynchronize(h->stream), "synchronize"))) return rc;
+    if (status & kStDomainFull) return h->fail(LBM_E_DOMAIN_FULL, "front reached the top row of the window");
+    if (status & kStNonFinite) return h->fail(LBM_E_NONFINITE, "total mass is not finite");
+    return LBM_OK;
+}
+
+double decode_one(int prec, const char *base, size_t idx, double Wd)
+{
+    switch (prec) {
+    case LBM_FP64: {
+        double v;
+        std::memcpy(&v, base + idx * 8, 8);
+        return v;
+    }
+    case LBM_FP32: {
+        float v;
+        std::memcpy(&v, base + idx * 4, 4);
+        return (double)v;
+    }
+    case LBM_FP16_OFFSET: {
+        uint16_t v;
+        std::memcpy(&v, base + idx * 2, 2);
+        return (double)(f16_to_f32(v) + (float)Wd);
+    }
+    default: {
+        uint16_t v;
+        std::memcpy(&v, base + idx * 2, 2);
+        return (double)(bf16_to_f32(v) + (float)Wd);
+    }
+    }
+}
+
+void encode_one(int prec, char *base, size_t idx, double f, double Wd)
+{
+    switch (prec) {
+    case LBM_FP64:
+        std::memcpy(base + idx * 8, &f, 8);
+        break;
+    case LBM_FP32: {
+        const float v = (float)f;
+        std::memcpy(base + idx * 4, &v, 4);
+        break;
+    }
+    case LBM_FP16_OFFSET: {
+        const uint16_t v = f32_to_f16((float)f - (float)Wd);
+        std::memcpy(base + idx * 2, &v, 2);
+        break;
+    }
+    default: {
+        const uint16_t v = f32_to_bf16((float)f - (float)Wd);
+        std::memcpy(base + idx * 2, &v, 2);
+        break;
+    }
+    }
+}
+
+int read_state(lbm_handle *h, DevState *out)
+{
+    int rc = h->hip(hipMemcpyAsync(out, h->st(), sizeof(DevState), hipMemcpyDeviceToHost, h->stream),
+                    "state copy");
+    if (rc) return rc;
+    return h->hip(hipStreamSynchronize(h->stream), "synchronize");
+}
+
+// State blob: header, current populations, current h slot, column maxima,
+// block partials and the device state.
+struct BlobHeader {
+    uint64_t magic;
+    lbm_params p;
+    int64_t t;
+    uint64_t fbytes, hbytes, pbytes;
+};
+constexpr uint64_t kMagic = 0x31626C6D62676C6Cull;
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char *lbm_version(void) { return "lbmgrow 1.0 gfx950"; }
+
+size_t lbm_workspace_bytes(const lbm_params *p)
+{
+    if (!params_ok(p, nullptr)) return 0;
+    return make_layout(p).total;
+}
+
+int lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *hip_stream,
+               lbm_handle **out)
+{
+    if (!out) return LBM_E_INVALID;
+    *out = nullptr;
+    std::string why;
+    if (!params_ok(p, &why)) return LBM_E_INVALID;
+    if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) != 0) return LBM_E_INVALID;
+    const Layout lay = make_layout(p);
+    if (ws_bytes < lay.total) return LBM_E_NOMEM;
+    lbm_handle *h = new (std::nothrow) lbm_handle();
+    if (!h) return LBM_E_NOMEM;
+    h->p = *p;
+    h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    h->ws = reinterpret_cast<char *>(dev_ws);
+    h->ws_bytes = ws_bytes;
+    h->lay = lay;
+    h->device_driven = p->ybc == LBM_Y_WALL_FOLLOW || (p->flags & LBM_FLAG_WINDOW);
+    h->mode = p->ybc == LBM_Y_PERIODIC ? kModePeriodic : (h->device_driven ? kModeDevice : kModeFixed);
+    for (int i = 0; i < 9; ++i) h->Wd[i] = offset_base(p->precision, i, p->rho_ref);
+    int rc = LBM_DISPATCH(p->precision, do_init, h);
+    if (rc == LBM_OK && h->device_driven) {
+        // rows the first step must sweep: the initial front (at most
+        // init_rows) plus one; every row above is empty
+        int64_t nr = (p->flags & LBM_FLAG_WINDOW) ? std::min<int64_t>(p->H, p->init_rows + 2) : p->H;
+        if (nr < 1) nr = 1;
+        rc = h->hip(launch_state_set(h->st(), 0, p->H, nr, 0, h->stream), "state");
+    }
+    if (rc != LBM_OK) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_handle *h, int64_t nsteps)
+{
+    int rc = usable(h);
+    if (rc) return rc;
+    if (nsteps < 0) return LBM_E_INVALID;
+    return LBM_DISPATCH(h->p.precision, do_step, h, nsteps);
+}
+
+int lbm_front_heights(lbm_handle *h, int32_t *host_h, int64_t *step_out)
+{
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!host_h) return LBM_E_INVALID;
+    rc = h->hip(hipMemcpyAsync(host_h, h->hslot(h->t), (size_t)h->p.L * 4, hipMemcpyDeviceToHost,
+                               h->stream),
+                "front heights copy");
+    if (rc) return rc;
+    if (step_out) *step_out = h->t;
+    return sync_and_check(h);
+}
+
+int lbm_front_heights_async(lbm_handle *h, int32_t *dst)
+{
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!dst) return LBM_E_INVALID;
+    return h->hip(hipMemcpyAsync(dst, h->hslot(h->t), (size_t)h->p.L * 4, hipMemcpyDefault,
+                                 h->stream),
+                  "front heights copy");
+}
+
+int lbm_diagnostics(lbm_handle *h, lbm_diag *out)
+{
+    if (!h || !out) return LBM_E_INVALID;
+    DiagArgs a{};
+    a.partials = h->partials();
+    a.nblocks = h->lay.nblocks;
+    a.h_cur = h->hslot(h->t);
+    a.colmax = h->colmax();
+    a.L = h->p.L;
+    a.st = h->st();
+    a.out = h->diag();
+    int rc = h->hip(launch_diag(a, h->stream), "diag kernel");
+    if (rc) return rc;
+    DiagOut d{};
+    rc = h->hip(hipMemcpyAsync(&d, h->diag(), sizeof(d), hipMemcpyDeviceToHost, h->stream),
+                "diag copy");
+    if (rc) return rc;
+    if ((rc = h->hip(hipStreamSynchronize(h->stream), "synchronize"))) return rc;
+    out->mass = d.mass;
+    out->src_total = d.src_total;
+    out->fix_total = d.fix_total;
+    out->retired = d.retired;
+    out->hbar = d.hbar;
+    out->W = d.W;
+    out->step = h->t;
+    out->y_wall = d.y_wall;
+    out->h_hi = d.h_hi;
+    out->status = d.status;
+    out->reserved = 0;
+    if (d.status & kStDomainFull) h->fail(LBM_E_DOMAIN_FULL, "front reached the top row of the window");
+    if (d.status & kStNonFinite) h->fail(LBM_E_NONFINITE, "total mass is not finite");
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_handle *h, double *host_f)
+{
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!host_f) return LBM_E_INVALID;
+    const Layout &l = h->lay;
+    const lbm_params &p = h->p;
+    std::vector<char> raw(l.nelem * l.esize);
+    rc = h->hip(hipMemcpyAsync(raw.data(), h->fbuf(h->cur), raw.size(), hipMemcpyDeviceToHost,
+                               h->stream),
+                "populations copy");
+    if (rc) return rc;
+    DevState st{};
+    if ((rc = read_state(h, &st))) return rc;
+    const bool ring = h->mode == kModeDevice;
+    for (int q = 0; q < 9; ++q)
+        for (int j = 0; j < p.H; ++j) {
+            const int64_t y = st.y_wall + j;
+            const bool valid = h->mode == kModePeriodic || y < st.y_valid_top;
+            const int64_t r = ring ? (y % p.H) : j;
+            for (int x = 0; x < p.L; ++x) {
+                const size_t o = ((size_t)q * p.H + j) * p.L + x;
+                host_f[o] = valid ? decode_one(p.precision, raw.data(), (size_t)l.tl.at(q, r, x),
+                                               h->Wd[q])
+                                  : 0.0;
+            }
+        }
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_handle *h, const double *host_f)
+{
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!host_f) return LBM_E_INVALID;
+    const Layout &l = h->lay;
+    const lbm_params &p = h->p;
+    DevState st{};
+    if ((rc = read_state(h, &st))) return rc;
+    std::vector<char> raw(l.nelem * l.esize, 0);
+    const bool ring = h->mode == kModeDevice;
+    for (int q = 0; q < 9; ++q)
+        for (int j = 0; j < p.H; ++j) {
+            const int64_t y = st.y_wall + j;
+            const int64_t r = ring ? (y % p.H) : j;
+            for (int x = 0; x < p.L; ++x)
+                encode_one(p.precision, raw.data(), (size_t)l.tl.at(q, r, x),
+                           host_f[((size_t)q * p.H + j) * p.L + x], h->Wd[q]);
+        }
+    rc = h->hip(hipMemcpyAsync(h->fbuf(h->cur), raw.data(), raw.size(), hipMemcpyHostToDevice,
+                               h->stream),
+                "populations copy");
+    if (rc) return rc;
+    // every row of the window is now live
+    const int64_t hi = st.y_wall + p.H;
+    if ((rc = h->hip(launch_state_set(h->st(), st.y_wall, st.y_wall + p.H, p.H,
+                                      h->device_driven ? hi : st.h_hi, h->stream),
+                     "state")))
+        return rc;
+    if ((rc = LBM_DISPATCH(p.precision, do_mass, h))) return rc;
+    return h->hip(hipStreamSynchronize(h->stream), "synchronize");
+}
+
+int lbm_set_front_heights(lbm_handle *h, const int32_t *host_h)
+{
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!host_h) return LBM_E_INVALID;
+    rc = h->hip(hipMemcpyAsync(h->hslot(h->t), host_h, (size_t)h->p.L * 4, hipMemcpyHostToDevice,
+                               h->stream),
+                "front heights copy");
+    if (rc) return rc;
+    return h->hip(hipStreamSynchronize(h->stream), "synchronize");
+}
+
+size_t lbm_state_bytes(const lbm_handle *h)
+{
+    if (!h) return 0;
+    const Layout &l = h->lay;
+    return sizeof(BlobHeader) + l.nelem * l.esize + 2 * (size_t)h->p.L * 4 +
+           (size_t)l.nblocks * 4 * 8 + sizeof(DevState);
+}
+
+int lbm_get_state(lbm_handle *h, void *host_blob, size_t bytes)
+{
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!host_blob) return LBM_E_INVALID;
+    if (bytes < lbm_state_bytes(h)) return LBM_E_NOMEM;
+    const Layout &l = h->lay;
+    char *b = reinterpret_cast<char *>(host_blob);
+    BlobHeader hd{};
+    hd.magic = kMagic;
+    hd.p = h->p;
+    hd.t = h->t;
+    hd.fbytes = (uint64_t)(l.nelem * l.esize);
+    hd.hbytes = (uint64_t)h->p.L * 4;
+    hd.pbytes = (uint64_t)l.nblocks * 4 * 8;
+    std::memcpy(b, &hd, sizeof hd);
+    size_t o = sizeof hd;
+    struct Piece {
+        const void *src;
+        size_t n;
+    } pieces[] = {{h->fbuf(h->cur), hd.fbytes},
+                  {h->hslot(h->t), hd.hbytes},
+                  {h->colmax(), hd.hbytes},
+                  {h->partials(), hd.pbytes},
+                  {h->st(), sizeof(DevState)}};
+    for (const Piece &pc : pieces) {
+        if ((rc = h->hip(hipMemcpyAsync(b + o, pc.src, pc.n, hipMemcpyDeviceToHost, h->stream),
+                         "state copy")))
+            return rc;
+        o += pc.n;
+    }
+    return h->hip(hipStreamSynchronize(h->stream), "synchronize");
+}
+
+int lbm_set_state(lbm_handle *h, const void *host_blob, size_t bytes)
+{
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!host_blob) return LBM_E_INVALID;
+    if (bytes < lbm_state_bytes(h)) return LBM_E_NOMEM;
+    const Layout &l = h->lay;
+    const char *b = reinterpret_cast<const char *>(host_blob);
+    BlobHeader hd;
+    std::memcpy(&hd, b, sizeof hd);
+    if (hd.magic != kMagic || std::memcmp(&hd.p, &h->p, sizeof(lbm_params)) != 0 ||
+        hd.fbytes != (uint64_t)(l.nelem * l.esize))
+        return LBM_E_INVALID;
+    h->t = hd.t;
+    size_t o = sizeof hd;
+    struct Piece {
+        void *dst;
+        size_t n;
+    } pieces[] = {{h->fbuf(h->cur), hd.fbytes},
+                  {h->hslot(h->t), hd.hbytes},
+                  {h->colmax(), hd.hbytes},
+                  {h->partials(), hd.pbytes},
+                  {h->st(), sizeof(DevState)}};
+    for (const Piece &pc : pieces) {
+        if ((rc = h->hip(hipMemcpyAsync(pc.dst, b + o, pc.n, hipMemcpyHostToDevice, h->stream),
+                         "state copy")))
+            return rc;
+        o += pc.n;
+    }
+    // the next step's front-height slot starts at the wall row
+    DevState st;
+    std::memcpy(&st, b + o - sizeof(DevState), sizeof st);
+    if ((rc = h->hip(launch_fill_i32(h->hslot(h->t + 1), h->p.L, (int32_t)st.y_wall, h->stream),
+                     "fill")))
+        return rc;
+    if (!h->device_driven &&
+        (rc = h->hip(launch_fill_i32(h->hslot(h->t + 2), h->p.L, 0, h->stream), "fill")))
+        return rc;
+    return h->hip(hipStreamSynchronize(h->stream), "synchronize");
+}
+
+const char *lbm_last_error(const lbm_handle *h)
+{
+    if (!h) return "null handle";
+    return h->msg.c_str();
+}
+
+int lbm_destroy(lbm_handle *h)
+{
+    if (!h) return LBM_E_INVALID;
+    delete h;
+    return LBM_OK;
+}
+
+}  // extern "C"
+// ============================================================================
+// Batches (implemented in lbm_batch.cpp when built; these are the entry
+// points used until then)
+// ============================================================================
+extern "C" {
+int lbm_batch_create(void *, lbm_batch **out)
+{
+    if (out) *out = nullptr;
+    return LBM_E_UNSUPPORTED;
+}
+int lbm_batch_add(lbm_batch *, lbm_handle *) { return LBM_E_UNSUPPORTED; }
+int lbm_batch_remove(lbm_batch *, lbm_handle *) { return LBM_E_UNSUPPORTED; }
+int lbm_batch_step(lbm_batch *, int64_t) { return LBM_E_UNSUPPORTED; }
+int lbm_batch_destroy(lbm_batch *) { return LBM_E_UNSUPPORTED; }
+}

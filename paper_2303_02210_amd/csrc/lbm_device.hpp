@@ -1,0 +1,127 @@
+// lbm_device.hpp -- device-side building blocks of the gfx950 growing-tissue
+// lattice Boltzmann library: the D2Q9 lattice, the Philox4x32-10 counter-based
+// generator and the population storage codecs.
+//
+// Lattice (square D2Q9; the paper's Eq. 3 and Eq. 4 written for it): weights
+// 4/9 (rest), 1/9 (axes), 1/36 (diagonals), c_s^2 = 1/3.  Directions:
+// 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+// as 1, 2, 3", SC'11).  Ten rounds of: two 32x32->64 multiplications of
+// counter words 0 and 2, halves swapped and xored with counter words 1, 3 and
+// the key; the key advances by the two Weyl increments between rounds.
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1)
+{
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)kMulA * c0;
+        const uint64_t pb = (uint64_t)kMulB * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += kWeylA;
+        k1 += kWeylB;
+    }
+    U4 o;
+    o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+    return o;
+}
+
+// Counter word 3 is 4 * stream + call.
+enum : uint32_t { kStreamNoise = 0, kStreamInit = 1 };
+
+// Nine 24-bit draws for the noise of site (x, y) at step t: the top 24 bits of
+// the eight words of calls 0 and 1, and the low bytes of call 0's words 0-2.
+// Returned as the exact factors v_i = (2 k_i + 1 - 2^24) 2^-24 in (-1, 1), so
+// that eta~_i = sigma v_i is uniform on (-sigma, sigma).
+template <class R>
+__device__ __forceinline__ void noise_factors(uint32_t seed, uint32_t replica, uint32_t t,
+                                              uint32_t x, uint32_t y, R v[9])
+{
+    const U4 a = philox10(x, y, t, 4u * kStreamNoise + 0u, seed, replica);
+    const U4 b = philox10(x, y, t, 4u * kStreamNoise + 1u, seed, replica);
+    uint32_t k[9];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        k[i] = a.v[i] >> 8;
+        k[4 + i] = b.v[i] >> 8;
+    }
+    k[8] = ((a.v[0] & 0xFFu) << 16) | ((a.v[1] & 0xFFu) << 8) | (a.v[2] & 0xFFu);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int n = (int)(2u * k[i] + 1u) - (1 << 24);   // odd, |n| < 2^24: exact
+        v[i] = (R)n * (R)(1.0 / 16777216.0);
+    }
+}
+
+// Uniform (k + 1/2) 2^-24 of the initial density at (x, y).
+__device__ __forceinline__ double init_uniform(uint32_t seed, uint32_t replica, uint32_t x,
+                                               uint32_t y)
+{
+    const U4 a = philox10(x, y, 0u, 4u * kStreamInit + 0u, seed, replica);
+    return ((double)(a.v[0] >> 8) + 0.5) * (1.0 / 16777216.0);
+}
+
+// ---------------------------------------------------------------------------
+// Storage codecs.  FP64 / FP32 store f_i as is.  The 16-bit storages keep
+// s_i = f_i - W_i with W_i = w_i rho_ref rounded to the storage type; an empty
+// site stores -W_i exactly and decodes to exactly 0.
+// ---------------------------------------------------------------------------
+template <class S>
+struct Codec;
+
+template <>
+struct Codec<double> {
+    using R = double;
+    __device__ __forceinline__ static R dec(double s, R) { return s; }
+    __device__ __forceinline__ static double enc(R f, R) { return f; }
+};
+
+template <>
+struct Codec<float> {
+    using R = float;
+    __device__ __forceinline__ static R dec(float s, R) { return s; }
+    __device__ __forceinline__ static float enc(R f, R) { return f; }
+};
+
+template <>
+struct Codec<__half> {
+    using R = float;
+    __device__ __forceinline__ static R dec(__half s, R W) { return __half2float(s) + W; }
+    __device__ __forceinline__ static __half enc(R f, R W) { return __float2half_rn(f - W); }
+};
+
+template <>
+struct Codec<__hip_bfloat16> {
+    using R = float;
+    __device__ __forceinline__ static R dec(__hip_bfloat16 s, R W)
+    {
+        return __bfloat162float(s) + W;
+    }
+    __device__ __forceinline__ static __hip_bfloat16 enc(R f, R W)
+    {
+        return __float2bfloat16(f - W);
+    }
+};
+
+}  // namespace lbm

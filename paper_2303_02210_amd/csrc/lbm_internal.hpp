@@ -1,0 +1,155 @@
+// lbm_internal.hpp -- kernel argument blocks and launchers shared by the
+// kernels (lbm_kernels.hip) and the C-ABI implementation (lbm_api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+namespace lbm {
+
+template <class S>
+struct Real;
+template <>
+struct Real<double> { using type = double; };
+template <>
+struct Real<float> { using type = float; };
+template <>
+struct Real<__half> { using type = float; };
+template <>
+struct Real<__hip_bfloat16> { using type = float; };
+
+enum : int { kModeFixed = 0, kModeDevice = 1, kModePeriodic = 2 };
+enum : int { kRegionAll = 0, kRegionFrontBand = 1, kRegionRearBand = 2 };
+enum : uint32_t { kStDomainFull = 1u, kStNonFinite = 2u };
+
+// Population layout.  Each row holds the padded width Lp = n_tiles * TW
+// columns as n_tiles consecutive tiles; a tile stores the 9 directions of TW
+// consecutive columns one after the other ([tile][direction][column in tile]).
+// A wavefront's reads of one row are then a few contiguous runs instead of
+// nine streams far apart.  TW is a power of two (64, 128 or 256 columns).
+struct Tiles {
+    int64_t rs;    // elements per row: 9 * Lp
+    int32_t tws;   // log2(TW)
+    __host__ __device__ int64_t col(int x) const
+    {
+        return ((int64_t)(x >> tws) * 9 << tws) + (x & ((1 << tws) - 1));
+    }
+    __host__ __device__ int64_t at(int q, int64_t r, int x) const
+    {
+        return r * rs + col(x) + ((int64_t)q << tws);
+    }
+};
+
+// Device-resident run state (in the workspace).
+struct DevState {
+    int64_t  y_wall;        // absolute row of window row 0
+    int64_t  y_valid_top;   // rows at or above this read as empty
+    int64_t  n_rows;        // window rows the next step sweeps
+    int64_t  h_hi;          // highest front height seen (device-driven modes)
+    double   retired_total; // mass of rows left behind by the wall
+    double   retired_last;  // ... by the last wall move
+    uint32_t status;        // kSt* bits
+    uint32_t pad;
+};
+
+// Diagnostics record written by diag_kernel (layout of lbm_diag).
+struct DiagOut {
+    double   mass, src_total, fix_total, retired, hbar, W;
+    int64_t  step, y_wall, h_hi;
+    uint32_t status, reserved;
+};
+
+template <class S>
+struct StepArgs {
+    using R = typename Real<S>::type;
+    const S *fin;
+    S *fout;
+    const int32_t *h_prev;
+    int32_t *h_next;
+    int32_t *h_clear;       // slot to reset to the wall row (fixed modes), or null
+    int32_t *colmax;        // per-column highest front
+    double *partials;       // [nblocks][4]: mass, injected, fix, spare
+    DevState *st;
+    int32_t L, H, ty;
+    Tiles tl;
+    int32_t mode, growth, region, region_width;
+    int32_t noise;
+    uint32_t t, seed, replica;
+    R omega, kmu, rho_c, g, sigma;
+    R w[9];
+    R Wd[9];
+};
+
+template <class S>
+struct InitArgs {
+    using R = typename Real<S>::type;
+    S *f;
+    int32_t *h0;
+    int32_t *colmax;
+    double *partials;
+    int32_t L, H, ty;
+    Tiles tl;
+    int32_t init_rows;
+    int32_t cpt;            // columns per thread
+    uint32_t seed, replica;
+    double rho_init, init_amp, rho_c;
+    double w[9];
+    R Wd[9];
+};
+
+template <class S>
+struct MassArgs {
+    using R = typename Real<S>::type;
+    const S *f;
+    double *partials;
+    const DevState *st;
+    int32_t L, H, ty;
+    int32_t cpt;            // columns per thread
+    Tiles tl;
+    R Wd[9];
+};
+
+template <class S>
+struct FinalizeArgs {
+    using R = typename Real<S>::type;
+    const S *f;             // state just written
+    int32_t *h_next;        // its front heights
+    int32_t *h_clear;       // slot of the step after next
+    const int32_t *colmax;  // per-column highest front since creation
+    DevState *st;
+    int32_t L, H;
+    Tiles tl;
+    int32_t follow, window, min_gap;
+    double w_factor;
+    R Wd[9];
+};
+
+struct DiagArgs {
+    const double *partials;
+    int32_t nblocks;
+    const int32_t *h_cur;
+    const int32_t *colmax;
+    int32_t L;
+    DevState *st;
+    DiagOut *out;
+};
+
+template <class S>
+hipError_t launch_step(const StepArgs<S> &a, dim3 grid, int nt, int rb, hipStream_t s);
+template <class S>
+hipError_t launch_step_vec(const StepArgs<S> &a, dim3 grid, int nt, int vb, int wpe, hipStream_t s);
+template <class S>
+hipError_t launch_init(const InitArgs<S> &a, dim3 grid, int nt, hipStream_t s);
+template <class S>
+hipError_t launch_mass(const MassArgs<S> &a, dim3 grid, int nt, hipStream_t s);
+template <class S>
+hipError_t launch_finalize(const FinalizeArgs<S> &a, hipStream_t s);
+hipError_t launch_diag(const DiagArgs &a, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+hipError_t launch_state_set(DevState *st, int64_t y_wall, int64_t y_valid_top, int64_t n_rows,
+                            int64_t h_hi, hipStream_t s);
+
+}  // namespace lbm

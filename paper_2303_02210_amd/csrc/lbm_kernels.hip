@@ -1,0 +1,1025 @@
+// lbm_kernels.hip -- gfx950 kernels of the growing-tissue D2Q9 lattice
+// Boltzmann library.
+//
+// One fused kernel advances the whole lattice by one step (the paper's
+// Appendix A, steps 1-7, on every site): pull-streaming with the rear-wall
+// bounce-back, moments (Eq. 1), the two-step bounce-back front (Sec. II),
+// the growth source, the friction-damped steady state (Eq. 3) and BGK
+// relaxation (Eq. 2), the zero-sum noise (Eq. 4) and the negative-population
+// fix, then the store, per-column front heights (atomic max) and per-block
+// float64 mass tallies.  Populations are stored row by row in tiles of TW
+// columns holding the 9 directions one after the other (see Tiles), so a
+// wavefront reads and writes a few contiguous runs per row.  Threads own
+// columns and march over `ty` rows.
+//
+// The arithmetic follows one fixed order with no contraction (this file is
+// compiled with -ffp-contract=off), so the float64 instantiation reproduces a
+// plain sequential float64 evaluation of the same formulas bit for bit.
+#include "lbm_device.hpp"
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ R sum9(const R v[9])
+{
+    R s = v[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) s = s + v[i];
+    return s;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic block sum of three values (fixed tree), result in thread 0.
+template <int NT>
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c)
+{
+    constexpr int NW = NT / 64;
+    __shared__ double red[3][NW];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    if (lane == 0) {
+        red[0][wave] = a;
+        red[1][wave] = b;
+        red[2][wave] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = red[0][0];
+        b = red[1][0];
+        c = red[2][0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+            a += red[0][w];
+            b += red[1][w];
+            c += red[2][w];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Steps 3-7 of the update at a tissue site (streamed density rho_s >= rho_c),
+// given its streamed populations fs.  S_acc / x_acc collect the injected mass
+// and the mass change of the negative-population fix.
+// ---------------------------------------------------------------------------
+template <class S>
+__device__ __forceinline__ void tissue_update(const StepArgs<S> &a, typename Codec<S>::R fs[9],
+                                              typename Codec<S>::R rho_s,
+                                              typename Codec<S>::R out[9], uint32_t x, int64_t y,
+                                              int64_t y_wall, int32_t hp, double &s_acc,
+                                              double &x_acc)
+{
+    using R = typename Codec<S>::R;
+    // ---- step 2 (rest): momentum ----------------------------------------------
+    const R jx = ((((fs[1] - fs[3]) + fs[5]) - fs[6]) - fs[7]) + fs[8];
+    const R jy = ((((fs[2] - fs[4]) + fs[5]) + fs[6]) - fs[7]) - fs[8];
+    // ---- step 3: growth source, shared by the 8 moving directions (opposite
+    // pairs receive equal amounts: no momentum) --------------------------------
+    bool grow = a.growth != 0;
+    if (a.region == kRegionFrontBand) grow = grow && (y >= (int64_t)hp - a.region_width);
+    else if (a.region == kRegionRearBand) grow = grow && (y < y_wall + a.region_width);
+    const R S_ = grow ? a.g * rho_s : R(0);
+    const R s8 = S_ * R(0.125);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) fs[i] = fs[i] + s8;
+    const R rho = rho_s + S_;
+    s_acc += (double)S_;
+
+    // ---- step 4: u* = (1 - mu) u and the steady state of Eq. 3 ---------------
+    const R ux = (jx / rho) * a.kmu;
+    const R uy = (jy / rho) * a.kmu;
+    const R usq = ux * ux + uy * uy;
+    const R u15 = R(1.5) * usq;
+    const R nux = -ux, nuy = -uy;
+    R cu[9];
+    cu[0] = R(0);
+    cu[1] = ux;
+    cu[2] = uy;
+    cu[3] = nux;
+    cu[4] = nuy;
+    cu[5] = ux + uy;
+    cu[6] = nux + uy;
+    cu[7] = nux + nuy;
+    cu[8] = ux + nuy;
+    // ---- step 5 (tissue): relax towards f^SS (Eq. 2) --------------------------
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const R c = cu[i];
+        const R fss = (a.w[i] * rho) * (((R(1) + R(3) * c) + R(4.5) * (c * c)) - u15);
+        out[i] = fs[i] - a.omega * (fs[i] - fss);
+    }
+    // ---- step 6: zero-sum noise where rho > rho_c (Eq. 4) ----------------------
+    if (a.noise && rho > a.rho_c) {
+        R v[9];
+        noise_factors<R>(a.seed, a.replica, a.t, x, (uint32_t)y, v);
+        R eta[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) eta[i] = a.sigma * v[i];
+        const R m = sum9(eta) / R(9);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) out[i] = out[i] + (eta[i] - m);
+    }
+    // ---- step 7: negative populations --------------------------------------------
+    bool neg = false;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) neg = neg || (out[i] < R(0));
+    if (neg) {
+        const R before = sum9(out);
+        if (out[0] < R(0)) {
+            const R rho_pre = sum9(out);
+            out[0] = R(0);
+            const R rest = sum9(out);
+            if (rest > R(0)) {
+                const R r = rho_pre / rest;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) out[i] = out[i] * r;
+            }
+        }
+        constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            if (out[i] < R(0)) {
+                out[opp[i]] = out[opp[i]] + (-out[i]);
+                out[i] = R(0);
+            }
+        }
+        x_acc += (double)(sum9(out) - before);
+    }
+}
+
+// Steps 2-7 at one site from its nine streamed raw (stored) values v, with
+// validity already applied to fs (the decoded values).  The void branch of
+// step 5 only reverses directions, so it forwards the stored values as they
+// are.  Writes the stored result to so[9]; returns true for tissue.
+template <class S>
+__device__ __forceinline__ bool site_step(const StepArgs<S> &a, const S v[9],
+                                          typename Codec<S>::R fs[9], const typename Codec<S>::R Wd[9],
+                                          S so[9], uint32_t x, int64_t y, int64_t y_wall, int32_t hp,
+                                          double &m_acc, double &s_acc, double &x_acc)
+{
+    using R = typename Codec<S>::R;
+    // ---- step 2: density ---------------------------------------------------------
+    const R rho_s = sum9(fs);
+    if (rho_s >= a.rho_c) {
+        R out[9];
+        tissue_update<S>(a, fs, rho_s, out, x, y, y_wall, hp, s_acc, x_acc);
+        R kept[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            so[i] = Codec<S>::enc(out[i], Wd[i]);
+            kept[i] = Codec<S>::dec(so[i], Wd[i]);
+        }
+        m_acc += (double)sum9(kept);
+        return true;
+    }
+    // ---- step 5 (void): reverse every direction ------------------------------------
+    constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) so[i] = v[opp[i]];
+    m_acc += (double)rho_s;
+    return false;
+}
+
+// Where one window row pulls its nine populations from (all wave-uniform):
+// the physical row and plane of each pull, and whether the source is live.
+struct RowSrc {
+    int rm, r0, rp;        // physical rows y-1, y, y+1
+    bool below;            // y-1 is behind the rear wall: reflect in place
+    bool vm, v0, vp;       // source rows hold live data
+};
+
+__device__ __forceinline__ RowSrc row_sources(int mode, int j, int r0, int H, int64_t y,
+                                              int64_t y_top)
+{
+    RowSrc s;
+    s.r0 = r0;
+    s.rm = (r0 == 0) ? H - 1 : r0 - 1;
+    s.rp = (r0 == H - 1) ? 0 : r0 + 1;
+    if (mode == kModePeriodic) {
+        s.below = false;
+        s.vm = s.v0 = s.vp = true;
+    } else {
+        s.below = (j == 0);
+        s.v0 = y < y_top;
+        s.vm = !s.below && (y - 1 < y_top);
+        s.vp = (y + 1 < y_top) && (j + 1 < H);
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// The fused step.  Each thread owns one column; a block of NT threads covers
+// NT consecutive columns and `ty` rows, visited in batches of RB rows whose
+// 9*RB loads are all issued before any of them is used.  Blocks are
+// renumbered so that each XCD (dispatch goes round-robin over the 8 XCDs)
+// works on one contiguous part of the lattice, keeping the cache lines that
+// neighbouring blocks share in one L2.
+// ---------------------------------------------------------------------------
+template <class S, int NT, int RB>
+__global__ __launch_bounds__(NT) void step_kernel(StepArgs<S> a)
+{
+    using R = typename Codec<S>::R;
+    const int nbx = gridDim.x;
+    const int nb = nbx * gridDim.y;
+    int lin = blockIdx.y * nbx + blockIdx.x;
+    if ((nb & 7) == 0) lin = (lin & 7) * (nb >> 3) + (lin >> 3);
+    const int bx = lin % nbx, by = lin / nbx;
+
+    const int L = a.L, H = a.H;
+    const int xr = bx * NT + threadIdx.x;
+    const bool active = xr < L;
+    const uint32_t x = active ? (uint32_t)xr : (uint32_t)(L - 1);   // loads stay in bounds
+    const uint32_t xm = (x == 0) ? (uint32_t)(L - 1) : x - 1;
+    const uint32_t xp = (x == (uint32_t)(L - 1)) ? 0u : x + 1;
+
+    int64_t y_wall = 0, y_top = H, nrows = H;
+    if (a.mode == kModeDevice) {
+        y_wall = a.st->y_wall;
+        y_top = a.st->y_valid_top;
+        nrows = a.st->n_rows;
+    }
+    const int j0 = by * a.ty;
+    const int jend = (int)min((int64_t)(j0 + a.ty), nrows);
+
+    double m_acc = 0.0, s_acc = 0.0, x_acc = 0.0;
+    int64_t ymax = -1;
+    const int32_t hp = (a.region == kRegionFrontBand) ? a.h_prev[x] : 0;
+    R Wd[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Wd[i] = a.Wd[i];
+
+    const Tiles tl = a.tl;
+    const int64_t cx = tl.col(x), cxm = tl.col(xm), cxp = tl.col(xp);
+    const int tws = tl.tws;
+    const S *__restrict__ F = a.fin;
+    S *__restrict__ G = a.fout;
+    int rnext = (a.mode == kModeDevice) ? (int)((y_wall + j0) % H) : j0;
+
+    for (int jb = j0; jb < jend; jb += RB) {
+        S raw[RB][9];
+        RowSrc src[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const int j = jb + k;
+            const int64_t y = y_wall + j;
+            src[k] = row_sources(a.mode, j, rnext, H, y, y_top);
+            rnext = src[k].rp;
+            if (j < jend) {
+                const RowSrc &s = src[k];
+                // ---- step 1: pull-stream; the wall reflects in place -----
+                const S *row0 = F + (int64_t)s.r0 * tl.rs;
+                const S *rowm = F + (int64_t)(s.below ? s.r0 : s.rm) * tl.rs;
+                const S *rowp = F + (int64_t)s.rp * tl.rs;
+                const int qn2 = s.below ? 4 : 2, qn5 = s.below ? 7 : 5, qn6 = s.below ? 8 : 6;
+                const int64_t cn5 = s.below ? cx : cxm, cn6 = s.below ? cx : cxp;
+                raw[k][0] = row0[cx + (0 << tws)];
+                raw[k][1] = row0[cxm + (1 << tws)];
+                raw[k][3] = row0[cxp + (3 << tws)];
+                raw[k][2] = rowm[cx + (qn2 << tws)];
+                raw[k][5] = rowm[cn5 + (qn5 << tws)];
+                raw[k][6] = rowm[cn6 + (qn6 << tws)];
+                raw[k][4] = rowp[cx + (4 << tws)];
+                raw[k][7] = rowp[cxp + (7 << tws)];
+                raw[k][8] = rowp[cxm + (8 << tws)];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+            const int j = jb + k;
+            if (j >= jend) break;
+            const int64_t y = y_wall + j;
+            const RowSrc &s = src[k];
+            S v[9];
+            R fs[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                v[i] = raw[k][i];
+                fs[i] = Codec<S>::dec(v[i], Wd[i]);
+            }
+            // sources that hold no live data stream in nothing
+            if (!s.v0) {
+                v[0] = Codec<S>::enc(R(0), Wd[0]);
+                v[1] = v[3] = Codec<S>::enc(R(0), Wd[1]);
+                fs[0] = fs[1] = fs[3] = R(0);
+            }
+            if (!s.below && !s.vm) {
+                v[2] = Codec<S>::enc(R(0), Wd[2]);
+                v[5] = v[6] = Codec<S>::enc(R(0), Wd[5]);
+                fs[2] = fs[5] = fs[6] = R(0);
+            }
+            if (!s.vp) {
+                v[4] = Codec<S>::enc(R(0), Wd[4]);
+                v[7] = v[8] = Codec<S>::enc(R(0), Wd[7]);
+                fs[4] = fs[7] = fs[8] = R(0);
+            }
+            S so[9];
+            double m_site = 0.0, s_site = 0.0, x_site = 0.0;
+            const bool tissue =
+                site_step<S>(a, v, fs, Wd, so, x, y, y_wall, hp, m_site, s_site, x_site);
+            S *rowg = G + (int64_t)s.r0 * tl.rs + cx;
+            if (active) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) rowg[i << tws] = so[i];
+                m_acc += m_site;
+                s_acc += s_site;
+                x_acc += x_site;
+                if (tissue) {
+                    ymax = y;
+                    if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
+                }
+            }
+        }
+    }
+
+    // ---- front heights -----------------------------------------------------
+    if (active) {
+        if (ymax >= 0) {
+            const int32_t hv = (int32_t)(ymax + 1);
+            atomicMax(a.h_next + x, hv);
+            atomicMax(a.colmax + x, hv);
+        }
+        if (a.h_clear && by == 0) a.h_clear[x] = 0;
+    }
+
+    // ---- per-block tallies (fixed order: deterministic) ------------------------
+    block_sum3<NT>(m_acc, s_acc, x_acc);
+    if (threadIdx.x == 0) {
+        double *p = a.partials + 4 * (by * nbx + bx);
+        p[0] = m_acc;
+        p[1] += s_acc;
+        p[2] += x_acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 16-byte vector form of the step.  Each lane owns V = 16 / sizeof(S)
+// consecutive columns, so every plane row is read and written with aligned
+// 16-byte accesses (nontemporal: each value is used once per step).  The
+// populations that move along x arrive from the neighbouring column: inside
+// a wavefront that is the neighbouring lane's first or last element (one
+// cross-lane shuffle per plane), at the wavefront's two edges and across the
+// periodic seam it is a single wave-uniform load.  Needs L % V == 0.
+// ---------------------------------------------------------------------------
+// Raw per-lane vectors of ND dwords (8 or 16 bytes).
+template <int ND>
+struct RawVec;
+template <>
+struct RawVec<1> {
+    typedef uint32_t type __attribute__((ext_vector_type(1)));
+};
+template <>
+struct RawVec<2> {
+    typedef uint32_t type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct RawVec<4> {
+    typedef uint32_t type __attribute__((ext_vector_type(4)));
+};
+
+template <class S, int ND>
+__device__ __forceinline__ S get_el(const typename RawVec<ND>::type &v, int i)
+{
+    if constexpr (sizeof(S) == 8) {
+        const uint64_t b = (uint64_t)v[2 * i] | ((uint64_t)v[2 * i + 1] << 32);
+        return __longlong_as_double((long long)b);
+    } else if constexpr (sizeof(S) == 4) {
+        return __uint_as_float(v[i]);
+    } else {
+        const unsigned short b = (unsigned short)((v[i >> 1] >> (16 * (i & 1))) & 0xFFFFu);
+        S r;
+        __builtin_memcpy(&r, &b, 2);
+        return r;
+    }
+}
+
+template <class S, int ND>
+__device__ __forceinline__ void put_el(typename RawVec<ND>::type &v, int i, S s)
+{
+    if constexpr (sizeof(S) == 8) {
+        const uint64_t b = (uint64_t)__double_as_longlong(s);
+        v[2 * i] = (uint32_t)b;
+        v[2 * i + 1] = (uint32_t)(b >> 32);
+    } else if constexpr (sizeof(S) == 4) {
+        v[i] = __float_as_uint(s);
+    } else {
+        unsigned short b;
+        __builtin_memcpy(&b, &s, 2);
+        const int sh = 16 * (i & 1);
+        v[i >> 1] = (v[i >> 1] & ~(0xFFFFu << sh)) | ((uint32_t)b << sh);
+    }
+}
+
+template <int ND>
+__device__ __forceinline__ typename RawVec<ND>::type vload(const void *p)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<const typename RawVec<ND>::type *>(p));
+}
+template <int ND>
+__device__ __forceinline__ void vstore(void *p, const typename RawVec<ND>::type &v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<typename RawVec<ND>::type *>(p));
+}
+
+// The left lane's last element (inside the wave) or the edge value.
+template <class S, int ND>
+__device__ __forceinline__ S from_left(const typename RawVec<ND>::type &own, S edge, bool use_edge)
+{
+    constexpr int NV = ND * 4 / (int)sizeof(S);
+    typename RawVec<ND>::type t;
+    t[ND - 1] = (uint32_t)__shfl_up((int)own[ND - 1], 1, 64);
+    if constexpr (sizeof(S) == 8) t[ND - 2] = (uint32_t)__shfl_up((int)own[ND - 2], 1, 64);
+    const S n = get_el<S, ND>(t, NV - 1);
+    return use_edge ? edge : n;
+}
+// The right lane's first element (inside the wave) or the edge value.
+template <class S, int ND>
+__device__ __forceinline__ S from_right(const typename RawVec<ND>::type &own, S edge, bool use_edge)
+{
+    typename RawVec<ND>::type t;
+    t[0] = (uint32_t)__shfl_down((int)own[0], 1, 64);
+    if constexpr (sizeof(S) == 8) t[1] = (uint32_t)__shfl_down((int)own[1], 1, 64);
+    const S n = get_el<S, ND>(t, 0);
+    return use_edge ? edge : n;
+}
+
+// ND dwords per lane; WPE: waves per SIMD the register allocation aims for.
+template <class S, int NT, int ND, int WPE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+void step_kernel_vec(StepArgs<S> a)
+{
+    using R = typename Codec<S>::R;
+    using VT = typename RawVec<ND>::type;
+    constexpr int V = ND * 4 / (int)sizeof(S);
+    const int nbx = gridDim.x;
+    const int nb = nbx * gridDim.y;
+    int lin = blockIdx.y * nbx + blockIdx.x;
+    if ((nb & 7) == 0) lin = (lin & 7) * (nb >> 3) + (lin >> 3);
+    const int bx = lin % nbx, by = lin / nbx;
+
+    const int L = a.L, H = a.H;
+    const int lane = threadIdx.x & 63;
+    const int xv = (bx * NT + (int)threadIdx.x) * V;          // first column of this lane
+    const int x0 = xv - lane * V;                               // first column of the wave
+    const bool active = xv < L;
+    // wave-uniform edge columns: left of the wave and right of it (periodic)
+    const int xl = (x0 == 0 || x0 >= L) ? L - 1 : x0 - 1;     // (a wave past L reads in bounds)
+    const int xr = (x0 + 64 * V < L) ? x0 + 64 * V : 0;
+    const bool edge_l = (lane == 0);
+    const bool edge_r = (lane == 63) || (xv + V >= L);
+
+    int64_t y_wall = 0, y_top = H, nrows = H;
+    if (a.mode == kModeDevice) {
+        y_wall = a.st->y_wall;
+        y_top = a.st->y_valid_top;
+        nrows = a.st->n_rows;
+    }
+    const int j0 = by * a.ty;
+    const int jend = (int)min((int64_t)(j0 + a.ty), nrows);
+
+    double m_acc = 0.0, s_acc = 0.0, x_acc = 0.0;
+    int32_t jmax[V], hp[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        jmax[i] = -1;
+        hp[i] = (a.region == kRegionFrontBand && active) ? a.h_prev[xv + i] : 0;
+    }
+    R Wd[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Wd[i] = a.Wd[i];
+
+    const Tiles tl = a.tl;
+    const int tws = tl.tws;
+    // lanes past the last column read (and never store) the last vector, so
+    // every access stays inside the row
+    const int64_t cv = tl.col(active ? xv : L - V), cl = tl.col(xl), cr = tl.col(xr);
+    const S *__restrict__ F = a.fin;
+    S *__restrict__ G = a.fout;
+    int r0 = (a.mode == kModeDevice) ? (int)((y_wall + j0) % H) : j0;
+
+    for (int j = j0; j < jend; ++j) {
+        const int64_t y = y_wall + j;
+        const RowSrc s = row_sources(a.mode, j, r0, H, y, y_top);
+        const S *row0 = F + (int64_t)s.r0 * tl.rs;
+        const S *rowm = F + (int64_t)(s.below ? s.r0 : s.rm) * tl.rs;
+        const S *rowp = F + (int64_t)s.rp * tl.rs;
+        // directions feeding N, NE, NW: the row below, or this site reflected
+        const int qn2 = s.below ? 4 : 2, qn5 = s.below ? 7 : 5, qn6 = s.below ? 8 : 6;
+
+        // ---- step 1: pull-stream (vector loads, all issued up front) ----
+        const VT A0 = vload<ND>(row0 + cv + (0 << tws));
+        const VT A1 = vload<ND>(row0 + cv + (1 << tws));
+        const VT A3 = vload<ND>(row0 + cv + (3 << tws));
+        const VT A2 = vload<ND>(rowm + cv + (qn2 << tws));
+        const VT A5 = vload<ND>(rowm + cv + (qn5 << tws));
+        const VT A6 = vload<ND>(rowm + cv + (qn6 << tws));
+        const VT A4 = vload<ND>(rowp + cv + (4 << tws));
+        const VT A7 = vload<ND>(rowp + cv + (7 << tws));
+        const VT A8 = vload<ND>(rowp + cv + (8 << tws));
+        const S e1 = row0[cl + (1 << tws)], e3 = row0[cr + (3 << tws)];
+        const S e5 = rowm[cl + (5 << tws)], e6 = rowm[cr + (6 << tws)];
+        const S e7 = rowp[cr + (7 << tws)], e8 = rowp[cl + (8 << tws)];
+        // neighbours across lanes (E-type: from x-1, W-type: from x+1)
+        const S n1 = from_left<S, ND>(A1, e1, edge_l);
+        const S n8 = from_left<S, ND>(A8, e8, edge_l);
+        const S n5 = from_left<S, ND>(A5, e5, edge_l);
+        const S n3 = from_right<S, ND>(A3, e3, edge_r);
+        const S n7 = from_right<S, ND>(A7, e7, edge_r);
+        const S n6 = from_right<S, ND>(A6, e6, edge_r);
+
+        VT O[9];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            S v[9];
+            v[0] = get_el<S, ND>(A0, k);
+            v[1] = (k == 0) ? n1 : get_el<S, ND>(A1, k - 1);
+            v[3] = (k == V - 1) ? n3 : get_el<S, ND>(A3, k + 1);
+            v[2] = get_el<S, ND>(A2, k);
+            if (s.below) {
+                v[5] = get_el<S, ND>(A5, k);
+                v[6] = get_el<S, ND>(A6, k);
+            } else {
+                v[5] = (k == 0) ? n5 : get_el<S, ND>(A5, k - 1);
+                v[6] = (k == V - 1) ? n6 : get_el<S, ND>(A6, k + 1);
+            }
+            v[4] = get_el<S, ND>(A4, k);
+            v[7] = (k == V - 1) ? n7 : get_el<S, ND>(A7, k + 1);
+            v[8] = (k == 0) ? n8 : get_el<S, ND>(A8, k - 1);
+            R fs[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fs[i] = Codec<S>::dec(v[i], Wd[i]);
+            // sources that hold no live data stream in nothing
+            if (!s.v0) {
+                v[0] = Codec<S>::enc(R(0), Wd[0]);
+                v[1] = v[3] = Codec<S>::enc(R(0), Wd[1]);
+                fs[0] = fs[1] = fs[3] = R(0);
+            }
+            if (!s.below && !s.vm) {
+                v[2] = Codec<S>::enc(R(0), Wd[2]);
+                v[5] = v[6] = Codec<S>::enc(R(0), Wd[5]);
+                fs[2] = fs[5] = fs[6] = R(0);
+            }
+            if (!s.vp) {
+                v[4] = Codec<S>::enc(R(0), Wd[4]);
+                v[7] = v[8] = Codec<S>::enc(R(0), Wd[7]);
+                fs[4] = fs[7] = fs[8] = R(0);
+            }
+            S so[9];
+            double m_site = 0.0, s_site = 0.0, x_site = 0.0;
+            const uint32_t x = (uint32_t)(xv + k);
+            const bool tissue =
+                site_step<S>(a, v, fs, Wd, so, x, y, y_wall, hp[k], m_site, s_site, x_site);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) put_el<S, ND>(O[i], k, so[i]);
+            if (active) {
+                m_acc += m_site;
+                s_acc += s_site;
+                x_acc += x_site;
+                if (tissue) {
+                    jmax[k] = j;
+                    if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
+                }
+            }
+        }
+        if (active) {
+            S *rowg = G + (int64_t)s.r0 * tl.rs + cv;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) vstore<ND>(rowg + (i << tws), O[i]);
+        }
+        r0 = s.rp;
+    }
+
+    // ---- front heights -----------------------------------------------------
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (jmax[k] >= 0) {
+                const int32_t hv = (int32_t)(y_wall + jmax[k] + 1);
+                atomicMax(a.h_next + xv + k, hv);
+                atomicMax(a.colmax + xv + k, hv);
+            }
+            if (a.h_clear && by == 0) a.h_clear[xv + k] = 0;
+        }
+    }
+
+    // ---- per-block tallies (fixed order: deterministic) ------------------------
+    block_sum3<NT>(m_acc, s_acc, x_acc);
+    if (threadIdx.x == 0) {
+        double *p = a.partials + 4 * (by * nbx + bx);
+        p[0] = m_acc;
+        p[1] += s_acc;
+        p[2] += x_acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Initial state (Appendix A): rows [0, init_rows) at rest, rho uniform on
+// [(1 - a), (1 + a)] rho_init, f_i = w_i rho; everything above empty.  Same
+// thread layout as the step so that partials[.][0] holds the initial mass.
+// ---------------------------------------------------------------------------
+template <class S, int NT>
+__global__ __launch_bounds__(NT) void init_kernel(InitArgs<S> a)
+{
+    using R = typename Codec<S>::R;
+    const int j0 = blockIdx.y * a.ty;
+    double m_acc = 0.0, z1 = 0.0, z2 = 0.0;
+    for (int c = 0; c < a.cpt; ++c) {
+        const int x = (blockIdx.x * NT + threadIdx.x) * a.cpt + c;
+        if (x >= a.L) break;
+        int ymax = -1;
+        const int jend = min(j0 + a.ty, a.H);
+        for (int j = j0; j < jend; ++j) {
+            double rho = 0.0;
+            if (j < a.init_rows) {
+                const double U = init_uniform(a.seed, a.replica, (uint32_t)x, (uint32_t)j);
+                rho = a.rho_init * (1.0 + a.init_amp * (2.0 * U - 1.0));
+            }
+            R kept[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const R f = (R)(a.w[i] * rho);
+                const S s = Codec<S>::enc(f, a.Wd[i]);
+                a.f[a.tl.at(i, j, x)] = s;
+                kept[i] = Codec<S>::dec(s, a.Wd[i]);
+            }
+            const R r = sum9(kept);
+            m_acc += (double)r;
+            if (r >= (R)a.rho_c) ymax = j;
+        }
+        if (ymax >= 0) {
+            atomicMax(a.h0 + x, ymax + 1);
+            atomicMax(a.colmax + x, ymax + 1);
+        }
+    }
+    block_sum3<NT>(m_acc, z1, z2);
+    if (threadIdx.x == 0) {
+        double *p = a.partials + 4 * (blockIdx.y * gridDim.x + blockIdx.x);
+        p[0] = m_acc;
+        p[1] = 0.0;
+        p[2] = 0.0;
+        p[3] = 0.0;
+    }
+}
+
+// Mass of the current state into partials[.][0] (after populations are
+// replaced from the host).  Rows at or above y_valid_top read as empty.
+template <class S, int NT>
+__global__ __launch_bounds__(NT) void mass_kernel(MassArgs<S> a)
+{
+    using R = typename Codec<S>::R;
+    const int j0 = blockIdx.y * a.ty;
+    double m_acc = 0.0, z1 = 0.0, z2 = 0.0;
+    const int64_t y_wall = a.st->y_wall, y_top = a.st->y_valid_top;
+    for (int c = 0; c < a.cpt; ++c) {
+        const int x = (blockIdx.x * NT + threadIdx.x) * a.cpt + c;
+        if (x >= a.L) break;
+        const int jend = min(j0 + a.ty, a.H);
+        for (int j = j0; j < jend; ++j) {
+            const int64_t y = y_wall + j;
+            if (y >= y_top) break;
+            const int r = (int)(y % a.H);
+            R v[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                v[i] = Codec<S>::dec(a.f[a.tl.at(i, r, x)], a.Wd[i]);
+            m_acc += (double)sum9(v);
+        }
+    }
+    block_sum3<NT>(m_acc, z1, z2);
+    if (threadIdx.x == 0) a.partials[4 * (blockIdx.y * gridDim.x + blockIdx.x)] = m_acc;
+}
+
+// ---------------------------------------------------------------------------
+// Small single-block kernels.
+// ---------------------------------------------------------------------------
+__global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_f64_kernel(double *p, int64_t n, double v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void state_set_kernel(DevState *st, int64_t y_wall, int64_t y_valid_top,
+                                 int64_t n_rows, int64_t h_hi)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->y_wall = y_wall;
+        st->y_valid_top = y_valid_top;
+        st->n_rows = n_rows;
+        st->h_hi = h_hi;
+        st->retired_total = 0.0;
+        st->retired_last = 0.0;
+        st->status = 0u;
+    }
+}
+
+constexpr int kRedThreads = 1024;
+
+// Deterministic reductions of one block of kRedThreads threads.
+__device__ __forceinline__ double block_sum_d(double v, double *sh)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[w];
+    return s;
+}
+
+__device__ __forceinline__ long long block_sum_i(long long v, long long *sh)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    long long s = 0;
+    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[w];
+    return s;
+}
+
+__device__ __forceinline__ long long block_max_i(long long v, long long *sh)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const long long o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    long long s = sh[0];
+    for (int w = 1; w < kRedThreads / 64; ++w) s = sh[w] > s ? sh[w] : s;
+    return s;
+}
+
+// hbar and w of Sec. III from integer sums relative to the wall row:
+// hbar = y_wall + S1 / L, w = sqrt(L S2 - S1^2) / L (exact sums, so the
+// result does not depend on the order of summation).
+__device__ __forceinline__ void height_stats(const int32_t *h, int L, int64_t y_wall,
+                                             long long *sh, double &hbar, double &W,
+                                             long long &hmax)
+{
+    long long s1 = 0, s2 = 0, mx = LLONG_MIN;
+    for (int x = threadIdx.x; x < L; x += kRedThreads) {
+        const long long d = (long long)h[x] - y_wall;
+        s1 += d;
+        s2 += d * d;
+        mx = (long long)h[x] > mx ? (long long)h[x] : mx;
+    }
+    const long long S1 = block_sum_i(s1, sh);
+    const long long S2 = block_sum_i(s2, sh);
+    hmax = block_max_i(mx, sh);
+    const long long num = (long long)L * S2 - S1 * S1;
+    hbar = (double)y_wall + (double)S1 / (double)L;
+    W = sqrt((double)num) / (double)L;
+}
+
+// Diagnostics of the current state.
+__global__ __launch_bounds__(kRedThreads) void diag_kernel(DiagArgs a)
+{
+    __shared__ double shd[kRedThreads / 64];
+    __shared__ long long shi[kRedThreads / 64];
+    double m = 0.0, s = 0.0, fx = 0.0;
+    for (int b = threadIdx.x; b < a.nblocks; b += kRedThreads) {
+        m += a.partials[4 * b + 0];
+        s += a.partials[4 * b + 1];
+        fx += a.partials[4 * b + 2];
+    }
+    m = block_sum_d(m, shd);
+    s = block_sum_d(s, shd);
+    fx = block_sum_d(fx, shd);
+    const int64_t y_wall = a.st->y_wall;
+    double hbar, W;
+    long long hmax;
+    height_stats(a.h_cur, a.L, y_wall, shi, hbar, W, hmax);
+    long long hi = LLONG_MIN;
+    for (int x = threadIdx.x; x < a.L; x += kRedThreads)
+        hi = (long long)a.colmax[x] > hi ? (long long)a.colmax[x] : hi;
+    hi = block_max_i(hi, shi);
+    if (threadIdx.x == 0) {
+        DiagOut *o = a.out;
+        const double mass = m - a.st->retired_last;
+        uint32_t st = a.st->status;
+        if (!isfinite(mass)) {
+            st |= kStNonFinite;
+            a.st->status = st;
+        }
+        o->mass = mass;
+        o->src_total = s;
+        o->fix_total = fx;
+        o->retired = a.st->retired_total;
+        o->hbar = hbar;
+        o->W = W;
+        o->y_wall = y_wall;
+        o->h_hi = hi;
+        o->status = st;
+    }
+}
+
+// Between steps when the device drives the window (rear wall that follows the
+// front, and/or the exact sweep window): wall rule of Appendix A, retired
+// mass, highest front so far, rows the next step must sweep, and the next
+// front-height slot reset to the wall row.
+template <class S>
+__global__ __launch_bounds__(kRedThreads) void finalize_kernel(FinalizeArgs<S> a)
+{
+    using R = typename Codec<S>::R;
+    __shared__ double shd[kRedThreads / 64];
+    __shared__ long long shi[kRedThreads / 64];
+    DevState *st = a.st;
+    const int64_t y_wall = st->y_wall;
+    const int64_t nrows_done = st->n_rows;
+    double hbar, W;
+    long long hmax;
+    height_stats(a.h_next, a.L, y_wall, shi, hbar, W, hmax);
+
+    int64_t k = 0;
+    if (a.follow) {
+        double gap = a.w_factor * W;
+        if (gap < (double)a.min_gap) gap = (double)a.min_gap;
+        const int64_t target = (int64_t)floor(hbar - gap);
+        if (target > y_wall) k = target - y_wall;
+        if (k > a.H - 1) k = a.H - 1;
+    }
+    double gone = 0.0;
+    if (k > 0) {
+        const int64_t n = k * (int64_t)a.L;
+        for (int64_t e = threadIdx.x; e < n; e += kRedThreads) {
+            const int64_t y = y_wall + e / a.L;
+            const int x = (int)(e % a.L);
+            const int r = (int)(y % a.H);
+            R v[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i)
+                v[i] = Codec<S>::dec(a.f[a.tl.at(i, r, x)], a.Wd[i]);
+            gone += (double)sum9(v);
+        }
+    }
+    gone = block_sum_d(gone, shd);
+    const int64_t y_new = y_wall + k;
+    // highest front so far and the rows the next step must sweep
+    long long cm = LLONG_MIN;
+    for (int x = threadIdx.x; x < a.L; x += kRedThreads)
+        cm = (long long)a.colmax[x] > cm ? (long long)a.colmax[x] : cm;
+    cm = block_max_i(cm, shi);
+    const long long hi = st->h_hi > cm ? st->h_hi : cm;
+    (void)hmax;
+    for (int x = threadIdx.x; x < a.L; x += kRedThreads) {
+        if (a.h_next[x] < y_new) a.h_next[x] = (int32_t)y_new;
+        a.h_clear[x] = (int32_t)y_new;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->retired_last = gone;
+        st->retired_total += gone;
+        st->y_valid_top = y_wall + nrows_done;
+        st->y_wall = y_new;
+        st->h_hi = hi;
+        int64_t nr = a.H;
+        if (a.window) {
+            nr = (int64_t)hi + 2 - y_new;
+            if (nr > a.H) nr = a.H;
+            if (nr < 1) nr = 1;
+        }
+        st->n_rows = nr;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (host side)
+// ---------------------------------------------------------------------------
+template <class S, int RB>
+void launch_step_rb(const StepArgs<S> &a, dim3 grid, int nt, hipStream_t s)
+{
+    if (nt == 256) hipLaunchKernelGGL((step_kernel<S, 256, RB>), grid, dim3(256), 0, s, a);
+    else if (nt == 128) hipLaunchKernelGGL((step_kernel<S, 128, RB>), grid, dim3(128), 0, s, a);
+    else hipLaunchKernelGGL((step_kernel<S, 64, RB>), grid, dim3(64), 0, s, a);
+}
+
+template <class S, int ND, int WPE>
+void launch_vec_nt(const StepArgs<S> &a, dim3 grid, int nt, hipStream_t s)
+{
+    if (nt == 256) hipLaunchKernelGGL((step_kernel_vec<S, 256, ND, WPE>), grid, dim3(256), 0, s, a);
+    else if (nt == 128) hipLaunchKernelGGL((step_kernel_vec<S, 128, ND, WPE>), grid, dim3(128), 0, s, a);
+    else hipLaunchKernelGGL((step_kernel_vec<S, 64, ND, WPE>), grid, dim3(64), 0, s, a);
+}
+
+// vb: bytes per lane (8 or 16); wpe: waves per SIMD to fit (1 = no bound).
+template <class S>
+hipError_t launch_step_vec(const StepArgs<S> &a, dim3 grid, int nt, int vb, int wpe, hipStream_t s)
+{
+    if (vb == 4) {
+        if constexpr (sizeof(S) <= 4) launch_vec_nt<S, 1, 1>(a, grid, nt, s);
+        else return hipErrorInvalidValue;
+    } else if (vb == 16) {
+        if (wpe >= 4) launch_vec_nt<S, 4, 4>(a, grid, nt, s);
+        else launch_vec_nt<S, 4, 1>(a, grid, nt, s);
+    } else {
+        if (wpe >= 4) launch_vec_nt<S, 2, 4>(a, grid, nt, s);
+        else launch_vec_nt<S, 2, 1>(a, grid, nt, s);
+    }
+    return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_step(const StepArgs<S> &a, dim3 grid, int nt, int rb, hipStream_t s)
+{
+    if (rb >= 4) launch_step_rb<S, 4>(a, grid, nt, s);
+    else if (rb == 2) launch_step_rb<S, 2>(a, grid, nt, s);
+    else launch_step_rb<S, 1>(a, grid, nt, s);
+    return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_init(const InitArgs<S> &a, dim3 grid, int nt, hipStream_t s)
+{
+    if (nt == 256) hipLaunchKernelGGL((init_kernel<S, 256>), grid, dim3(256), 0, s, a);
+    else if (nt == 128) hipLaunchKernelGGL((init_kernel<S, 128>), grid, dim3(128), 0, s, a);
+    else hipLaunchKernelGGL((init_kernel<S, 64>), grid, dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_mass(const MassArgs<S> &a, dim3 grid, int nt, hipStream_t s)
+{
+    if (nt == 256) hipLaunchKernelGGL((mass_kernel<S, 256>), grid, dim3(256), 0, s, a);
+    else if (nt == 128) hipLaunchKernelGGL((mass_kernel<S, 128>), grid, dim3(128), 0, s, a);
+    else hipLaunchKernelGGL((mass_kernel<S, 64>), grid, dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_finalize(const FinalizeArgs<S> &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((finalize_kernel<S>), dim3(1), dim3(kRedThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(const DiagArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(diag_kernel, dim3(1), dim3(kRedThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_set(DevState *st, int64_t y_wall, int64_t y_valid_top, int64_t n_rows,
+                            int64_t h_hi, hipStream_t s)
+{
+    hipLaunchKernelGGL(state_set_kernel, dim3(1), dim3(64), 0, s, st, y_wall, y_valid_top,
+                       n_rows, h_hi);
+    return hipGetLastError();
+}
+
+#define LBM_INSTANTIATE(S)                                                              \
+    template hipError_t launch_step<S>(const StepArgs<S> &, dim3, int, int, hipStream_t);    \
+    template hipError_t launch_step_vec<S>(const StepArgs<S> &, dim3, int, int, int, hipStream_t);    \
+    template hipError_t launch_init<S>(const InitArgs<S> &, dim3, int, hipStream_t);    \
+    template hipError_t launch_mass<S>(const MassArgs<S> &, dim3, int, hipStream_t);    \
+    template hipError_t launch_finalize<S>(const FinalizeArgs<S> &, hipStream_t);
+
+LBM_INSTANTIATE(double)
+LBM_INSTANTIATE(float)
+LBM_INSTANTIATE(__half)
+LBM_INSTANTIATE(__hip_bfloat16)
+
+}  // namespace lbm

@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports
+every entry point include/lbmgrow.h declares, lays out its structs as the
+header does, and validates parameters before touching the device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import synth_inputs as si
+from paper_2303_02210_amd import _ffi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbmgrow.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _ffi.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(_ffi.ENTRY_POINTS) == declared
+    out = subprocess.run(["nm", "-D", "--defined-only", _ffi.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (lbm_[a-z_0-9]+)", out))
+    assert set(declared) <= exported
+
+
+def test_struct_layout_matches_header(tmp_path):
+    # compile a probe against the header and compare every offset with ctypes
+    fields = [f for f, _ in _ffi.Params._fields_]
+    dfields = [f for f, _ in _ffi.Diag._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbmgrow.h"', 'int main(void){',
+           'printf("%zu %zu\\n", sizeof(lbm_params), sizeof(lbm_diag));']
+    for f in fields:
+        src.append(f'printf("P {f} %zu\\n", offsetof(lbm_params, {f}));')
+    for f in dfields:
+        src.append(f'printf("D {f} %zu\\n", offsetof(lbm_diag, {f}));')
+    src.append("return 0;}")
+    c = tmp_path / "probe.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    sp, sd = (int(v) for v in lines[0].split())
+    assert sp == ctypes.sizeof(_ffi.Params) and sd == ctypes.sizeof(_ffi.Diag)
+    for line in lines[1:]:
+        if not line:
+            continue
+        kind, name, off = line.split()
+        cls = _ffi.Params if kind == "P" else _ffi.Diag
+        assert getattr(cls, name).offset == int(off), name
+
+
+def test_version_string():
+    assert b"gfx950" in _ffi.lib().lbm_version()
+
+
+def _ws(cfg):
+    p = _ffi.make_params(cfg)
+    return int(_ffi.lib().lbm_workspace_bytes(ctypes.byref(p)))
+
+
+def test_workspace_bytes_scales_with_precision():
+    base = dict(si.BULK_4096_FP32)
+    n = {pr: _ws(dict(base, precision=pr)) for pr in ("fp64", "fp32", "fp16", "bf16")}
+    pops = 2 * 9 * 4096 * 4096
+    for pr, b in (("fp64", 8), ("fp32", 4), ("fp16", 2), ("bf16", 2)):
+        assert pops * b <= n[pr] < pops * b + 4 * 2 ** 20
+    assert n["fp16"] == n["bf16"]
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau=0.5), dict(tau=float("nan")), dict(rho_c=0.0), dict(L=1), dict(H=3),
+    dict(sigma=-1.0), dict(growth_rate=-1e-3), dict(init_rows=65), dict(mu=1.5),
+    dict(init_amp=1.0), dict(region_width=-1), dict(precision="fp64", window=True, ybc="periodic"),
+])
+def test_invalid_parameters_rejected_on_host(bad):
+    c = dict(si.SMALL_FP64)
+    c.update(bad)
+    assert _ws(c) == 0
+    p = _ffi.make_params(c)
+    h = ctypes.c_void_p()
+    rc = _ffi.lib().lbm_create(ctypes.byref(p), ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(h))
+    assert rc == _ffi.E_INVALID and not h.value
+
+
+def test_abi_version_and_size_checked():
+    p = _ffi.make_params(si.SMALL_FP64)
+    p.abi_version = 99
+    assert _ffi.lib().lbm_workspace_bytes(ctypes.byref(p)) == 0
+    p = _ffi.make_params(si.SMALL_FP64)
+    p.struct_size = 8
+    assert _ffi.lib().lbm_workspace_bytes(ctypes.byref(p)) == 0
+
+
+def test_create_rejects_bad_workspace_before_device_work():
+    p = _ffi.make_params(si.SMALL_FP64)
+    n = _ffi.lib().lbm_workspace_bytes(ctypes.byref(p))
+    h = ctypes.c_void_p()
+    L = _ffi.lib()
+    assert L.lbm_create(ctypes.byref(p), None, n, None, ctypes.byref(h)) == _ffi.E_INVALID
+    assert L.lbm_create(ctypes.byref(p), ctypes.c_void_p(4096 + 8), n, None,
+                        ctypes.byref(h)) == _ffi.E_INVALID          # not 256-byte aligned
+    assert L.lbm_create(ctypes.byref(p), ctypes.c_void_p(4096), n - 1, None,
+                        ctypes.byref(h)) == _ffi.E_NOMEM
+    assert L.lbm_step(None, 1) == _ffi.E_INVALID
+    assert L.lbm_destroy(None) == _ffi.E_INVALID
