@@ -34,7 +34,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("lbm_kernels.hip", "lbm_device.hpp", "lbm_internal.hpp"):
+    for f in ("lbm_step.hpp", "lbm_device.hpp", "lbm_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2303_02210_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -120,6 +120,11 @@ typedef enum {
  *                 type, so that an empty site decodes to exactly 0.
  *   seed, replica Philox4x32-10 key words of all random draws.
  *   flags         LBM_FLAG_* bits.
+ *   kernel_vb, kernel_ty
+ *                 launch shape (results do not depend on it): 0 = library
+ *                 default; kernel_vb 1 = one column per lane, 4 / 8 / 16 =
+ *                 that many bytes of columns per lane (used when the width
+ *                 splits evenly); kernel_ty = rows per thread (1..64).
  */
 typedef struct {
     uint32_t abi_version;
@@ -140,6 +145,8 @@ typedef struct {
     double   wall_w_factor;
     double   rho_ref;
     uint32_t seed, replica;
+    int32_t  kernel_vb;
+    int32_t  kernel_ty;
 } lbm_params;
 
 /* Diagnostics after the last enqueued step (all reductions in float64). */
@@ -218,17 +225,31 @@ const char *lbm_last_error(const lbm_handle *h);
 int lbm_destroy(lbm_handle *h);
 
 /*
- * Batches: many handles of any size and precision advanced together, one
- * kernel launch per precision per step over a flattened table of tiles, so
- * that small lattices share the GPU.  Every handle keeps its own workspace,
- * state and status; results are bit for bit those of lbm_step on the
- * handle alone.  All handles must use the batch's stream.
- *   lbm_batch_create     empty batch on hip_stream.
- *   lbm_batch_add/remove membership changes (take effect at the next step).
- *   lbm_batch_step       nsteps steps of every member.  Does not synchronize.
- *   lbm_batch_destroy    releases the batch, not its handles.
+ * Batches: many handles of any size and precision advanced together.  Per
+ * step there is one kernel launch per group of members sharing a storage
+ * type and kernel form, over the flattened table of all their tiles (plus,
+ * when any member follows the front or sweeps a window, one launch of the
+ * between-step bookkeeping for all of them); a run of K steps is captured in
+ * a HIP graph and replayed while the membership stays the same.  Every
+ * member keeps its own workspace, state and status, and its populations come
+ * out bit for bit as with lbm_step on the handle alone.
+ *   lbm_batch_workspace_bytes  device workspace for up to max_members.
+ *   lbm_batch_create     empty batch in dev_ws (256-byte aligned, caller
+ *                        owned, valid until lbm_batch_destroy) on hip_stream;
+ *                        members must use the same stream.
+ *   lbm_batch_add/remove membership changes (take effect at the next step);
+ *                        a handle belongs to at most one batch, and
+ *                        lbm_destroy removes it from its batch.
+ *   lbm_batch_step       nsteps >= 0 steps of every member; does not
+ *                        synchronize; LBM_E_STATE if a member is in an error
+ *                        state (remove it and step again).
+ *   lbm_batch_destroy    releases the batch, not its members.
+ * Errors: LBM_E_INVALID (null/foreign handles, stream mismatch, full batch),
+ * LBM_E_NOMEM (workspace too small), LBM_E_DEVICE.
  */
-int lbm_batch_create(void *hip_stream, lbm_batch **out);
+size_t lbm_batch_workspace_bytes(int max_members);
+int lbm_batch_create(void *dev_ws, size_t ws_bytes, int max_members, void *hip_stream,
+                     lbm_batch **out);
 int lbm_batch_add(lbm_batch *b, lbm_handle *h);
 int lbm_batch_remove(lbm_batch *b, lbm_handle *h);
 int lbm_batch_step(lbm_batch *b, int64_t nsteps);

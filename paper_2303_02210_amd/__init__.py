@@ -6,5 +6,6 @@ PyTorch for device memory and streams only.
 """
 from ._ffi import LbmError, lib, make_params  # noqa: F401
 from .sim import Sim  # noqa: F401
+from .ensemble import Ensemble  # noqa: F401
 
-__all__ = ["Sim", "LbmError", "lib", "make_params"]
+__all__ = ["Sim", "Ensemble", "LbmError", "lib", "make_params"]

@@ -45,6 +45,7 @@ class Params(ctypes.Structure):
         ("wall_min_gap", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("wall_w_factor", ctypes.c_double), ("rho_ref", ctypes.c_double),
         ("seed", ctypes.c_uint32), ("replica", ctypes.c_uint32),
+        ("kernel_vb", ctypes.c_int32), ("kernel_ty", ctypes.c_int32),
     ]
 
 
@@ -77,7 +78,9 @@ _SIGS = [
     ("lbm_set_state", ctypes.c_int, [_VP, _VP, ctypes.c_size_t]),
     ("lbm_last_error", ctypes.c_char_p, [_VP]),
     ("lbm_destroy", ctypes.c_int, [_VP]),
-    ("lbm_batch_create", ctypes.c_int, [_VP, ctypes.POINTER(_VP)]),
+    ("lbm_batch_workspace_bytes", ctypes.c_size_t, [ctypes.c_int]),
+    ("lbm_batch_create", ctypes.c_int, [_VP, ctypes.c_size_t, ctypes.c_int, _VP,
+                                        ctypes.POINTER(_VP)]),
     ("lbm_batch_add", ctypes.c_int, [_VP, _VP]),
     ("lbm_batch_remove", ctypes.c_int, [_VP, _VP]),
     ("lbm_batch_step", ctypes.c_int, [_VP, ctypes.c_int64]),
@@ -131,6 +134,8 @@ def make_params(cfg: dict) -> Params:
     p.seed = int(cfg.get("seed", 0)) & 0xFFFFFFFF
     p.replica = int(cfg.get("replica", 0)) & 0xFFFFFFFF
     p.flags = FLAG_WINDOW if cfg.get("window", False) else 0
+    p.kernel_vb = int(cfg.get("kernel_vb", 0))
+    p.kernel_ty = int(cfg.get("kernel_ty", 0))
     return p
 
 

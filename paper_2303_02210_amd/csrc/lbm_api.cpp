@@ -110,11 +110,11 @@ struct Layout {
     size_t fbytes = 0;
     size_t off_f[2] = {0, 0};
     size_t off_h[3] = {0, 0, 0};
-    size_t off_colmax = 0, off_partials = 0, off_state = 0, off_diag = 0;
+    size_t off_colmax = 0, off_partials = 0, off_state = 0, off_diag = 0, off_rep = 0;
     size_t total = 0;
     int nt = 256, ty = 16, gx = 1, gy = 1, nblocks = 1, rb = 2;
     bool vec = false;   // vector kernel: vb bytes (cpt columns) per thread
-    int cpt = 1, vb = 16, wpe = 4;
+    int cpt = 1, vb = 16;
 };
 
 bool params_ok(const lbm_params *p, std::string *why)
@@ -144,6 +144,10 @@ bool params_ok(const lbm_params *p, std::string *why)
     if (p->ybc == LBM_Y_WALL_FOLLOW && (p->wall_min_gap < 0 || !(p->wall_w_factor >= 0.0)))
         return bad("bad wall follow parameters");
     if ((p->flags & ~LBM_FLAG_WINDOW) != 0) return bad("unknown flags");
+    if (!(p->kernel_vb == 0 || p->kernel_vb == 1 || p->kernel_vb == 4 || p->kernel_vb == 8 ||
+          p->kernel_vb == 16))
+        return bad("kernel_vb must be 0, 1, 4, 8 or 16");
+    if (p->kernel_ty < 0 || p->kernel_ty > 64) return bad("kernel_ty must be in [0, 64]");
     if ((p->flags & LBM_FLAG_WINDOW) && p->ybc == LBM_Y_PERIODIC)
         return bad("the sweep window needs a rear wall");
     if ((p->precision == LBM_FP16_OFFSET || p->precision == LBM_BF16_OFFSET) &&
@@ -152,12 +156,9 @@ bool params_ok(const lbm_params *p, std::string *why)
     return true;
 }
 
-int pick_ty(int gx, int H, int pref)
+int pick_ty(int gx, int H, int pref, bool forced)
 {
-    if (const char *e = std::getenv("LBMGROW_TY")) {
-        const int v = std::atoi(e);
-        if (v >= 1 && v <= 256) return v;
-    }
+    if (forced) return pref;
     // rows per thread: the preferred count, fewer if that would leave the
     // device with under 2048 blocks (8 per CU)
     int t = pref;
@@ -173,10 +174,6 @@ Layout make_layout(const lbm_params *p)
     // rounded up to 64 (no padding beyond that)
     const int64_t l64 = (int64_t)align_up((size_t)p->L, 64);
     int tws = (l64 % 256 == 0) ? 8 : ((l64 % 128 == 0) ? 7 : 6);
-    if (const char *e = std::getenv("LBMGROW_TW")) {
-        const int v = std::atoi(e);
-        if (v == 64 || v == 128 || v == 256) tws = v == 64 ? 6 : (v == 128 ? 7 : 8);
-    }
     l.lp = (int64_t)align_up((size_t)p->L, (size_t)1 << tws);
     l.tl.tws = tws;
     l.tl.rs = 9 * l.lp;
@@ -186,25 +183,21 @@ Layout make_layout(const lbm_params *p)
     // and rows per thread as measured best on MI355X for a 4096 x 4096
     // lattice: float64 16 B / 1 row, float32 4 B / 2 rows, 16-bit 8 B / 4 rows
     l.vb = l.esize == 8 ? 16 : (l.esize == 4 ? 4 : 8);
-    const int ty_pref = l.esize == 8 ? 1 : (l.esize == 4 ? 2 : 4);
-    if (const char *e = std::getenv("LBMGROW_VB")) {
-        const int v = std::atoi(e);
-        l.vb = (v == 4 || v == 8) ? v : 16;
-    }
+    int ty_pref = l.esize == 8 ? 1 : (l.esize == 4 ? 2 : 4);
+    bool scalar = false;
+    if (p->kernel_vb == 1) scalar = true;                 // one column per lane
+    else if (p->kernel_vb > 1) l.vb = p->kernel_vb;       // 4, 8 or 16 bytes per lane
     if ((size_t)l.vb < l.esize) l.vb = (int)l.esize;
-    if (const char *e = std::getenv("LBMGROW_WPE")) l.wpe = std::atoi(e);
+    if (p->kernel_ty > 0) ty_pref = p->kernel_ty;
     const int V = (int)(l.vb / l.esize);
-    l.vec = (p->L % V) == 0;
-    if (const char *e = std::getenv("LBMGROW_KERNEL"))
-        if (std::strcmp(e, "scalar") == 0) l.vec = false;
+    l.vec = !scalar && (p->L % V) == 0;
     l.cpt = l.vec ? V : 1;
     const int lanes = (p->L + l.cpt - 1) / l.cpt;
     l.nt = lanes <= 64 ? 64 : (lanes <= 128 ? 128 : 256);
     l.gx = (lanes + l.nt - 1) / l.nt;
-    l.ty = pick_ty(l.gx, p->H, l.vec ? ty_pref : 2);
+    l.ty = pick_ty(l.gx, p->H, l.vec || p->kernel_ty > 0 ? ty_pref : 2, p->kernel_ty > 0);
     l.gy = (p->H + l.ty - 1) / l.ty;
     l.rb = 2;
-    if (const char *e = std::getenv("LBMGROW_RB")) l.rb = std::atoi(e);
     l.nblocks = l.gx * l.gy;
     size_t o = 0;
     l.off_f[0] = o; o += l.fbytes;
@@ -215,6 +208,7 @@ Layout make_layout(const lbm_params *p)
     l.off_partials = o; o += align_up((size_t)l.nblocks * 4 * 8, kAlign);
     l.off_state = o; o += align_up(sizeof(DevState), kAlign);
     l.off_diag = o; o += align_up(sizeof(DiagOut), kAlign);
+    l.off_rep = o; o += align_up(sizeof(BatchRep<double>), kAlign);
     l.total = o;
     return l;
 }
@@ -234,6 +228,10 @@ struct lbm_handle {
     int err = LBM_OK;
     std::string msg = "no error";
     double Wd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    lbm_batch *batch = nullptr;     // batch this handle belongs to
+    bool rep_ok = false;            // device descriptor matches (rep_t0, rep_cur0)
+    int64_t rep_t0 = 0;
+    int rep_cur0 = 0;
 
     template <class T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -306,12 +304,12 @@ int do_init(lbm_handle *h)
 }
 
 template <class S>
-int do_step(lbm_handle *h, int64_t n)
+void fill_step_args(const lbm_handle *h, StepArgs<S> &a)
 {
     using R = typename Real<S>::type;
     const lbm_params &p = h->p;
     const Layout &l = h->lay;
-    StepArgs<S> a{};
+    a = StepArgs<S>{};
     a.partials = h->partials();
     a.colmax = h->colmax();
     a.st = h->st();
@@ -335,17 +333,34 @@ int do_step(lbm_handle *h, int64_t n)
         a.w[i] = (R)kW[i];
         a.Wd[i] = (R)h->Wd[i];
     }
-    FinalizeArgs<S> fa{};
+}
+
+template <class S>
+void fill_finalize_args(const lbm_handle *h, FinalizeArgs<S> &fa)
+{
+    using R = typename Real<S>::type;
+    const lbm_params &p = h->p;
+    fa = FinalizeArgs<S>{};
     fa.st = h->st();
     fa.colmax = h->colmax();
     fa.L = p.L;
     fa.H = p.H;
-    fa.tl = l.tl;
+    fa.tl = h->lay.tl;
     fa.follow = p.ybc == LBM_Y_WALL_FOLLOW;
     fa.window = (p.flags & LBM_FLAG_WINDOW) != 0;
     fa.min_gap = p.wall_min_gap;
     fa.w_factor = p.wall_w_factor;
     for (int i = 0; i < 9; ++i) fa.Wd[i] = (R)h->Wd[i];
+}
+
+template <class S>
+int do_step(lbm_handle *h, int64_t n)
+{
+    const Layout &l = h->lay;
+    StepArgs<S> a;
+    fill_step_args<S>(h, a);
+    FinalizeArgs<S> fa;
+    fill_finalize_args<S>(h, fa);
 
     const dim3 grid(l.gx, l.gy);
     for (int64_t k = 0; k < n; ++k) {
@@ -355,7 +370,7 @@ int do_step(lbm_handle *h, int64_t n)
         a.h_next = h->hslot(h->t + 1);
         a.h_clear = h->device_driven ? nullptr : h->hslot(h->t + 2);
         a.t = (uint32_t)h->t;
-        int rc = h->hip(l.vec ? launch_step_vec<S>(a, grid, l.nt, l.vb, l.wpe, h->stream)
+        int rc = h->hip(l.vec ? launch_step_vec<S>(a, grid, l.nt, l.vb, h->stream)
                               : launch_step<S>(a, grid, l.nt, l.rb, h->stream),
                         "step kernel");
         if (rc) return rc;
@@ -767,23 +782,280 @@ const char *lbm_last_error(const lbm_handle *h)
 int lbm_destroy(lbm_handle *h)
 {
     if (!h) return LBM_E_INVALID;
+    if (h->batch) lbm_batch_remove(h->batch, h);
     delete h;
     return LBM_OK;
 }
 
 }  // extern "C"
 // ============================================================================
-// Batches (implemented in lbm_batch.cpp when built; these are the entry
-// points used until then)
+// Batches
 // ============================================================================
-extern "C" {
-int lbm_batch_create(void *, lbm_batch **out)
+namespace {
+
+constexpr int kMaxGroups = 16;
+
+struct BatchGroup {
+    int prec = 0, vec = 0, nt = 0, vbrb = 0;     // storage type and kernel form
+    std::vector<lbm_handle *> m;
+    int total = 0;                               // tiles over all members
+    int ndev = 0;                                // members finalized each step
+    void **reps = nullptr;                       // device: descriptor pointers
+    int32_t *offs = nullptr;                     // device: tile prefix sums
+};
+
+size_t batch_slot_bytes(int max_members)
 {
-    if (out) *out = nullptr;
-    return LBM_E_UNSUPPORTED;
+    return align_up((size_t)(max_members + 1) * 4, kAlign) +
+           align_up((size_t)max_members * sizeof(void *), kAlign);
 }
-int lbm_batch_add(lbm_batch *, lbm_handle *) { return LBM_E_UNSUPPORTED; }
-int lbm_batch_remove(lbm_batch *, lbm_handle *) { return LBM_E_UNSUPPORTED; }
-int lbm_batch_step(lbm_batch *, int64_t) { return LBM_E_UNSUPPORTED; }
-int lbm_batch_destroy(lbm_batch *) { return LBM_E_UNSUPPORTED; }
+
+template <class S>
+int write_rep(lbm_handle *h)
+{
+    BatchRep<S> r{};
+    fill_step_args<S>(h, r.a);
+    fill_finalize_args<S>(h, r.fa);
+    r.f[0] = reinterpret_cast<S *>(h->fbuf(0));
+    r.f[1] = reinterpret_cast<S *>(h->fbuf(1));
+    for (int k = 0; k < 3; ++k) r.hs[k] = h->at<int32_t>(h->lay.off_h[k]);
+    r.t0 = h->t;
+    r.cur0 = h->cur;
+    r.gx = h->lay.gx;
+    r.device_driven = h->device_driven ? 1 : 0;
+    int rc = h->hip(hipMemcpyAsync(h->ws + h->lay.off_rep, &r, sizeof r, hipMemcpyHostToDevice,
+                                   h->stream),
+                    "batch descriptor copy");
+    if (rc) return rc;
+    // the copy reads r: wait for it before r goes out of scope
+    rc = h->hip(hipStreamSynchronize(h->stream), "synchronize");
+    if (rc) return rc;
+    h->rep_ok = true;
+    h->rep_t0 = h->t;
+    h->rep_cur0 = h->cur;
+    return LBM_OK;
 }
+
+template <class S>
+hipError_t enqueue_group_step(const BatchGroup &g, int k, hipStream_t s)
+{
+    return launch_step_batch<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps), g.offs,
+                                (int)g.m.size(), g.total, g.vec, g.nt, g.vbrb, k, s);
+}
+template <class S>
+hipError_t enqueue_group_finalize(const BatchGroup &g, int k, hipStream_t s)
+{
+    return launch_finalize_batch<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps),
+                                    (int)g.m.size(), k, s);
+}
+template <class S>
+hipError_t enqueue_group_advance(const BatchGroup &g, int K, hipStream_t s)
+{
+    return launch_batch_advance<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps),
+                                   (int)g.m.size(), K, s);
+}
+
+#define LBM_DISPATCH_HIP(prec, fn, ...)                               \
+    ((prec) == LBM_FP64   ? fn<double>(__VA_ARGS__)                    \
+     : (prec) == LBM_FP32 ? fn<float>(__VA_ARGS__)                     \
+     : (prec) == LBM_FP16_OFFSET ? fn<__half>(__VA_ARGS__)             \
+                                 : fn<__hip_bfloat16>(__VA_ARGS__))
+
+}  // namespace
+
+struct lbm_batch {
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    int max_members = 0;
+    std::vector<lbm_handle *> members;
+    std::vector<BatchGroup> groups;
+    bool dirty = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int64_t graph_n = -1;
+
+    void drop_graph()
+    {
+        if (gexec) hipGraphExecDestroy(gexec);
+        if (graph) hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
+        graph_n = -1;
+    }
+
+    // Group members by storage type and kernel form; upload the tables.
+    int rebuild()
+    {
+        groups.clear();
+        for (lbm_handle *h : members) {
+            const int vbrb = h->lay.vec ? h->lay.vb : h->lay.rb;
+            BatchGroup *g = nullptr;
+            for (BatchGroup &c : groups)
+                if (c.prec == h->p.precision && c.vec == (int)h->lay.vec && c.nt == h->lay.nt &&
+                    c.vbrb == vbrb)
+                    g = &c;
+            if (!g) {
+                if ((int)groups.size() == kMaxGroups) return LBM_E_INVALID;
+                groups.emplace_back();
+                g = &groups.back();
+                g->prec = h->p.precision;
+                g->vec = h->lay.vec;
+                g->nt = h->lay.nt;
+                g->vbrb = vbrb;
+            }
+            g->m.push_back(h);
+        }
+        const size_t slot = batch_slot_bytes(max_members);
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            BatchGroup &g = groups[gi];
+            char *base = ws + gi * slot;
+            g.offs = reinterpret_cast<int32_t *>(base);
+            g.reps = reinterpret_cast<void **>(base + align_up((size_t)(max_members + 1) * 4, kAlign));
+            std::vector<int32_t> offs(g.m.size() + 1, 0);
+            std::vector<void *> reps(g.m.size());
+            int64_t tot = 0;
+            g.ndev = 0;
+            for (size_t i = 0; i < g.m.size(); ++i) {
+                offs[i] = (int32_t)tot;
+                tot += g.m[i]->lay.nblocks;
+                reps[i] = g.m[i]->ws + g.m[i]->lay.off_rep;
+                g.ndev += g.m[i]->device_driven ? 1 : 0;
+            }
+            if (tot > INT32_MAX) return LBM_E_INVALID;
+            offs[g.m.size()] = (int32_t)tot;
+            g.total = (int)tot;
+            if (hipMemcpyAsync(g.offs, offs.data(), offs.size() * 4, hipMemcpyHostToDevice, stream) !=
+                    hipSuccess ||
+                hipMemcpyAsync(g.reps, reps.data(), reps.size() * sizeof(void *),
+                               hipMemcpyHostToDevice, stream) != hipSuccess ||
+                hipStreamSynchronize(stream) != hipSuccess)
+                return LBM_E_DEVICE;
+        }
+        dirty = false;
+        drop_graph();
+        return LBM_OK;
+    }
+
+    hipError_t enqueue(int64_t n)
+    {
+        hipError_t e = hipSuccess;
+        for (int64_t k = 0; k < n && e == hipSuccess; ++k) {
+            for (const BatchGroup &g : groups) {
+                e = LBM_DISPATCH_HIP(g.prec, enqueue_group_step, g, (int)k, stream);
+                if (e != hipSuccess) return e;
+            }
+            for (const BatchGroup &g : groups) {
+                if (g.ndev == 0) continue;
+                e = LBM_DISPATCH_HIP(g.prec, enqueue_group_finalize, g, (int)k, stream);
+                if (e != hipSuccess) return e;
+            }
+        }
+        for (const BatchGroup &g : groups) {
+            e = LBM_DISPATCH_HIP(g.prec, enqueue_group_advance, g, (int)n, stream);
+            if (e != hipSuccess) return e;
+        }
+        return e;
+    }
+};
+
+extern "C" {
+
+size_t lbm_batch_workspace_bytes(int max_members)
+{
+    if (max_members < 1) return 0;
+    return kMaxGroups * batch_slot_bytes(max_members);
+}
+
+int lbm_batch_create(void *dev_ws, size_t ws_bytes, int max_members, void *hip_stream,
+                     lbm_batch **out)
+{
+    if (!out) return LBM_E_INVALID;
+    *out = nullptr;
+    if (!dev_ws || max_members < 1 || (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) != 0)
+        return LBM_E_INVALID;
+    if (ws_bytes < lbm_batch_workspace_bytes(max_members)) return LBM_E_NOMEM;
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return LBM_E_NOMEM;
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->ws = reinterpret_cast<char *>(dev_ws);
+    b->ws_bytes = ws_bytes;
+    b->max_members = max_members;
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_add(lbm_batch *b, lbm_handle *h)
+{
+    if (!b || !h || h->batch || h->stream != b->stream) return LBM_E_INVALID;
+    if ((int)b->members.size() >= b->max_members) return LBM_E_INVALID;
+    b->members.push_back(h);
+    h->batch = b;
+    h->rep_ok = false;
+    b->dirty = true;
+    return LBM_OK;
+}
+
+int lbm_batch_remove(lbm_batch *b, lbm_handle *h)
+{
+    if (!b || !h || h->batch != b) return LBM_E_INVALID;
+    b->members.erase(std::find(b->members.begin(), b->members.end(), h));
+    h->batch = nullptr;
+    b->dirty = true;
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch *b, int64_t nsteps)
+{
+    if (!b || nsteps < 0 || nsteps > INT32_MAX) return LBM_E_INVALID;
+    if (nsteps == 0 || b->members.empty()) return LBM_OK;
+    for (lbm_handle *h : b->members)
+        if (h->err != LBM_OK) return LBM_E_STATE;
+    int rc;
+    if (b->dirty && (rc = b->rebuild())) return rc;
+    // descriptors of members stepped on their own (or new) since the last run
+    for (lbm_handle *h : b->members)
+        if (!h->rep_ok || h->rep_t0 != h->t || h->rep_cur0 != h->cur)
+            if ((rc = LBM_DISPATCH(h->p.precision, write_rep, h))) return rc;
+    if (b->graph_n != nsteps) {
+        b->drop_graph();
+        // capture the run; streams that cannot be captured (the null stream)
+        // get the same launches directly
+        if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            const hipError_t e = b->enqueue(nsteps);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+            if (e == hipSuccess && e2 == hipSuccess && g &&
+                hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) == hipSuccess) {
+                b->graph = g;
+                b->graph_n = nsteps;
+            } else {
+                if (g) hipGraphDestroy(g);
+                b->gexec = nullptr;
+                (void)hipGetLastError();
+            }
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    hipError_t e = b->gexec ? hipGraphLaunch(b->gexec, b->stream) : b->enqueue(nsteps);
+    if (e != hipSuccess) return LBM_E_DEVICE;
+    for (lbm_handle *h : b->members) {
+        h->t += nsteps;
+        h->cur ^= (int)(nsteps & 1);
+        h->rep_t0 += nsteps;
+        h->rep_cur0 = (int)((h->rep_cur0 + nsteps) & 1);
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch *b)
+{
+    if (!b) return LBM_E_INVALID;
+    for (lbm_handle *h : b->members) h->batch = nullptr;
+    b->drop_graph();
+    delete b;
+    return LBM_OK;
+}
+
+}  // extern "C"

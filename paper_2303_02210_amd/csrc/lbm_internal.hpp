@@ -136,10 +136,35 @@ struct DiagArgs {
     DiagOut *out;
 };
 
+// One member of a batch: its static step and finalize parameters plus what
+// the per-step fields are derived from.  Lives in the member's workspace.
+template <class S>
+struct BatchRep {
+    StepArgs<S> a;          // per-step fields (fin, fout, h_*, t) unused
+    FinalizeArgs<S> fa;     // per-step fields (f, h_next, h_clear) unused
+    S *f[2];                // the two population buffers
+    int32_t *hs[3];         // the three front-height slots
+    int64_t t0;             // steps taken when the current batch run started
+    int32_t cur0;           // buffer holding the state at that point
+    int32_t gx;             // tiles along x
+    int32_t device_driven;  // follow wall / sweep window: finalize each step
+    int32_t pad;
+};
+
 template <class S>
 hipError_t launch_step(const StepArgs<S> &a, dim3 grid, int nt, int rb, hipStream_t s);
+// A batch group: n members with the same storage type and kernel form.
+// reps: device array of member descriptors; offs: device prefix sums of
+// their tile counts (offs[n] = total tiles).
 template <class S>
-hipError_t launch_step_vec(const StepArgs<S> &a, dim3 grid, int nt, int vb, int wpe, hipStream_t s);
+hipError_t launch_step_batch(BatchRep<S> *const *reps, const int32_t *offs, int n, int total,
+                             int vec, int nt, int vb_or_rb, int k, hipStream_t s);
+template <class S>
+hipError_t launch_finalize_batch(BatchRep<S> *const *reps, int n, int k, hipStream_t s);
+template <class S>
+hipError_t launch_batch_advance(BatchRep<S> *const *reps, int n, int K, hipStream_t s);
+template <class S>
+hipError_t launch_step_vec(const StepArgs<S> &a, dim3 grid, int nt, int vb, hipStream_t s);
 template <class S>
 hipError_t launch_init(const InitArgs<S> &a, dim3 grid, int nt, hipStream_t s);
 template <class S>

@@ -1,4 +1,4 @@
-// lbm_kernels.hip -- gfx950 kernels of the growing-tissue D2Q9 lattice
+// lbm_step.hpp -- gfx950 kernels of the growing-tissue D2Q9 lattice
 // Boltzmann library.
 //
 // One fused kernel advances the whole lattice by one step (the paper's
@@ -15,8 +15,10 @@
 // The arithmetic follows one fixed order with no contraction (this file is
 // compiled with -ffp-contract=off), so the float64 instantiation reproduces a
 // plain sequential float64 evaluation of the same formulas bit for bit.
+#pragma once
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
+#include <climits>
 
 namespace lbm {
 
@@ -75,7 +77,7 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c)
 // and the mass change of the negative-population fix.
 // ---------------------------------------------------------------------------
 template <class S>
-__device__ __forceinline__ void tissue_update(const StepArgs<S> &a, typename Codec<S>::R fs[9],
+__device__ __forceinline__ void tissue_update(const StepArgs<S> &a, uint32_t t, typename Codec<S>::R fs[9],
                                               typename Codec<S>::R rho_s,
                                               typename Codec<S>::R out[9], uint32_t x, int64_t y,
                                               int64_t y_wall, int32_t hp, double &s_acc,
@@ -123,7 +125,7 @@ __device__ __forceinline__ void tissue_update(const StepArgs<S> &a, typename Cod
     // ---- step 6: zero-sum noise where rho > rho_c (Eq. 4) ----------------------
     if (a.noise && rho > a.rho_c) {
         R v[9];
-        noise_factors<R>(a.seed, a.replica, a.t, x, (uint32_t)y, v);
+        noise_factors<R>(a.seed, a.replica, t, x, (uint32_t)y, v);
         R eta[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) eta[i] = a.sigma * v[i];
@@ -164,7 +166,7 @@ __device__ __forceinline__ void tissue_update(const StepArgs<S> &a, typename Cod
 // step 5 only reverses directions, so it forwards the stored values as they
 // are.  Writes the stored result to so[9]; returns true for tissue.
 template <class S>
-__device__ __forceinline__ bool site_step(const StepArgs<S> &a, const S v[9],
+__device__ __forceinline__ bool site_step(const StepArgs<S> &a, uint32_t t, const S v[9],
                                           typename Codec<S>::R fs[9], const typename Codec<S>::R Wd[9],
                                           S so[9], uint32_t x, int64_t y, int64_t y_wall, int32_t hp,
                                           double &m_acc, double &s_acc, double &x_acc)
@@ -174,7 +176,7 @@ __device__ __forceinline__ bool site_step(const StepArgs<S> &a, const S v[9],
     const R rho_s = sum9(fs);
     if (rho_s >= a.rho_c) {
         R out[9];
-        tissue_update<S>(a, fs, rho_s, out, x, y, y_wall, hp, s_acc, x_acc);
+        tissue_update<S>(a, t, fs, rho_s, out, x, y, y_wall, hp, s_acc, x_acc);
         R kept[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -227,15 +229,30 @@ __device__ __forceinline__ RowSrc row_sources(int mode, int j, int r0, int H, in
 // works on one contiguous part of the lattice, keeping the cache lines that
 // neighbouring blocks share in one L2.
 // ---------------------------------------------------------------------------
+// Block-to-tile order: dispatch goes round-robin over the 8 XCDs, so block
+// `lin` is renumbered to give each XCD one contiguous run of tiles.
+__device__ __forceinline__ int xcd_order(int lin, int nb)
+{
+    return ((nb & 7) == 0) ? (lin & 7) * (nb >> 3) + (lin >> 3) : lin;
+}
+
+// Per-step inputs of one tile: the buffers and front-height slots of this
+// step and the step counter.
+template <class S>
+struct StepIO {
+    const S *fin;
+    S *fout;
+    const int32_t *h_prev;
+    int32_t *h_next;
+    int32_t *h_clear;
+    uint32_t t;
+};
+
 template <class S, int NT, int RB>
-__global__ __launch_bounds__(NT) void step_kernel(StepArgs<S> a)
+__device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const StepIO<S> &io, int bx,
+                                                 int by, int nbx)
 {
     using R = typename Codec<S>::R;
-    const int nbx = gridDim.x;
-    const int nb = nbx * gridDim.y;
-    int lin = blockIdx.y * nbx + blockIdx.x;
-    if ((nb & 7) == 0) lin = (lin & 7) * (nb >> 3) + (lin >> 3);
-    const int bx = lin % nbx, by = lin / nbx;
 
     const int L = a.L, H = a.H;
     const int xr = bx * NT + threadIdx.x;
@@ -255,7 +272,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs<S> a)
 
     double m_acc = 0.0, s_acc = 0.0, x_acc = 0.0;
     int64_t ymax = -1;
-    const int32_t hp = (a.region == kRegionFrontBand) ? a.h_prev[x] : 0;
+    const int32_t hp = (a.region == kRegionFrontBand) ? io.h_prev[x] : 0;
     R Wd[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Wd[i] = a.Wd[i];
@@ -263,8 +280,8 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs<S> a)
     const Tiles tl = a.tl;
     const int64_t cx = tl.col(x), cxm = tl.col(xm), cxp = tl.col(xp);
     const int tws = tl.tws;
-    const S *__restrict__ F = a.fin;
-    S *__restrict__ G = a.fout;
+    const S *__restrict__ F = io.fin;
+    S *__restrict__ G = io.fout;
     int rnext = (a.mode == kModeDevice) ? (int)((y_wall + j0) % H) : j0;
 
     for (int jb = j0; jb < jend; jb += RB) {
@@ -327,7 +344,7 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs<S> a)
             S so[9];
             double m_site = 0.0, s_site = 0.0, x_site = 0.0;
             const bool tissue =
-                site_step<S>(a, v, fs, Wd, so, x, y, y_wall, hp, m_site, s_site, x_site);
+                site_step<S>(a, io.t, v, fs, Wd, so, x, y, y_wall, hp, m_site, s_site, x_site);
             S *rowg = G + (int64_t)s.r0 * tl.rs + cx;
             if (active) {
 #pragma unroll
@@ -347,10 +364,10 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs<S> a)
     if (active) {
         if (ymax >= 0) {
             const int32_t hv = (int32_t)(ymax + 1);
-            atomicMax(a.h_next + x, hv);
+            atomicMax(io.h_next + x, hv);
             atomicMax(a.colmax + x, hv);
         }
-        if (a.h_clear && by == 0) a.h_clear[x] = 0;
+        if (io.h_clear && by == 0) io.h_clear[x] = 0;
     }
 
     // ---- per-block tallies (fixed order: deterministic) ------------------------
@@ -361,6 +378,15 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs<S> a)
         p[1] += s_acc;
         p[2] += x_acc;
     }
+}
+
+template <class S, int NT, int RB>
+__global__ __launch_bounds__(NT) void step_kernel(StepArgs<S> a)
+{
+    const int nbx = gridDim.x;
+    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y);
+    const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
+    step_scalar_tile<S, NT, RB>(a, io, lin % nbx, lin / nbx, nbx);
 }
 
 // ---------------------------------------------------------------------------
@@ -455,18 +481,13 @@ __device__ __forceinline__ S from_right(const typename RawVec<ND>::type &own, S 
 }
 
 // ND dwords per lane; WPE: waves per SIMD the register allocation aims for.
-template <class S, int NT, int ND, int WPE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
-void step_kernel_vec(StepArgs<S> a)
+template <class S, int NT, int ND>
+__device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO<S> &io, int bx,
+                                              int by, int nbx)
 {
     using R = typename Codec<S>::R;
     using VT = typename RawVec<ND>::type;
     constexpr int V = ND * 4 / (int)sizeof(S);
-    const int nbx = gridDim.x;
-    const int nb = nbx * gridDim.y;
-    int lin = blockIdx.y * nbx + blockIdx.x;
-    if ((nb & 7) == 0) lin = (lin & 7) * (nb >> 3) + (lin >> 3);
-    const int bx = lin % nbx, by = lin / nbx;
 
     const int L = a.L, H = a.H;
     const int lane = threadIdx.x & 63;
@@ -493,7 +514,7 @@ void step_kernel_vec(StepArgs<S> a)
 #pragma unroll
     for (int i = 0; i < V; ++i) {
         jmax[i] = -1;
-        hp[i] = (a.region == kRegionFrontBand && active) ? a.h_prev[xv + i] : 0;
+        hp[i] = (a.region == kRegionFrontBand && active) ? io.h_prev[xv + i] : 0;
     }
     R Wd[9];
 #pragma unroll
@@ -504,8 +525,8 @@ void step_kernel_vec(StepArgs<S> a)
     // lanes past the last column read (and never store) the last vector, so
     // every access stays inside the row
     const int64_t cv = tl.col(active ? xv : L - V), cl = tl.col(xl), cr = tl.col(xr);
-    const S *__restrict__ F = a.fin;
-    S *__restrict__ G = a.fout;
+    const S *__restrict__ F = io.fin;
+    S *__restrict__ G = io.fout;
     int r0 = (a.mode == kModeDevice) ? (int)((y_wall + j0) % H) : j0;
 
     for (int j = j0; j < jend; ++j) {
@@ -579,7 +600,7 @@ void step_kernel_vec(StepArgs<S> a)
             double m_site = 0.0, s_site = 0.0, x_site = 0.0;
             const uint32_t x = (uint32_t)(xv + k);
             const bool tissue =
-                site_step<S>(a, v, fs, Wd, so, x, y, y_wall, hp[k], m_site, s_site, x_site);
+                site_step<S>(a, io.t, v, fs, Wd, so, x, y, y_wall, hp[k], m_site, s_site, x_site);
 #pragma unroll
             for (int i = 0; i < 9; ++i) put_el<S, ND>(O[i], k, so[i]);
             if (active) {
@@ -606,10 +627,10 @@ void step_kernel_vec(StepArgs<S> a)
         for (int k = 0; k < V; ++k) {
             if (jmax[k] >= 0) {
                 const int32_t hv = (int32_t)(y_wall + jmax[k] + 1);
-                atomicMax(a.h_next + xv + k, hv);
+                atomicMax(io.h_next + xv + k, hv);
                 atomicMax(a.colmax + xv + k, hv);
             }
-            if (a.h_clear && by == 0) a.h_clear[xv + k] = 0;
+            if (io.h_clear && by == 0) io.h_clear[xv + k] = 0;
         }
     }
 
@@ -621,6 +642,15 @@ void step_kernel_vec(StepArgs<S> a)
         p[1] += s_acc;
         p[2] += x_acc;
     }
+}
+
+template <class S, int NT, int ND>
+__global__ __launch_bounds__(NT) void step_kernel_vec(StepArgs<S> a)
+{
+    const int nbx = gridDim.x;
+    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y);
+    const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
+    step_vec_tile<S, NT, ND>(a, io, lin % nbx, lin / nbx, nbx);
 }
 
 // ---------------------------------------------------------------------------
@@ -703,34 +733,6 @@ __global__ __launch_bounds__(NT) void mass_kernel(MassArgs<S> a)
 // ---------------------------------------------------------------------------
 // Small single-block kernels.
 // ---------------------------------------------------------------------------
-__global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
-__global__ void fill_f64_kernel(double *p, int64_t n, double v)
-{
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
-__global__ void state_set_kernel(DevState *st, int64_t y_wall, int64_t y_valid_top,
-                                 int64_t n_rows, int64_t h_hi)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        st->y_wall = y_wall;
-        st->y_valid_top = y_valid_top;
-        st->n_rows = n_rows;
-        st->h_hi = h_hi;
-        st->retired_total = 0.0;
-        st->retired_last = 0.0;
-        st->status = 0u;
-    }
-}
-
 constexpr int kRedThreads = 1024;
 
 // Deterministic reductions of one block of kRedThreads threads.
@@ -797,54 +799,12 @@ __device__ __forceinline__ void height_stats(const int32_t *h, int L, int64_t y_
     W = sqrt((double)num) / (double)L;
 }
 
-// Diagnostics of the current state.
-__global__ __launch_bounds__(kRedThreads) void diag_kernel(DiagArgs a)
-{
-    __shared__ double shd[kRedThreads / 64];
-    __shared__ long long shi[kRedThreads / 64];
-    double m = 0.0, s = 0.0, fx = 0.0;
-    for (int b = threadIdx.x; b < a.nblocks; b += kRedThreads) {
-        m += a.partials[4 * b + 0];
-        s += a.partials[4 * b + 1];
-        fx += a.partials[4 * b + 2];
-    }
-    m = block_sum_d(m, shd);
-    s = block_sum_d(s, shd);
-    fx = block_sum_d(fx, shd);
-    const int64_t y_wall = a.st->y_wall;
-    double hbar, W;
-    long long hmax;
-    height_stats(a.h_cur, a.L, y_wall, shi, hbar, W, hmax);
-    long long hi = LLONG_MIN;
-    for (int x = threadIdx.x; x < a.L; x += kRedThreads)
-        hi = (long long)a.colmax[x] > hi ? (long long)a.colmax[x] : hi;
-    hi = block_max_i(hi, shi);
-    if (threadIdx.x == 0) {
-        DiagOut *o = a.out;
-        const double mass = m - a.st->retired_last;
-        uint32_t st = a.st->status;
-        if (!isfinite(mass)) {
-            st |= kStNonFinite;
-            a.st->status = st;
-        }
-        o->mass = mass;
-        o->src_total = s;
-        o->fix_total = fx;
-        o->retired = a.st->retired_total;
-        o->hbar = hbar;
-        o->W = W;
-        o->y_wall = y_wall;
-        o->h_hi = hi;
-        o->status = st;
-    }
-}
-
 // Between steps when the device drives the window (rear wall that follows the
 // front, and/or the exact sweep window): wall rule of Appendix A, retired
 // mass, highest front so far, rows the next step must sweep, and the next
 // front-height slot reset to the wall row.
 template <class S>
-__global__ __launch_bounds__(kRedThreads) void finalize_kernel(FinalizeArgs<S> a)
+__device__ __forceinline__ void finalize_body(const FinalizeArgs<S> &a)
 {
     using R = typename Codec<S>::R;
     __shared__ double shd[kRedThreads / 64];
@@ -908,6 +868,96 @@ __global__ __launch_bounds__(kRedThreads) void finalize_kernel(FinalizeArgs<S> a
     }
 }
 
+template <class S>
+__global__ __launch_bounds__(kRedThreads) void finalize_kernel(FinalizeArgs<S> a)
+{
+    finalize_body<S>(a);
+}
+
+// ---------------------------------------------------------------------------
+// Batches: one launch advances every member of a group by one step.  The
+// 1-D grid enumerates all members' tiles; a block finds its member by binary
+// search over the prefix sums of tile counts and runs the same tile body as
+// the solo kernels, so each member's populations come out bit for bit as in
+// a solo run.  Per-step buffers and slots follow from the member's step count.
+// ---------------------------------------------------------------------------
+template <class S>
+__device__ __forceinline__ const BatchRep<S> *batch_locate(BatchRep<S> *const *reps,
+                                                           const int32_t *offs, int n, int lin,
+                                                           int &local)
+{
+    int lo = 0, hi = n;   // offs[lo] <= lin < offs[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (offs[mid] <= lin) lo = mid;
+        else hi = mid;
+    }
+    local = lin - offs[lo];
+    return reps[lo];
+}
+
+template <class S>
+__device__ __forceinline__ StepIO<S> batch_io(const BatchRep<S> *R, int k)
+{
+    const int64_t tt = R->t0 + k;
+    const int cur = (R->cur0 + k) & 1;
+    StepIO<S> io;
+    io.fin = R->f[cur];
+    io.fout = R->f[cur ^ 1];
+    io.h_prev = R->hs[tt % 3];
+    io.h_next = R->hs[(tt + 1) % 3];
+    io.h_clear = R->device_driven ? nullptr : R->hs[(tt + 2) % 3];
+    io.t = (uint32_t)tt;
+    return io;
+}
+
+template <class S, int NT, int ND>
+__global__ __launch_bounds__(NT) void step_batch_vec(BatchRep<S> *const *reps, const int32_t *offs,
+                                                     int n, int total, int k)
+{
+    int local;
+    const BatchRep<S> *R = batch_locate(reps, offs, n, xcd_order(blockIdx.x, total), local);
+    const StepArgs<S> a = R->a;
+    const StepIO<S> io = batch_io(R, k);
+    step_vec_tile<S, NT, ND>(a, io, local % R->gx, local / R->gx, R->gx);
+}
+
+template <class S, int NT, int RB>
+__global__ __launch_bounds__(NT) void step_batch_scalar(BatchRep<S> *const *reps,
+                                                        const int32_t *offs, int n, int total, int k)
+{
+    int local;
+    const BatchRep<S> *R = batch_locate(reps, offs, n, xcd_order(blockIdx.x, total), local);
+    const StepArgs<S> a = R->a;
+    const StepIO<S> io = batch_io(R, k);
+    step_scalar_tile<S, NT, RB>(a, io, local % R->gx, local / R->gx, R->gx);
+}
+
+template <class S>
+__global__ __launch_bounds__(kRedThreads) void finalize_batch(BatchRep<S> *const *reps, int k)
+{
+    const BatchRep<S> *R = reps[blockIdx.x];
+    if (!R->device_driven) return;
+    FinalizeArgs<S> fa = R->fa;
+    const int64_t tt = R->t0 + k;
+    const int cur = (R->cur0 + k) & 1;
+    fa.f = R->f[cur ^ 1];
+    fa.h_next = R->hs[(tt + 1) % 3];
+    fa.h_clear = R->hs[(tt + 2) % 3];
+    finalize_body<S>(fa);
+}
+
+template <class S>
+__global__ void batch_advance(BatchRep<S> *const *reps, int n, int K)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        BatchRep<S> *R = reps[i];
+        R->t0 += K;
+        R->cur0 = (R->cur0 + K) & 1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers (host side)
 // ---------------------------------------------------------------------------
@@ -919,27 +969,25 @@ void launch_step_rb(const StepArgs<S> &a, dim3 grid, int nt, hipStream_t s)
     else hipLaunchKernelGGL((step_kernel<S, 64, RB>), grid, dim3(64), 0, s, a);
 }
 
-template <class S, int ND, int WPE>
+template <class S, int ND>
 void launch_vec_nt(const StepArgs<S> &a, dim3 grid, int nt, hipStream_t s)
 {
-    if (nt == 256) hipLaunchKernelGGL((step_kernel_vec<S, 256, ND, WPE>), grid, dim3(256), 0, s, a);
-    else if (nt == 128) hipLaunchKernelGGL((step_kernel_vec<S, 128, ND, WPE>), grid, dim3(128), 0, s, a);
-    else hipLaunchKernelGGL((step_kernel_vec<S, 64, ND, WPE>), grid, dim3(64), 0, s, a);
+    if (nt == 256) hipLaunchKernelGGL((step_kernel_vec<S, 256, ND>), grid, dim3(256), 0, s, a);
+    else if (nt == 128) hipLaunchKernelGGL((step_kernel_vec<S, 128, ND>), grid, dim3(128), 0, s, a);
+    else hipLaunchKernelGGL((step_kernel_vec<S, 64, ND>), grid, dim3(64), 0, s, a);
 }
 
-// vb: bytes per lane (8 or 16); wpe: waves per SIMD to fit (1 = no bound).
+// vb: bytes per lane (4, 8 or 16).
 template <class S>
-hipError_t launch_step_vec(const StepArgs<S> &a, dim3 grid, int nt, int vb, int wpe, hipStream_t s)
+hipError_t launch_step_vec(const StepArgs<S> &a, dim3 grid, int nt, int vb, hipStream_t s)
 {
     if (vb == 4) {
-        if constexpr (sizeof(S) <= 4) launch_vec_nt<S, 1, 1>(a, grid, nt, s);
+        if constexpr (sizeof(S) <= 4) launch_vec_nt<S, 1>(a, grid, nt, s);
         else return hipErrorInvalidValue;
-    } else if (vb == 16) {
-        if (wpe >= 4) launch_vec_nt<S, 4, 4>(a, grid, nt, s);
-        else launch_vec_nt<S, 4, 1>(a, grid, nt, s);
+    } else if (vb == 8) {
+        launch_vec_nt<S, 2>(a, grid, nt, s);
     } else {
-        if (wpe >= 4) launch_vec_nt<S, 2, 4>(a, grid, nt, s);
-        else launch_vec_nt<S, 2, 1>(a, grid, nt, s);
+        launch_vec_nt<S, 4>(a, grid, nt, s);
     }
     return hipGetLastError();
 }
@@ -947,8 +995,7 @@ hipError_t launch_step_vec(const StepArgs<S> &a, dim3 grid, int nt, int vb, int 
 template <class S>
 hipError_t launch_step(const StepArgs<S> &a, dim3 grid, int nt, int rb, hipStream_t s)
 {
-    if (rb >= 4) launch_step_rb<S, 4>(a, grid, nt, s);
-    else if (rb == 2) launch_step_rb<S, 2>(a, grid, nt, s);
+    if (rb >= 2) launch_step_rb<S, 2>(a, grid, nt, s);
     else launch_step_rb<S, 1>(a, grid, nt, s);
     return hipGetLastError();
 }
@@ -978,48 +1025,50 @@ hipError_t launch_finalize(const FinalizeArgs<S> &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_diag(const DiagArgs &a, hipStream_t s)
+template <class S, int NT>
+void launch_batch_nt(BatchRep<S> *const *reps, const int32_t *offs, int n, int total, int vec,
+                     int vb_or_rb, int k, hipStream_t s)
 {
-    hipLaunchKernelGGL(diag_kernel, dim3(1), dim3(kRedThreads), 0, s, a);
+    const dim3 g(total), b(NT);
+    if (vec) {
+        if (vb_or_rb == 4) {
+            if constexpr (sizeof(S) <= 4) hipLaunchKernelGGL((step_batch_vec<S, NT, 1>), g, b, 0, s, reps, offs, n, total, k);
+        } else if (vb_or_rb == 8) {
+            hipLaunchKernelGGL((step_batch_vec<S, NT, 2>), g, b, 0, s, reps, offs, n, total, k);
+        } else {
+            hipLaunchKernelGGL((step_batch_vec<S, NT, 4>), g, b, 0, s, reps, offs, n, total, k);
+        }
+    } else {
+        if (vb_or_rb >= 2) hipLaunchKernelGGL((step_batch_scalar<S, NT, 2>), g, b, 0, s, reps, offs, n, total, k);
+        else hipLaunchKernelGGL((step_batch_scalar<S, NT, 1>), g, b, 0, s, reps, offs, n, total, k);
+    }
+}
+
+template <class S>
+hipError_t launch_step_batch(BatchRep<S> *const *reps, const int32_t *offs, int n, int total,
+                             int vec, int nt, int vb_or_rb, int k, hipStream_t s)
+{
+    if (total <= 0) return hipSuccess;
+    if (nt == 256) launch_batch_nt<S, 256>(reps, offs, n, total, vec, vb_or_rb, k, s);
+    else if (nt == 128) launch_batch_nt<S, 128>(reps, offs, n, total, vec, vb_or_rb, k, s);
+    else launch_batch_nt<S, 64>(reps, offs, n, total, vec, vb_or_rb, k, s);
     return hipGetLastError();
 }
 
-hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
+template <class S>
+hipError_t launch_finalize_batch(BatchRep<S> *const *reps, int n, int k, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    int blocks = (int)((n + 255) / 256);
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks), dim3(256), 0, s, p, n, v);
+    hipLaunchKernelGGL((finalize_batch<S>), dim3(n), dim3(kRedThreads), 0, s, reps, k);
     return hipGetLastError();
 }
 
-hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s)
+template <class S>
+hipError_t launch_batch_advance(BatchRep<S> *const *reps, int n, int K, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    int blocks = (int)((n + 255) / 256);
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks), dim3(256), 0, s, p, n, v);
+    hipLaunchKernelGGL((batch_advance<S>), dim3((n + 255) / 256), dim3(256), 0, s, reps, n, K);
     return hipGetLastError();
 }
-
-hipError_t launch_state_set(DevState *st, int64_t y_wall, int64_t y_valid_top, int64_t n_rows,
-                            int64_t h_hi, hipStream_t s)
-{
-    hipLaunchKernelGGL(state_set_kernel, dim3(1), dim3(64), 0, s, st, y_wall, y_valid_top,
-                       n_rows, h_hi);
-    return hipGetLastError();
-}
-
-#define LBM_INSTANTIATE(S)                                                              \
-    template hipError_t launch_step<S>(const StepArgs<S> &, dim3, int, int, hipStream_t);    \
-    template hipError_t launch_step_vec<S>(const StepArgs<S> &, dim3, int, int, int, hipStream_t);    \
-    template hipError_t launch_init<S>(const InitArgs<S> &, dim3, int, hipStream_t);    \
-    template hipError_t launch_mass<S>(const MassArgs<S> &, dim3, int, hipStream_t);    \
-    template hipError_t launch_finalize<S>(const FinalizeArgs<S> &, hipStream_t);
-
-LBM_INSTANTIATE(double)
-LBM_INSTANTIATE(float)
-LBM_INSTANTIATE(__half)
-LBM_INSTANTIATE(__hip_bfloat16)
 
 }  // namespace lbm

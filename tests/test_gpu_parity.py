@@ -68,20 +68,16 @@ def test_fp64_parity_64x64_workload_1000_steps():
 
 
 @pytest.fixture(params=["vector", "scalar"])
-def kernel_form(request, monkeypatch):
-    """Both forms of the step kernel: 16-byte vectors per lane (used when the
-    width splits evenly into lanes) and one column per lane."""
-    if request.param == "scalar":
-        monkeypatch.setenv("LBMGROW_KERNEL", "scalar")
-    else:
-        monkeypatch.delenv("LBMGROW_KERNEL", raising=False)
-    return request.param
+def kernel_form(request):
+    """Both forms of the step kernel: vectors of columns per lane (used when
+    the width splits evenly into lanes) and one column per lane."""
+    return {"kernel_vb": 1} if request.param == "scalar" else {}
 
 
 @pytest.mark.parametrize("L,H", [(300, 96), (130, 70), (7, 40)])
 def test_fp64_parity_noise_front_band_ragged(L, H, kernel_form):
     cfg = si.cfg(L=L, H=H, init_rows=20, tau=0.8, sigma=1e-2, growth_rate=5e-3,
-                 region="front_band", region_width=4, seed=3, replica=2)
+                 region="front_band", region_width=4, seed=3, replica=2, **kernel_form)
     _run_fp64(cfg, [1, 7, 50, 200])
 
 
@@ -215,7 +211,7 @@ def _one_step_check(sim, cfg, prec):
 @pytest.mark.parametrize("L", [200, 1000, 98])
 def test_reduced_precision_one_step_parity(prec, L, kernel_form):
     cfg = si.cfg(L=L, H=160, init_rows=64, tau=0.8, sigma=1e-3, growth_rate=1e-3,
-                 region="front_band", region_width=8, precision=prec, seed=1)
+                 region="front_band", region_width=8, precision=prec, seed=1, **kernel_form)
     sim = _sim(cfg)
     sim.front_heights()
     errs = [_one_step_check(sim, cfg, prec)]
