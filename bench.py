@@ -98,6 +98,13 @@ def main():
     ap.add_argument("--h-every", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=600, help="served: trace length")
+    ap.add_argument("--time-limit", type=float, default=300.0, help="served: wall-clock limit (s)")
+    ap.add_argument("--workload", default="bulk", choices=["bulk", "edge", "ensemble", "served"],
+                    help="bulk: 4096 x 4096 bulk growth (default); edge: 2048 x 8192 growth "
+                         "within 8 rows of the front; ensemble: 256 replicas of uneven size, "
+                         "batched, against the same runs stepped one after another")
+    ap.add_argument("--tuned", action="store_true", help="launch shapes from the autotuner cache")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -110,7 +117,15 @@ def main():
     import synth_inputs as si
     from paper_2303_02210_amd import Sim
 
-    cfg = dict(si.BULK_4096_FP32, precision=args.precision)
+    if args.workload == "ensemble":
+        return bench_ensemble(args)
+    if args.workload == "served":
+        return bench_served(args)
+    base = si.BULK_4096_FP32 if args.workload == "bulk" else si.EDGE_2048x8192
+    cfg = dict(base, precision=args.precision)
+    if args.tuned:
+        from paper_2303_02210_amd import autotune
+        cfg = autotune.apply(cfg)
     L, H = cfg["L"], cfg["H"]
     bpu = 2 * 9 * STORE_BYTES[args.precision]          # read 9 + write 9 populations
 
@@ -163,9 +178,12 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[args.precision], "data": "synthetic",
         "config": {"workload": cfg["name"], "L": L, "H": H, "precision": args.precision,
-                   "growth": "bulk", "growth_rate": cfg["growth_rate"], "sigma": cfg["sigma"],
+                   "growth": cfg["region"] if cfg["region"] != "all" else "bulk",
+                   "growth_rate": cfg["growth_rate"], "tau": cfg["tau"], "sigma": cfg["sigma"],
                    "init_rows": cfg["init_rows"], "h_every": every, "sweep": "full",
-                   "bytes_per_update": bpu},
+                   "bytes_per_update": bpu,
+                   "launch": {"kernel_vb": cfg.get("kernel_vb", 0),
+                              "kernel_ty": cfg.get("kernel_ty", 0)}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
@@ -179,6 +197,113 @@ def main():
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_steps} steps ...")
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def bench_ensemble(args):
+    """256 replicas (widths 128..2048 with 96/64/48/32/16 copies, height 4L,
+    bulk growth 1e-4, noise 1e-3, float32) advanced together by the batch API,
+    against the same runs stepped one after another on their own."""
+    import torch
+    import synth_inputs as si
+    from paper_2303_02210_amd import Ensemble, Sim
+
+    cfgs = si.ensemble()
+    if args.tuned:
+        from paper_2303_02210_amd import autotune
+        cfgs = [autotune.apply(c) for c in cfgs]
+    K = args.steps
+    sites = sum(c["L"] * c["H"] for c in cfgs)
+    bpu = 2 * 9 * STORE_BYTES["fp32"]
+    log(f"ensemble: {len(cfgs)} replicas, {sites} sites, {K} steps each")
+    ens = Ensemble(cfgs)
+    ens.step(args.warmup)
+    ens.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(ens.stream)
+    done = 0
+    while done < K:
+        n = min(100, K - done)
+        ens.step(n)
+        done += n
+    e1.record(ens.stream)
+    ens.synchronize()
+    t_batch = e0.elapsed_time(e1) / 1e3
+    W = [m.diagnostics()["W"] for m in ens.members]
+    ens.close()
+    for m in list(ens.members):
+        m.close()
+    del ens
+    torch.cuda.empty_cache()
+    log(f"batched: {t_batch:.3f} s; mean W {sum(W) / len(W):.3f}")
+    # the same runs, one after another, each on its own
+    t_seq = 0.0
+    for c in cfgs:
+        sim = Sim(c)
+        sim.step(args.warmup)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(sim.stream)
+        sim.step(K)
+        b.record(sim.stream)
+        torch.cuda.synchronize()
+        t_seq += a.elapsed_time(b) / 1e3
+        sim.close()
+    log(f"sequential: {t_seq:.3f} s")
+    mlups = sites * K / t_batch / 1e6
+    full_steps = si.ensemble()[0]["steps"]
+    out = {
+        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": round(t_batch / K * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ensemble_256_fp32", "replicas": len(cfgs),
+                   "widths": list(si.ENSEMBLE_WIDTHS), "counts": list(si.ENSEMBLE_COUNTS),
+                   "height": "4L", "sites": sites, "bytes_per_update": bpu},
+        "roofline": {"bound": "hbm", "achieved": round(sites * bpu / (t_batch / K) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(sites * bpu / (t_batch / K) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "runs_per_hour": round(len(cfgs) / (t_batch * full_steps / K) * 3600, 1),
+        "sequential": {"value": round(sites * K / t_seq / 1e6, 1), "unit": "MLUPS",
+                       "runs_per_hour": round(len(cfgs) / (t_seq * full_steps / K) * 3600, 1)},
+        "speedup_vs_sequential": round(t_seq / t_batch, 3),
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(args):
+    """Poisson arrivals at 20 requests/s of runs with L in {128..4096}, H in
+    [2L, 4L], 1000-50000 steps, bulk or front-band growth, FP64 / FP32 /
+    FP16-offset; admitted by HBM footprint into the running batch; rear wall
+    following the front; front heights streamed back every tick."""
+    import synth_inputs as si
+    from paper_2303_02210_amd.serve import Server
+
+    reqs = si.served_trace(n=args.requests)
+    if args.tuned:
+        from paper_2303_02210_amd import autotune
+        reqs = [autotune.apply(c) for c in reqs]
+    srv = Server(hbm_budget=200e9, tick_steps=100)
+    summ = srv.serve(reqs, time_limit=args.time_limit, log=log)
+    srv.close()
+    log(json.dumps(summ))
+    out = {
+        "metric": METRIC, "value": round(summ["runs_per_hour"], 1), "unit": "runs/hour",
+        "n_gpus": 1, "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "mixed f64/f32/f16-offset",
+        "data": "synthetic",
+        "config": {"workload": f"served_poisson20_{args.requests}", "requests": args.requests,
+                   "rate_hz": 20.0, "widths": [128, 256, 512, 1024, 2048, 4096],
+                   "steps_range": [1000, 50000], "wall": "follow", "sweep": "window",
+                   "hbm_budget_bytes": 200e9, "tick_steps": 100,
+                   "time_limit_s": args.time_limit},
+        "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
+        "completed": summ["completed"], "unfinished": summ["running"] + summ["queued"],
+        "mlups_nominal": round(summ["mlups_nominal"], 1),
+        "gpu_busy_frac": round(summ["gpu_busy_frac"], 4), "wall_s": round(summ["wall_s"], 2),
+        "roofline": None, "cpu_baseline": None,
+    }
     print(json.dumps(out), flush=True)
 
 

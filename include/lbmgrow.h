@@ -233,7 +233,10 @@ int lbm_destroy(lbm_handle *h);
  * a HIP graph and replayed while the membership stays the same.  Every
  * member keeps its own workspace, state and status, and its populations come
  * out bit for bit as with lbm_step on the handle alone.
- *   lbm_batch_workspace_bytes  device workspace for up to max_members.
+ *   lbm_tiles            tiles (thread blocks per step) of a simulation
+ *                        with parameters p; 0 if p is invalid.
+ *   lbm_batch_workspace_bytes  device workspace for up to max_members whose
+ *                        tiles add up to at most max_tiles.
  *   lbm_batch_create     empty batch in dev_ws (256-byte aligned, caller
  *                        owned, valid until lbm_batch_destroy) on hip_stream;
  *                        members must use the same stream.
@@ -245,11 +248,13 @@ int lbm_destroy(lbm_handle *h);
  *                        state (remove it and step again).
  *   lbm_batch_destroy    releases the batch, not its members.
  * Errors: LBM_E_INVALID (null/foreign handles, stream mismatch, full batch),
- * LBM_E_NOMEM (workspace too small), LBM_E_DEVICE.
+ * LBM_E_NOMEM (workspace too small, or members' tiles beyond max_tiles at
+ * the next step), LBM_E_DEVICE.
  */
-size_t lbm_batch_workspace_bytes(int max_members);
-int lbm_batch_create(void *dev_ws, size_t ws_bytes, int max_members, void *hip_stream,
-                     lbm_batch **out);
+int64_t lbm_tiles(const lbm_params *p);
+size_t lbm_batch_workspace_bytes(int max_members, int64_t max_tiles);
+int lbm_batch_create(void *dev_ws, size_t ws_bytes, int max_members, int64_t max_tiles,
+                     void *hip_stream, lbm_batch **out);
 int lbm_batch_add(lbm_batch *b, lbm_handle *h);
 int lbm_batch_remove(lbm_batch *b, lbm_handle *h);
 int lbm_batch_step(lbm_batch *b, int64_t nsteps);

@@ -78,8 +78,9 @@ _SIGS = [
     ("lbm_set_state", ctypes.c_int, [_VP, _VP, ctypes.c_size_t]),
     ("lbm_last_error", ctypes.c_char_p, [_VP]),
     ("lbm_destroy", ctypes.c_int, [_VP]),
-    ("lbm_batch_workspace_bytes", ctypes.c_size_t, [ctypes.c_int]),
-    ("lbm_batch_create", ctypes.c_int, [_VP, ctypes.c_size_t, ctypes.c_int, _VP,
+    ("lbm_tiles", ctypes.c_int64, [ctypes.POINTER(Params)]),
+    ("lbm_batch_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, ctypes.c_int64]),
+    ("lbm_batch_create", ctypes.c_int, [_VP, ctypes.c_size_t, ctypes.c_int, ctypes.c_int64, _VP,
                                         ctypes.POINTER(_VP)]),
     ("lbm_batch_add", ctypes.c_int, [_VP, _VP]),
     ("lbm_batch_remove", ctypes.c_int, [_VP, _VP]),

@@ -794,20 +794,22 @@ int lbm_destroy(lbm_handle *h)
 namespace {
 
 constexpr int kMaxGroups = 16;
+constexpr int kWindowGrid = 8192;   // blocks of a windowed group's launch
 
 struct BatchGroup {
-    int prec = 0, vec = 0, nt = 0, vbrb = 0;     // storage type and kernel form
+    int prec = 0, vec = 0, nt = 0, vbrb = 0, ty = 0, windowed = 0;   // kernel form
     std::vector<lbm_handle *> m;
-    int total = 0;                               // tiles over all members
+    int64_t tiles = 0;                           // tiles over all members
+    int grid = 0;                                // blocks per step launch
     int ndev = 0;                                // members finalized each step
     void **reps = nullptr;                       // device: descriptor pointers
-    int32_t *offs = nullptr;                     // device: tile prefix sums
+    int32_t *count = nullptr;                    // device: table entries to run
+    TileRef *table = nullptr;                    // device: the group's tiles
 };
 
 size_t batch_slot_bytes(int max_members)
 {
-    return align_up((size_t)(max_members + 1) * 4, kAlign) +
-           align_up((size_t)max_members * sizeof(void *), kAlign);
+    return align_up((size_t)max_members * sizeof(void *), kAlign) + kAlign;
 }
 
 template <class S>
@@ -822,7 +824,11 @@ int write_rep(lbm_handle *h)
     r.t0 = h->t;
     r.cur0 = h->cur;
     r.gx = h->lay.gx;
+    r.ty = h->lay.ty;
+    r.nblocks = h->lay.nblocks;
     r.device_driven = h->device_driven ? 1 : 0;
+    r.window = (h->p.flags & LBM_FLAG_WINDOW) ? 1 : 0;
+    r.last_live = h->lay.nblocks;   // first windowed launch clears every idle tile
     int rc = h->hip(hipMemcpyAsync(h->ws + h->lay.off_rep, &r, sizeof r, hipMemcpyHostToDevice,
                                    h->stream),
                     "batch descriptor copy");
@@ -839,8 +845,13 @@ int write_rep(lbm_handle *h)
 template <class S>
 hipError_t enqueue_group_step(const BatchGroup &g, int k, hipStream_t s)
 {
-    return launch_step_batch<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps), g.offs,
-                                (int)g.m.size(), g.total, g.vec, g.nt, g.vbrb, k, s);
+    hipError_t e = hipSuccess;
+    if (g.windowed)
+        e = launch_plan_batch<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps), (int)g.m.size(),
+                                 g.table, g.count, s);
+    if (e != hipSuccess) return e;
+    return launch_step_batch<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps), g.table, g.count,
+                                g.grid, g.vec, g.nt, g.vbrb, k, s);
 }
 template <class S>
 hipError_t enqueue_group_finalize(const BatchGroup &g, int k, hipStream_t s)
@@ -868,6 +879,7 @@ struct lbm_batch {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     int max_members = 0;
+    int64_t max_tiles = 0;
     std::vector<lbm_handle *> members;
     std::vector<BatchGroup> groups;
     bool dirty = true;
@@ -890,10 +902,11 @@ struct lbm_batch {
         groups.clear();
         for (lbm_handle *h : members) {
             const int vbrb = h->lay.vec ? h->lay.vb : h->lay.rb;
+            const int win = (h->p.flags & LBM_FLAG_WINDOW) ? 1 : 0;
             BatchGroup *g = nullptr;
             for (BatchGroup &c : groups)
                 if (c.prec == h->p.precision && c.vec == (int)h->lay.vec && c.nt == h->lay.nt &&
-                    c.vbrb == vbrb)
+                    c.vbrb == vbrb && c.ty == h->lay.ty && c.windowed == win)
                     g = &c;
             if (!g) {
                 if ((int)groups.size() == kMaxGroups) return LBM_E_INVALID;
@@ -903,32 +916,49 @@ struct lbm_batch {
                 g->vec = h->lay.vec;
                 g->nt = h->lay.nt;
                 g->vbrb = vbrb;
+                g->ty = h->lay.ty;
+                g->windowed = win;
             }
             g->m.push_back(h);
         }
         const size_t slot = batch_slot_bytes(max_members);
+        TileRef *table = reinterpret_cast<TileRef *>(ws + kMaxGroups * slot);
+        int64_t used = 0;
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             BatchGroup &g = groups[gi];
             char *base = ws + gi * slot;
-            g.offs = reinterpret_cast<int32_t *>(base);
-            g.reps = reinterpret_cast<void **>(base + align_up((size_t)(max_members + 1) * 4, kAlign));
-            std::vector<int32_t> offs(g.m.size() + 1, 0);
+            g.reps = reinterpret_cast<void **>(base);
+            g.count = reinterpret_cast<int32_t *>(base + slot - kAlign);
             std::vector<void *> reps(g.m.size());
-            int64_t tot = 0;
+            g.tiles = 0;
             g.ndev = 0;
             for (size_t i = 0; i < g.m.size(); ++i) {
-                offs[i] = (int32_t)tot;
-                tot += g.m[i]->lay.nblocks;
                 reps[i] = g.m[i]->ws + g.m[i]->lay.off_rep;
+                g.tiles += g.m[i]->lay.nblocks;
                 g.ndev += g.m[i]->device_driven ? 1 : 0;
             }
-            if (tot > INT32_MAX) return LBM_E_INVALID;
-            offs[g.m.size()] = (int32_t)tot;
-            g.total = (int)tot;
-            if (hipMemcpyAsync(g.offs, offs.data(), offs.size() * 4, hipMemcpyHostToDevice, stream) !=
-                    hipSuccess ||
-                hipMemcpyAsync(g.reps, reps.data(), reps.size() * sizeof(void *),
+            if (used + g.tiles > max_tiles || g.tiles > INT32_MAX) return LBM_E_NOMEM;
+            g.table = table + used;
+            used += g.tiles;
+            std::vector<TileRef> tab;
+            int32_t cnt = 0;
+            if (g.windowed) {
+                g.grid = (int)std::min<int64_t>(g.tiles, kWindowGrid);
+            } else {
+                // every tile, member by member, in runs of kTilesPerRun
+                for (size_t i = 0; i < g.m.size(); ++i) {
+                    const int nb = g.m[i]->lay.nblocks;
+                    for (int l = 0; l < nb; l += kTilesPerRun)
+                        tab.push_back(TileRef{(int32_t)i, l, std::min(kTilesPerRun, nb - l), 0});
+                }
+                cnt = (int32_t)tab.size();
+                g.grid = cnt;
+            }
+            if (hipMemcpyAsync(g.reps, reps.data(), reps.size() * sizeof(void *),
                                hipMemcpyHostToDevice, stream) != hipSuccess ||
+                hipMemcpyAsync(g.count, &cnt, sizeof cnt, hipMemcpyHostToDevice, stream) != hipSuccess ||
+                (!tab.empty() && hipMemcpyAsync(g.table, tab.data(), tab.size() * sizeof(TileRef),
+                                                hipMemcpyHostToDevice, stream) != hipSuccess) ||
                 hipStreamSynchronize(stream) != hipSuccess)
                 return LBM_E_DEVICE;
         }
@@ -961,26 +991,35 @@ struct lbm_batch {
 
 extern "C" {
 
-size_t lbm_batch_workspace_bytes(int max_members)
+size_t lbm_batch_workspace_bytes(int max_members, int64_t max_tiles)
 {
-    if (max_members < 1) return 0;
-    return kMaxGroups * batch_slot_bytes(max_members);
+    if (max_members < 1 || max_tiles < 1) return 0;
+    return kMaxGroups * batch_slot_bytes(max_members) +
+           align_up((size_t)max_tiles * sizeof(TileRef), kAlign);
 }
 
-int lbm_batch_create(void *dev_ws, size_t ws_bytes, int max_members, void *hip_stream,
-                     lbm_batch **out)
+int64_t lbm_tiles(const lbm_params *p)
+{
+    if (!params_ok(p, nullptr)) return 0;
+    return make_layout(p).nblocks;
+}
+
+int lbm_batch_create(void *dev_ws, size_t ws_bytes, int max_members, int64_t max_tiles,
+                     void *hip_stream, lbm_batch **out)
 {
     if (!out) return LBM_E_INVALID;
     *out = nullptr;
-    if (!dev_ws || max_members < 1 || (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) != 0)
+    if (!dev_ws || max_members < 1 || max_tiles < 1 ||
+        (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) != 0)
         return LBM_E_INVALID;
-    if (ws_bytes < lbm_batch_workspace_bytes(max_members)) return LBM_E_NOMEM;
+    if (ws_bytes < lbm_batch_workspace_bytes(max_members, max_tiles)) return LBM_E_NOMEM;
     lbm_batch *b = new (std::nothrow) lbm_batch();
     if (!b) return LBM_E_NOMEM;
     b->stream = reinterpret_cast<hipStream_t>(hip_stream);
     b->ws = reinterpret_cast<char *>(dev_ws);
     b->ws_bytes = ws_bytes;
     b->max_members = max_members;
+    b->max_tiles = max_tiles;
     *out = b;
     return LBM_OK;
 }

@@ -11,8 +11,11 @@ namespace lbm {
     template hipError_t launch_init<S>(const InitArgs<S> &, dim3, int, hipStream_t);    \
     template hipError_t launch_mass<S>(const MassArgs<S> &, dim3, int, hipStream_t);    \
     template hipError_t launch_finalize<S>(const FinalizeArgs<S> &, hipStream_t);           \
-    template hipError_t launch_step_batch<S>(BatchRep<S> *const *, const int32_t *, int, int, \
-                                             int, int, int, int, hipStream_t);              \
+    template hipError_t launch_step_batch<S>(BatchRep<S> *const *, const TileRef *,           \
+                                             const int32_t *, int, int, int, int, int,      \
+                                             hipStream_t);                                  \
+    template hipError_t launch_plan_batch<S>(BatchRep<S> *const *, int, TileRef *, int32_t *, \
+                                             hipStream_t);                                  \
     template hipError_t launch_finalize_batch<S>(BatchRep<S> *const *, int, int, hipStream_t); \
     template hipError_t launch_batch_advance<S>(BatchRep<S> *const *, int, int, hipStream_t);
 

@@ -147,18 +147,38 @@ struct BatchRep {
     int64_t t0;             // steps taken when the current batch run started
     int32_t cur0;           // buffer holding the state at that point
     int32_t gx;             // tiles along x
+    int32_t ty;             // rows per tile
+    int32_t nblocks;        // tiles in all
     int32_t device_driven;  // follow wall / sweep window: finalize each step
+    int32_t window;         // sweep window: only tiles of live rows run
+    int32_t last_live;      // tiles run by the last windowed launch
+    int32_t pad2;
+};
+
+// Entry of a batch tile table: a run of n consecutive tiles of one member
+// (member index in its group, first tile number inside the member; tiles are
+// numbered row strip major, x fastest).
+struct TileRef {
+    int32_t rep;
+    int32_t local0;
+    int32_t n;
     int32_t pad;
 };
+constexpr int kTilesPerRun = 8;
 
 template <class S>
 hipError_t launch_step(const StepArgs<S> &a, dim3 grid, int nt, int rb, hipStream_t s);
 // A batch group: n members with the same storage type and kernel form.
-// reps: device array of member descriptors; offs: device prefix sums of
-// their tile counts (offs[n] = total tiles).
+// reps: device array of member descriptors; table: the group's tiles;
+// count: device word holding how many table entries the next launch runs.
+// grid: blocks launched (each runs table entries blockIdx.x + i * grid).
 template <class S>
-hipError_t launch_step_batch(BatchRep<S> *const *reps, const int32_t *offs, int n, int total,
-                             int vec, int nt, int vb_or_rb, int k, hipStream_t s);
+hipError_t launch_step_batch(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
+                             int grid, int vec, int nt, int vb_or_rb, int k, hipStream_t s);
+// Rebuild the table of a windowed group from its members' live rows.
+template <class S>
+hipError_t launch_plan_batch(BatchRep<S> *const *reps, int n, TileRef *table, int32_t *count,
+                             hipStream_t s);
 template <class S>
 hipError_t launch_finalize_batch(BatchRep<S> *const *reps, int n, int k, hipStream_t s);
 template <class S>

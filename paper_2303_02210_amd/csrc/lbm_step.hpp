@@ -19,12 +19,58 @@
 #include "lbm_device.hpp"
 #include "lbm_internal.hpp"
 #include <climits>
+#include <type_traits>
 
 namespace lbm {
 
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
+// Population buffers always live in global memory; saying so lets the
+// compiler use global (not flat) loads and stores for pointers that were read
+// from memory (batch descriptors).
+#define LBM_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ const T LBM_GLOBAL *as_global(const T *p)
+{
+    return (const T LBM_GLOBAL *)p;
+}
+template <class T>
+__device__ __forceinline__ T LBM_GLOBAL *as_global(T *p)
+{
+    return (T LBM_GLOBAL *)p;
+}
+
+// Storage types as they sit in memory: the 16-bit formats are accessed as
+// raw 16-bit words (their C++ classes cannot be assigned through
+// address-space-qualified pointers) and converted bit for bit.
+template <class S>
+using MemT = typename std::conditional<sizeof(S) == 2, uint16_t, S>::type;
+
+template <class S>
+__device__ __forceinline__ S from_mem(MemT<S> v)
+{
+    if constexpr (sizeof(S) == 2) {
+        S r;
+        __builtin_memcpy(&r, &v, 2);
+        return r;
+    } else {
+        return v;
+    }
+}
+template <class S>
+__device__ __forceinline__ MemT<S> to_mem(S v)
+{
+    if constexpr (sizeof(S) == 2) {
+        uint16_t r;
+        __builtin_memcpy(&r, &v, 2);
+        return r;
+    } else {
+        return v;
+    }
+}
+
 template <class R>
 __device__ __forceinline__ R sum9(const R v[9])
 {
@@ -280,8 +326,8 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
     const Tiles tl = a.tl;
     const int64_t cx = tl.col(x), cxm = tl.col(xm), cxp = tl.col(xp);
     const int tws = tl.tws;
-    const S *__restrict__ F = io.fin;
-    S *__restrict__ G = io.fout;
+    const MemT<S> LBM_GLOBAL *__restrict__ F = as_global(reinterpret_cast<const MemT<S> *>(io.fin));
+    MemT<S> LBM_GLOBAL *__restrict__ G = as_global(reinterpret_cast<MemT<S> *>(io.fout));
     int rnext = (a.mode == kModeDevice) ? (int)((y_wall + j0) % H) : j0;
 
     for (int jb = j0; jb < jend; jb += RB) {
@@ -296,20 +342,20 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
             if (j < jend) {
                 const RowSrc &s = src[k];
                 // ---- step 1: pull-stream; the wall reflects in place -----
-                const S *row0 = F + (int64_t)s.r0 * tl.rs;
-                const S *rowm = F + (int64_t)(s.below ? s.r0 : s.rm) * tl.rs;
-                const S *rowp = F + (int64_t)s.rp * tl.rs;
+                const MemT<S> LBM_GLOBAL *row0 = F + (int64_t)s.r0 * tl.rs;
+                const MemT<S> LBM_GLOBAL *rowm = F + (int64_t)(s.below ? s.r0 : s.rm) * tl.rs;
+                const MemT<S> LBM_GLOBAL *rowp = F + (int64_t)s.rp * tl.rs;
                 const int qn2 = s.below ? 4 : 2, qn5 = s.below ? 7 : 5, qn6 = s.below ? 8 : 6;
                 const int64_t cn5 = s.below ? cx : cxm, cn6 = s.below ? cx : cxp;
-                raw[k][0] = row0[cx + (0 << tws)];
-                raw[k][1] = row0[cxm + (1 << tws)];
-                raw[k][3] = row0[cxp + (3 << tws)];
-                raw[k][2] = rowm[cx + (qn2 << tws)];
-                raw[k][5] = rowm[cn5 + (qn5 << tws)];
-                raw[k][6] = rowm[cn6 + (qn6 << tws)];
-                raw[k][4] = rowp[cx + (4 << tws)];
-                raw[k][7] = rowp[cxp + (7 << tws)];
-                raw[k][8] = rowp[cxm + (8 << tws)];
+                raw[k][0] = from_mem<S>(row0[cx + (0 << tws)]);
+                raw[k][1] = from_mem<S>(row0[cxm + (1 << tws)]);
+                raw[k][3] = from_mem<S>(row0[cxp + (3 << tws)]);
+                raw[k][2] = from_mem<S>(rowm[cx + (qn2 << tws)]);
+                raw[k][5] = from_mem<S>(rowm[cn5 + (qn5 << tws)]);
+                raw[k][6] = from_mem<S>(rowm[cn6 + (qn6 << tws)]);
+                raw[k][4] = from_mem<S>(rowp[cx + (4 << tws)]);
+                raw[k][7] = from_mem<S>(rowp[cxp + (7 << tws)]);
+                raw[k][8] = from_mem<S>(rowp[cxm + (8 << tws)]);
             }
         }
 #pragma unroll
@@ -345,10 +391,10 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
             double m_site = 0.0, s_site = 0.0, x_site = 0.0;
             const bool tissue =
                 site_step<S>(a, io.t, v, fs, Wd, so, x, y, y_wall, hp, m_site, s_site, x_site);
-            S *rowg = G + (int64_t)s.r0 * tl.rs + cx;
+            MemT<S> LBM_GLOBAL *rowg = G + (int64_t)s.r0 * tl.rs + cx;
             if (active) {
 #pragma unroll
-                for (int i = 0; i < 9; ++i) rowg[i << tws] = so[i];
+                for (int i = 0; i < 9; ++i) rowg[i << tws] = to_mem<S>(so[i]);
                 m_acc += m_site;
                 s_acc += s_site;
                 x_acc += x_site;
@@ -447,15 +493,16 @@ __device__ __forceinline__ void put_el(typename RawVec<ND>::type &v, int i, S s)
     }
 }
 
-template <int ND>
-__device__ __forceinline__ typename RawVec<ND>::type vload(const void *p)
+template <int ND, class T>
+__device__ __forceinline__ typename RawVec<ND>::type vload(const T LBM_GLOBAL *p)
 {
-    return __builtin_nontemporal_load(reinterpret_cast<const typename RawVec<ND>::type *>(p));
+    return __builtin_nontemporal_load(
+        reinterpret_cast<const typename RawVec<ND>::type LBM_GLOBAL *>(p));
 }
-template <int ND>
-__device__ __forceinline__ void vstore(void *p, const typename RawVec<ND>::type &v)
+template <int ND, class T>
+__device__ __forceinline__ void vstore(T LBM_GLOBAL *p, const typename RawVec<ND>::type &v)
 {
-    __builtin_nontemporal_store(v, reinterpret_cast<typename RawVec<ND>::type *>(p));
+    __builtin_nontemporal_store(v, reinterpret_cast<typename RawVec<ND>::type LBM_GLOBAL *>(p));
 }
 
 // The left lane's last element (inside the wave) or the edge value.
@@ -525,16 +572,16 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
     // lanes past the last column read (and never store) the last vector, so
     // every access stays inside the row
     const int64_t cv = tl.col(active ? xv : L - V), cl = tl.col(xl), cr = tl.col(xr);
-    const S *__restrict__ F = io.fin;
-    S *__restrict__ G = io.fout;
+    const MemT<S> LBM_GLOBAL *__restrict__ F = as_global(reinterpret_cast<const MemT<S> *>(io.fin));
+    MemT<S> LBM_GLOBAL *__restrict__ G = as_global(reinterpret_cast<MemT<S> *>(io.fout));
     int r0 = (a.mode == kModeDevice) ? (int)((y_wall + j0) % H) : j0;
 
     for (int j = j0; j < jend; ++j) {
         const int64_t y = y_wall + j;
         const RowSrc s = row_sources(a.mode, j, r0, H, y, y_top);
-        const S *row0 = F + (int64_t)s.r0 * tl.rs;
-        const S *rowm = F + (int64_t)(s.below ? s.r0 : s.rm) * tl.rs;
-        const S *rowp = F + (int64_t)s.rp * tl.rs;
+        const MemT<S> LBM_GLOBAL *row0 = F + (int64_t)s.r0 * tl.rs;
+        const MemT<S> LBM_GLOBAL *rowm = F + (int64_t)(s.below ? s.r0 : s.rm) * tl.rs;
+        const MemT<S> LBM_GLOBAL *rowp = F + (int64_t)s.rp * tl.rs;
         // directions feeding N, NE, NW: the row below, or this site reflected
         const int qn2 = s.below ? 4 : 2, qn5 = s.below ? 7 : 5, qn6 = s.below ? 8 : 6;
 
@@ -548,9 +595,9 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
         const VT A4 = vload<ND>(rowp + cv + (4 << tws));
         const VT A7 = vload<ND>(rowp + cv + (7 << tws));
         const VT A8 = vload<ND>(rowp + cv + (8 << tws));
-        const S e1 = row0[cl + (1 << tws)], e3 = row0[cr + (3 << tws)];
-        const S e5 = rowm[cl + (5 << tws)], e6 = rowm[cr + (6 << tws)];
-        const S e7 = rowp[cr + (7 << tws)], e8 = rowp[cl + (8 << tws)];
+        const S e1 = from_mem<S>(row0[cl + (1 << tws)]), e3 = from_mem<S>(row0[cr + (3 << tws)]);
+        const S e5 = from_mem<S>(rowm[cl + (5 << tws)]), e6 = from_mem<S>(rowm[cr + (6 << tws)]);
+        const S e7 = from_mem<S>(rowp[cr + (7 << tws)]), e8 = from_mem<S>(rowp[cl + (8 << tws)]);
         // neighbours across lanes (E-type: from x-1, W-type: from x+1)
         const S n1 = from_left<S, ND>(A1, e1, edge_l);
         const S n8 = from_left<S, ND>(A8, e8, edge_l);
@@ -614,7 +661,7 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
             }
         }
         if (active) {
-            S *rowg = G + (int64_t)s.r0 * tl.rs + cv;
+            MemT<S> LBM_GLOBAL *rowg = G + (int64_t)s.r0 * tl.rs + cv;
 #pragma unroll
             for (int i = 0; i < 9; ++i) vstore<ND>(rowg + (i << tws), O[i]);
         }
@@ -882,21 +929,6 @@ __global__ __launch_bounds__(kRedThreads) void finalize_kernel(FinalizeArgs<S> a
 // a solo run.  Per-step buffers and slots follow from the member's step count.
 // ---------------------------------------------------------------------------
 template <class S>
-__device__ __forceinline__ const BatchRep<S> *batch_locate(BatchRep<S> *const *reps,
-                                                           const int32_t *offs, int n, int lin,
-                                                           int &local)
-{
-    int lo = 0, hi = n;   // offs[lo] <= lin < offs[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (offs[mid] <= lin) lo = mid;
-        else hi = mid;
-    }
-    local = lin - offs[lo];
-    return reps[lo];
-}
-
-template <class S>
 __device__ __forceinline__ StepIO<S> batch_io(const BatchRep<S> *R, int k)
 {
     const int64_t tt = R->t0 + k;
@@ -911,26 +943,104 @@ __device__ __forceinline__ StepIO<S> batch_io(const BatchRep<S> *R, int k)
     return io;
 }
 
-template <class S, int NT, int ND>
-__global__ __launch_bounds__(NT) void step_batch_vec(BatchRep<S> *const *reps, const int32_t *offs,
-                                                     int n, int total, int k)
+// Copy a member descriptor from global memory into LDS (one dword per
+// thread); the tile bodies then read its fields from LDS.
+template <int NT>
+__device__ __forceinline__ void stage_dwords(const void *src, uint32_t *lds, int ndw)
 {
-    int local;
-    const BatchRep<S> *R = batch_locate(reps, offs, n, xcd_order(blockIdx.x, total), local);
-    const StepArgs<S> a = R->a;
-    const StepIO<S> io = batch_io(R, k);
-    step_vec_tile<S, NT, ND>(a, io, local % R->gx, local / R->gx, R->gx);
+    const uint32_t *g = reinterpret_cast<const uint32_t *>(src);
+    __syncthreads();
+    for (int i = threadIdx.x; i < ndw; i += NT) lds[i] = g[i];
+    __syncthreads();
 }
 
-template <class S, int NT, int RB>
-__global__ __launch_bounds__(NT) void step_batch_scalar(BatchRep<S> *const *reps,
-                                                        const int32_t *offs, int n, int total, int k)
+// Each table entry is a run of up to kTilesPerRun tiles of one member, so
+// a block fetches the member's descriptor once (through LDS, into scalar
+// registers) and then runs the tiles back to back.  Windowed groups launch a
+// fixed grid that strides over the entries.
+template <class S, int NT, int ND, bool VEC>
+__global__ __launch_bounds__(NT) void step_batch(BatchRep<S> *const *reps, const TileRef *table,
+                                                 const int32_t *count, int k)
 {
-    int local;
-    const BatchRep<S> *R = batch_locate(reps, offs, n, xcd_order(blockIdx.x, total), local);
-    const StepArgs<S> a = R->a;
-    const StepIO<S> io = batch_io(R, k);
-    step_scalar_tile<S, NT, RB>(a, io, local % R->gx, local / R->gx, R->gx);
+    static_assert(sizeof(BatchRep<S>) % 4 == 0, "descriptor is staged as dwords");
+    __shared__ uint32_t stage[sizeof(BatchRep<S>) / 4];
+    const BatchRep<S> &R = *reinterpret_cast<const BatchRep<S> *>(stage);
+    const int total = *count;
+    for (int c = blockIdx.x; c < total; c += gridDim.x) {
+        const TileRef e = table[xcd_order(c, total)];
+        stage_dwords<NT>(reps[e.rep], stage, (int)(sizeof(BatchRep<S>) / 4));
+        const StepIO<S> io = batch_io(&R, k);
+        for (int i = 0; i < e.n; ++i) {
+            const int local = e.local0 + i;
+            if constexpr (VEC) step_vec_tile<S, NT, ND>(R.a, io, local % R.gx, local / R.gx, R.gx);
+            else step_scalar_tile<S, NT, ND>(R.a, io, local % R.gx, local / R.gx, R.gx);
+        }
+    }
+}
+
+// Tile table of a windowed group: each member contributes the tiles of its
+// live rows (the first n_rows window rows, as set by its last finalize).
+// One block: tile counts, exclusive scan, then the entries.
+__device__ __forceinline__ int live_tiles(int32_t gx, int32_t ty, int32_t nblocks, int window,
+                                          int64_t n_rows)
+{
+    if (!window) return nblocks;
+    const int64_t strips = (n_rows + ty - 1) / ty;
+    const int64_t c = strips * gx;
+    return c < nblocks ? (int)c : nblocks;
+}
+
+template <class S>
+__global__ __launch_bounds__(kRedThreads) void plan_batch(BatchRep<S> *const *reps, int n,
+                                                          TileRef *table, int32_t *count)
+{
+    __shared__ int32_t pre[kRedThreads + 1];
+    __shared__ int32_t live_sh[kRedThreads];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += kRedThreads) {
+        const int i = base + threadIdx.x;
+        int c = 0, live = 0;
+        if (i < n) {
+            const BatchRep<S> *R = reps[i];
+            live = live_tiles(R->gx, R->ty, R->nblocks, R->window, R->a.st->n_rows);
+            c = (live + kTilesPerRun - 1) / kTilesPerRun;      // runs of this member
+        }
+        live_sh[threadIdx.x] = live;
+        // inclusive scan of this chunk (Hillis-Steele)
+        pre[threadIdx.x] = c;
+        __syncthreads();
+        for (int off = 1; off < kRedThreads; off <<= 1) {
+            const int v = threadIdx.x >= off ? pre[threadIdx.x - off] : 0;
+            __syncthreads();
+            pre[threadIdx.x] += v;
+            __syncthreads();
+        }
+        __syncthreads();
+        // entries of this chunk's members, filled by the whole block
+        const int m_end = min(n - base, kRedThreads);
+        for (int m = 0; m < m_end; ++m) {
+            const int cm = pre[m] - (m ? pre[m - 1] : 0);
+            const int s0 = carry + (m ? pre[m - 1] : 0);
+            const int live = live_sh[m];
+            for (int l = threadIdx.x; l < cm; l += kRedThreads) {
+                const int first = l * kTilesPerRun;
+                table[s0 + l] = TileRef{base + m, first, min(kTilesPerRun, live - first), 0};
+            }
+            // tiles that ran last step but not this one: their mass tally
+            // would otherwise stay behind (a solo launch writes 0 there)
+            BatchRep<S> *R = reps[base + m];
+            const int last = R->last_live;
+            for (int b = live + threadIdx.x; b < last; b += kRedThreads) R->a.partials[4 * b] = 0.0;
+            __syncthreads();
+            if (threadIdx.x == 0) R->last_live = live;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry += pre[m_end - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = carry;
 }
 
 template <class S>
@@ -1026,32 +1136,42 @@ hipError_t launch_finalize(const FinalizeArgs<S> &a, hipStream_t s)
 }
 
 template <class S, int NT>
-void launch_batch_nt(BatchRep<S> *const *reps, const int32_t *offs, int n, int total, int vec,
-                     int vb_or_rb, int k, hipStream_t s)
+void launch_batch_nt(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
+                     int grid, int vec, int vb_or_rb, int k, hipStream_t s)
 {
-    const dim3 g(total), b(NT);
+    const dim3 g(grid), b(NT);
     if (vec) {
         if (vb_or_rb == 4) {
-            if constexpr (sizeof(S) <= 4) hipLaunchKernelGGL((step_batch_vec<S, NT, 1>), g, b, 0, s, reps, offs, n, total, k);
+            if constexpr (sizeof(S) <= 4)
+                hipLaunchKernelGGL((step_batch<S, NT, 1, true>), g, b, 0, s, reps, table, count, k);
         } else if (vb_or_rb == 8) {
-            hipLaunchKernelGGL((step_batch_vec<S, NT, 2>), g, b, 0, s, reps, offs, n, total, k);
+            hipLaunchKernelGGL((step_batch<S, NT, 2, true>), g, b, 0, s, reps, table, count, k);
         } else {
-            hipLaunchKernelGGL((step_batch_vec<S, NT, 4>), g, b, 0, s, reps, offs, n, total, k);
+            hipLaunchKernelGGL((step_batch<S, NT, 4, true>), g, b, 0, s, reps, table, count, k);
         }
     } else {
-        if (vb_or_rb >= 2) hipLaunchKernelGGL((step_batch_scalar<S, NT, 2>), g, b, 0, s, reps, offs, n, total, k);
-        else hipLaunchKernelGGL((step_batch_scalar<S, NT, 1>), g, b, 0, s, reps, offs, n, total, k);
+        if (vb_or_rb >= 2) hipLaunchKernelGGL((step_batch<S, NT, 2, false>), g, b, 0, s, reps, table, count, k);
+        else hipLaunchKernelGGL((step_batch<S, NT, 1, false>), g, b, 0, s, reps, table, count, k);
     }
 }
 
 template <class S>
-hipError_t launch_step_batch(BatchRep<S> *const *reps, const int32_t *offs, int n, int total,
-                             int vec, int nt, int vb_or_rb, int k, hipStream_t s)
+hipError_t launch_step_batch(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
+                             int grid, int vec, int nt, int vb_or_rb, int k, hipStream_t s)
 {
-    if (total <= 0) return hipSuccess;
-    if (nt == 256) launch_batch_nt<S, 256>(reps, offs, n, total, vec, vb_or_rb, k, s);
-    else if (nt == 128) launch_batch_nt<S, 128>(reps, offs, n, total, vec, vb_or_rb, k, s);
-    else launch_batch_nt<S, 64>(reps, offs, n, total, vec, vb_or_rb, k, s);
+    if (grid <= 0) return hipSuccess;
+    if (nt == 256) launch_batch_nt<S, 256>(reps, table, count, grid, vec, vb_or_rb, k, s);
+    else if (nt == 128) launch_batch_nt<S, 128>(reps, table, count, grid, vec, vb_or_rb, k, s);
+    else launch_batch_nt<S, 64>(reps, table, count, grid, vec, vb_or_rb, k, s);
+    return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_plan_batch(BatchRep<S> *const *reps, int n, TileRef *table, int32_t *count,
+                             hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((plan_batch<S>), dim3(1), dim3(kRedThreads), 0, s, reps, n, table, count);
     return hipGetLastError();
 }
 

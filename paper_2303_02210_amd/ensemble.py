@@ -9,6 +9,12 @@ from . import _ffi
 from .sim import Sim, _torch
 
 
+def tiles(cfg: dict) -> int:
+    """Thread blocks per step of a simulation with this workload dict."""
+    p = _ffi.make_params(cfg)
+    return int(_ffi.lib().lbm_tiles(ctypes.byref(p)))
+
+
 class Ensemble:
     """A set of ``Sim`` members stepped together on one stream.
 
@@ -16,18 +22,23 @@ class Ensemble:
     priority torch stream unless one is given), which the graph capture needs.
     """
 
-    def __init__(self, cfgs=(), device: str = "cuda:0", stream=None, max_members: int = 1024):
+    def __init__(self, cfgs=(), device: str = "cuda:0", stream=None, max_members: int = 1024,
+                 max_tiles: int | None = None):
         torch = _torch()
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self._lib = _ffi.lib()
-        self.max_members = int(max_members)
-        nbytes = int(self._lib.lbm_batch_workspace_bytes(self.max_members))
+        cfgs = list(cfgs)
+        self.max_members = max(int(max_members), len(cfgs))
+        if max_tiles is None:
+            max_tiles = max(1 << 20, sum(tiles(c) for c in cfgs))
+        self.max_tiles = int(max_tiles)
+        nbytes = int(self._lib.lbm_batch_workspace_bytes(self.max_members, self.max_tiles))
         self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         b = ctypes.c_void_p()
         rc = self._lib.lbm_batch_create(ctypes.c_void_p(self._ws.data_ptr()), nbytes,
-                                        self.max_members, ctypes.c_void_p(self.stream.cuda_stream),
-                                        ctypes.byref(b))
+                                        self.max_members, self.max_tiles,
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(b))
         if rc != 0:
             raise _ffi.LbmError(rc, "lbm_batch_create")
         self._b = b

@@ -1,0 +1,167 @@
+"""Continuous batching of simulation requests on one GPU.
+
+Requests (workload dicts with a step count and an arrival time) are admitted
+in arrival order whenever their device workspace fits the HBM budget, join the
+running ensemble at the next tick, and leave it as soon as their own step
+count is reached; runs that arrive while others are on the GPU therefore share
+every launch with them.  Each tick advances all resident runs by the same
+number of steps (at most ``tick_steps``, never past a run's end) through the
+batch API and copies every run's front heights h(x) back to pinned host
+memory.  Results are those of the run stepped alone: the batch changes only
+how tiles are grouped into launches.
+"""
+from __future__ import annotations
+
+import collections
+import ctypes
+import time
+
+import numpy as np
+
+from . import _ffi
+from .ensemble import Ensemble, tiles
+from .sim import _torch
+
+
+def workspace_bytes(cfg: dict) -> int:
+    p = _ffi.make_params(cfg)
+    return int(_ffi.lib().lbm_workspace_bytes(ctypes.byref(p)))
+
+
+class Run:
+    """One admitted request."""
+
+    def __init__(self, req: dict, sim, arrival: float, admitted: float, pinned):
+        self.req = req
+        self.sim = sim
+        self.arrival = arrival
+        self.admitted = admitted
+        self.remaining = int(req["steps"])
+        self.h = pinned              # latest streamed front heights (pinned host)
+        self.h_updates = 0
+        self.finished = None
+        self.diag = None
+
+
+class Server:
+    def __init__(self, hbm_budget: float = 200e9, tick_steps: int = 100, device: str = "cuda:0",
+                 max_members: int = 1024, max_tiles: int = 1 << 23, keep_results: bool = False,
+                 clock=time.perf_counter):
+        torch = _torch()
+        self.torch = torch
+        self.ens = Ensemble(device=device, max_members=max_members, max_tiles=max_tiles)
+        self.budget = float(hbm_budget)
+        self.used = 0.0
+        self.tick_steps = int(tick_steps)
+        self.max_members = int(max_members)
+        self.queue: collections.deque = collections.deque()
+        self.running: list[Run] = []
+        self.done: list[Run] = []
+        self.keep_results = keep_results
+        self.clock = clock
+        self.t0 = None
+        self.site_updates = 0.0
+        self.gpu_busy = 0.0
+        self.ticks = 0
+
+    def now(self) -> float:
+        return self.clock() - self.t0
+
+    def submit(self, req: dict) -> None:
+        self.queue.append(req)
+
+    # -- admission ---------------------------------------------------------
+    def _admit(self, now: float) -> int:
+        n = 0
+        while self.queue and self.queue[0].get("arrival_s", 0.0) <= now:
+            req = self.queue[0]
+            need = workspace_bytes(req)
+            if need == 0:
+                raise ValueError(f"invalid request {req.get('name')}")
+            if self.used + need > self.budget or len(self.running) >= self.max_members:
+                break
+            self.queue.popleft()
+            sim = self.ens.add(req)
+            pinned = self.torch.empty(int(req["L"]), dtype=self.torch.int32).pin_memory()
+            self.running.append(Run(req, sim, req.get("arrival_s", 0.0), now, pinned))
+            self.used += need
+            n += 1
+        return n
+
+    # -- one tick ---------------------------------------------------------------
+    def tick(self) -> None:
+        k = min([self.tick_steps] + [r.remaining for r in self.running])
+        ev0 = self.torch.cuda.Event(enable_timing=True)
+        ev1 = self.torch.cuda.Event(enable_timing=True)
+        ev0.record(self.ens.stream)
+        self.ens.step(k)
+        ev1.record(self.ens.stream)
+        for r in self.running:
+            r.sim.front_heights_async(r.h)
+        self.ens.synchronize()
+        self.gpu_busy += ev0.elapsed_time(ev1) / 1e3
+        self.ticks += 1
+        now = self.now()
+        still = []
+        for r in self.running:
+            r.remaining -= k
+            r.h_updates += 1
+            self.site_updates += float(r.req["L"]) * float(r.req["H"]) * k
+            if r.remaining == 0:
+                r.finished = now
+                r.diag = r.sim.diagnostics()
+                if self.keep_results:
+                    r.result = (r.sim.populations(), r.sim.front_heights(), r.diag)
+                self.ens.remove(r.sim)
+                r.sim.close()
+                r.sim = None
+                self.used -= workspace_bytes(r.req)
+                self.done.append(r)
+            else:
+                still.append(r)
+        self.running = still
+
+    # -- the loop -----------------------------------------------------------------
+    def serve(self, requests, time_limit: float | None = None, log=None) -> dict:
+        """Replay a request trace in real time; returns the summary."""
+        for q in sorted(requests, key=lambda q: q.get("arrival_s", 0.0)):
+            self.submit(q)
+        self.t0 = self.clock()
+        while self.queue or self.running:
+            now = self.now()
+            if time_limit is not None and now > time_limit:
+                break
+            self._admit(now)
+            if not self.running:
+                if self.queue:
+                    time.sleep(max(0.0, min(self.queue[0].get("arrival_s", 0.0) - now, 0.05)))
+                continue
+            self.tick()
+            if log and self.ticks % 50 == 0:
+                log(f"t={self.now():.1f}s ticks={self.ticks} running={len(self.running)} "
+                    f"queued={len(self.queue)} done={len(self.done)}")
+        return self.summary()
+
+    def summary(self) -> dict:
+        wall = self.now()
+        lat = np.array([r.finished - r.arrival for r in self.done]) if self.done else np.zeros(0)
+        return {
+            "completed": len(self.done), "running": len(self.running), "queued": len(self.queue),
+            "wall_s": wall,
+            "runs_per_hour": len(self.done) / wall * 3600 if wall > 0 else 0.0,
+            "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
+            "mean_latency_s": float(lat.mean()) if lat.size else None,
+            "site_updates": self.site_updates,
+            "mlups_nominal": self.site_updates / wall / 1e6 if wall > 0 else 0.0,
+            "gpu_busy_frac": self.gpu_busy / wall if wall > 0 else 0.0,
+            "ticks": self.ticks,
+        }
+
+    def close(self) -> None:
+        for r in self.running:
+            if r.sim is not None:
+                self.ens.remove(r.sim)
+                r.sim.close()
+        self.running = []
+        self.ens.close()

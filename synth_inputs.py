@@ -88,8 +88,9 @@ def served_trace(n: int = 600, rate_hz: float = 20.0, seed: int = 0,
     L uniform over powers of two in [128, 4096]; H uniform in [2L, 4L]
     rounded to 64; steps uniform in steps_range; growth bulk (1e-4) or front
     band (ell = 8, 1e-3) with equal odds; precision FP64 / FP32 / FP16-offset
-    with equal odds; tissue initially in the first quarter; rear wall that
-    follows the front.
+    with equal odds; tissue initially in the first 128 rows; rear wall that
+    follows the front (gap max(50, 10 w)); only rows that can hold mass are
+    swept.
     """
     rng = np.random.default_rng(seed)
     t = 0.0
@@ -101,8 +102,8 @@ def served_trace(n: int = 600, rate_hz: float = 20.0, seed: int = 0,
         steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
         edge = bool(rng.integers(0, 2))
         prec = ["fp64", "fp32", "fp16"][int(rng.integers(0, 3))]
-        c = cfg(name=f"req{k}", L=L, H=H, init_rows=H // 4, sigma=1e-3,
-                ybc="follow", precision=prec, steps=steps, seed=k, replica=0,
+        c = cfg(name=f"req{k}", L=L, H=H, init_rows=128, sigma=1e-3,
+                ybc="follow", window=True, precision=prec, steps=steps, seed=k, replica=0,
                 arrival_s=t)
         if edge:
             c.update(growth_rate=1e-3, region="front_band", region_width=8)

@@ -42,6 +42,10 @@ MIXED = [
            precision="fp64", seed=7),
     si.cfg(L=128, H=256, init_rows=40, sigma=1e-3, growth_rate=3e-3, window=True, precision="fp32",
            seed=8),
+    si.cfg(L=96, H=160, init_rows=100, sigma=1e-2, growth_rate=1e-2, ybc="follow", wall_min_gap=10,
+           window=True, precision="fp64", seed=9),
+    si.cfg(L=128, H=192, init_rows=100, sigma=1e-3, growth_rate=5e-3, ybc="follow", wall_min_gap=10,
+           window=True, precision="fp16", seed=10),
 ]
 
 
@@ -98,3 +102,27 @@ def test_batch_member_fault_is_its_own():
     ens.step(3)
     ens.synchronize()
     _same(good, _solo(ok, 403), "good")
+
+
+def test_server_results_equal_solo_runs():
+    """Continuous batching: requests join and leave the running batch at
+    different times; each finished run equals the same run stepped alone."""
+    from paper_2303_02210_amd.serve import Server
+    reqs = []
+    for k, (L, H, prec, steps, t) in enumerate([
+            (128, 256, "fp32", 230, 0.0), (64, 192, "fp64", 150, 0.0), (256, 512, "fp16", 310, 0.0),
+            (128, 384, "fp32", 120, 0.05), (192, 256, "bf16", 90, 0.1), (64, 128, "fp64", 260, 0.1)]):
+        reqs.append(si.cfg(name=f"r{k}", L=L, H=H, init_rows=100, sigma=1e-3, growth_rate=2e-3,
+                           ybc="follow", wall_min_gap=20, window=True, precision=prec,
+                           steps=steps, seed=k, arrival_s=t))
+    srv = Server(hbm_budget=4e9, tick_steps=40, keep_results=True)
+    summ = srv.serve(reqs)
+    srv.close()
+    assert summ["completed"] == len(reqs) and summ["p99_latency_s"] is not None
+    for r in srv.done:
+        f, h, d = r.result
+        ref = _solo(r.req, r.req["steps"])
+        assert np.array_equal(f, ref[0]), r.req["name"]
+        assert np.array_equal(h, ref[1]), r.req["name"]
+        assert d["step"] == r.req["steps"] and d["y_wall"] == ref[2]["y_wall"]
+        assert r.h_updates >= r.req["steps"] // 40
