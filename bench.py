@@ -100,11 +100,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=600, help="served: trace length")
     ap.add_argument("--time-limit", type=float, default=300.0, help="served: wall-clock limit (s)")
-    ap.add_argument("--workload", default="bulk", choices=["bulk", "edge", "ensemble", "served"],
+    ap.add_argument("--out", default=None, help="precision: write the curves to this JSON file")
+    ap.add_argument("--workload", default="bulk",
+                    choices=["bulk", "edge", "ensemble", "served", "precision"],
                     help="bulk: 4096 x 4096 bulk growth (default); edge: 2048 x 8192 growth "
                          "within 8 rows of the front; ensemble: 256 replicas of uneven size, "
                          "batched, against the same runs stepped one after another")
     ap.add_argument("--tuned", action="store_true", help="launch shapes from the autotuner cache")
+    ap.add_argument("--shape", default=None, help="force a launch shape: kernel_vb,kernel_ty")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -121,11 +124,16 @@ def main():
         return bench_ensemble(args)
     if args.workload == "served":
         return bench_served(args)
+    if args.workload == "precision":
+        return bench_precision(args)
     base = si.BULK_4096_FP32 if args.workload == "bulk" else si.EDGE_2048x8192
     cfg = dict(base, precision=args.precision)
     if args.tuned:
         from paper_2303_02210_amd import autotune
         cfg = autotune.apply(cfg)
+    if args.shape:
+        v = [int(x) for x in args.shape.split(",")]
+        cfg.update(kernel_vb=v[0], kernel_ty=v[1])
     L, H = cfg["L"], cfg["H"]
     bpu = 2 * 9 * STORE_BYTES[args.precision]          # read 9 + write 9 populations
 
@@ -304,6 +312,107 @@ def bench_served(args):
         "gpu_busy_frac": round(summ["gpu_busy_frac"], 4), "wall_s": round(summ["wall_s"], 2),
         "roofline": None, "cpu_baseline": None,
     }
+    print(json.dumps(out), flush=True)
+
+
+def _curves(sims, steps, every, stream_sync):
+    """Advance sims together and record hbar(t), W(t) and mass every `every`
+    steps (sims: an Ensemble)."""
+    import numpy as np
+    rec = {"t": [], "hbar": [], "W": [], "mass": []}
+    done = 0
+    while done < steps:
+        n = min(every, steps - done)
+        sims.step(n)
+        done += n
+        stream_sync()
+        ds = [m.diagnostics() for m in sims.members]
+        rec["t"].append(done)
+        rec["hbar"].append([d["hbar"] for d in ds])
+        rec["W"].append([d["W"] for d in ds])
+        rec["mass"].append([d["mass"] - d["src_total"] - d["fix_total"] + d["retired"] for d in ds])
+    return {k: np.asarray(v) for k, v in rec.items()}
+
+
+def bench_precision(args):
+    """W(L,t), mean front height and mass balance of the float32 and 16-bit
+    offset storages against float64 (bit-identical to the oracle).  (a) The
+    2048 x 8192 edge-growth strip at full size, one run per storage; (b) the
+    same model at 256 x 1024 as 8 seeds per storage, batched, for means and
+    95% intervals."""
+    import numpy as np
+    import synth_inputs as si
+    from paper_2303_02210_amd import Ensemble
+
+    precs = ["fp64", "fp32", "fp16", "bf16"]
+    steps = args.steps
+    every = max(100, steps // 100)
+    res = {"full": {}, "seeds": {}}
+    # (a) full size, all four storages in one batch
+    cfgs = [dict(si.EDGE_2048x8192, precision=p) for p in precs]
+    ens = Ensemble(cfgs)
+    log(f"precision (a): 2048x8192 x {steps} steps, {precs}")
+    c = _curves(ens, steps, every, ens.synchronize)
+    ens.close()
+    for m in ens.members:
+        m.close()
+    ref_h, ref_W = c["hbar"][:, 0], c["W"][:, 0]
+    m0 = c["mass"][0]
+    for i, p in enumerate(precs):
+        res["full"][p] = {
+            "hbar_final": float(c["hbar"][-1, i]), "W_final": float(c["W"][-1, i]),
+            "max_abs_dhbar": float(np.max(np.abs(c["hbar"][:, i] - ref_h))),
+            "max_rel_dW": float(np.max(np.abs(c["W"][:, i] - ref_W) / np.maximum(ref_W, 1e-9))),
+            "mass_balance_drift_rel": float(np.max(np.abs(c["mass"][:, i] - m0[i])) / m0[i]),
+        }
+    res["full_curves"] = {"t": c["t"].tolist(), "hbar": c["hbar"].tolist(), "W": c["W"].tolist()}
+    # (b) 8 seeds x 4 storages at 256 x 1024
+    nseed = 8
+    small = []
+    for p in precs:
+        for sd in range(nseed):
+            small.append(dict(si.EDGE_2048x8192, name=f"edge256_{p}_s{sd}", L=256, H=1024,
+                              init_rows=128, precision=p, seed=100 + sd, replica=sd))
+    ens = Ensemble(small)
+    log(f"precision (b): 256x1024 x {steps} steps, {nseed} seeds x {precs}")
+    c = _curves(ens, steps, every, ens.synchronize)
+    ens.close()
+    for m in ens.members:
+        m.close()
+    W = c["W"].reshape(len(c["t"]), len(precs), nseed)
+    Hb = c["hbar"].reshape(len(c["t"]), len(precs), nseed)
+    # time at which each run's front first leaves its initial row
+    t_arr = np.asarray(c["t"])
+    init_h = float(small[0]["init_rows"])
+    adv = np.where((Hb > init_h + 0.5).any(0), t_arr[np.argmax(Hb > init_h + 0.5, axis=0)], -1)
+    for i, p in enumerate(precs):
+        dW = W[:, i].mean(1) - W[:, 0].mean(1)
+        seW = np.sqrt(W[:, i].var(1, ddof=1) / nseed + W[:, 0].var(1, ddof=1) / nseed)
+        dH = Hb[:, i].mean(1) - Hb[:, 0].mean(1)
+        seH = np.sqrt(Hb[:, i].var(1, ddof=1) / nseed + Hb[:, 0].var(1, ddof=1) / nseed)
+        ta = adv[i][adv[i] >= 0]
+        res["seeds"][p] = {
+            "front_starts_t_mean": float(ta.mean()) if ta.size else None,
+            "front_starts_t_ci95": float(1.96 * ta.std(ddof=1) / np.sqrt(ta.size)) if ta.size > 1 else None,
+            "runs_advanced": int(ta.size),
+            "W_mean_final": float(W[-1, i].mean()), "W_ci95_final": float(1.96 * W[-1, i].std(ddof=1) / np.sqrt(nseed)),
+            "hbar_ci95_final": float(1.96 * Hb[-1, i].std(ddof=1) / np.sqrt(nseed)),
+            "hbar_mean_final": float(Hb[-1, i].mean()),
+            "max_dW_over_se": float(np.max(np.abs(dW) / np.maximum(seW, 1e-12))) if i else 0.0,
+            "max_dhbar_over_se": float(np.max(np.abs(dH) / np.maximum(seH, 1e-12))) if i else 0.0,
+            "max_abs_dW_mean": float(np.max(np.abs(dW))), "max_abs_dhbar_mean": float(np.max(np.abs(dH))),
+        }
+    res["seed_curves"] = {"t": c["t"].tolist(), "W_mean": W.mean(2).tolist(), "hbar_mean": Hb.mean(2).tolist()}
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump(res, fh)
+    summ = {k: v for k, v in res.items() if k in ("full", "seeds")}
+    out = {"metric": METRIC, "value": None, "unit": None, "n_gpus": 1, "steps": steps,
+           "warmup": 0, "higher_is_better": True, "vs_baseline": None, "data": "synthetic",
+           "dtype": "f64/f32/f16-offset/bf16-offset",
+           "config": {"workload": "precision_edge", "full": "2048x8192", "seeds": "8 x 256x1024",
+                      "every": every},
+           "accuracy": summ}
     print(json.dumps(out), flush=True)
 
 
