@@ -122,9 +122,13 @@ typedef enum {
  *   flags         LBM_FLAG_* bits.
  *   kernel_vb, kernel_ty
  *                 launch shape (results do not depend on it): 0 = library
- *                 default; kernel_vb 1 = one column per lane, 4 / 8 / 16 =
+ *                 default; kernel_vb 1 = one column per lane, 2 = population
+ *                 rows staged through LDS by asynchronous global-to-LDS
+ *                 loads (16-bit storages need an even width), 4 / 8 / 16 =
  *                 that many bytes of columns per lane (used when the width
  *                 splits evenly); kernel_ty = rows per thread (1..64).
+ *                 Batches run staged members in the 4-byte (float64: 8-byte)
+ *                 vector form.
  */
 typedef struct {
     uint32_t abi_version;

@@ -1,8 +1,9 @@
 """Launch-shape autotuner.
 
-The step kernel's launch shape -- bytes of columns per lane (``kernel_vb``:
-1 = one column per lane, or 4 / 8 / 16 bytes) and rows per thread
-(``kernel_ty``) -- changes speed, never results (every site's update is the
+The step kernel's launch shape -- its form and bytes of columns per lane
+(``kernel_vb``: 1 = one column per lane, 2 = rows staged through LDS, or
+4 / 8 / 16 bytes) and rows per thread (``kernel_ty``) -- changes speed, never
+results (every site's update is the
 same arithmetic in any shape).  ``tune`` times the candidates on the GPU for
 one workload and ``apply`` fills a workload dict from the cache of tuned
 shapes, keyed by storage type and the width and height rounded up to powers
@@ -39,6 +40,9 @@ def candidates(cfg: dict):
     for vb in vbs:
         for ty in (1, 2, 4, 8):
             yield {"kernel_vb": vb, "kernel_ty": ty}
+    if esize != 2 or int(cfg["L"]) % 2 == 0:
+        for ty in (16, 32, 64):
+            yield {"kernel_vb": 2, "kernel_ty": ty}
 
 
 def _load(path):

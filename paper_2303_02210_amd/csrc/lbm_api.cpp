@@ -114,6 +114,7 @@ struct Layout {
     size_t total = 0;
     int nt = 256, ty = 16, gx = 1, gy = 1, nblocks = 1, rb = 2;
     bool vec = false;   // vector kernel: vb bytes (cpt columns) per thread
+    bool staged = false;  // LDS-staged kernel (same tiles as the vector form)
     int cpt = 1, vb = 16;
 };
 
@@ -144,9 +145,9 @@ bool params_ok(const lbm_params *p, std::string *why)
     if (p->ybc == LBM_Y_WALL_FOLLOW && (p->wall_min_gap < 0 || !(p->wall_w_factor >= 0.0)))
         return bad("bad wall follow parameters");
     if ((p->flags & ~LBM_FLAG_WINDOW) != 0) return bad("unknown flags");
-    if (!(p->kernel_vb == 0 || p->kernel_vb == 1 || p->kernel_vb == 4 || p->kernel_vb == 8 ||
-          p->kernel_vb == 16))
-        return bad("kernel_vb must be 0, 1, 4, 8 or 16");
+    if (!(p->kernel_vb == 0 || p->kernel_vb == 1 || p->kernel_vb == 2 || p->kernel_vb == 4 ||
+          p->kernel_vb == 8 || p->kernel_vb == 16))
+        return bad("kernel_vb must be 0, 1, 2, 4, 8 or 16");
     if (p->kernel_ty < 0 || p->kernel_ty > 64) return bad("kernel_ty must be in [0, 64]");
     if ((p->flags & LBM_FLAG_WINDOW) && p->ybc == LBM_Y_PERIODIC)
         return bad("the sweep window needs a rear wall");
@@ -181,12 +182,21 @@ Layout make_layout(const lbm_params *p)
     l.fbytes = align_up(l.nelem * l.esize, kAlign);
     // vector kernel when the columns split evenly into lanes; bytes per lane
     // and rows per thread as measured best on MI355X for a 4096 x 4096
-    // lattice: float64 16 B / 1 row, float32 4 B / 2 rows, 16-bit 8 B / 4 rows
-    l.vb = l.esize == 8 ? 16 : (l.esize == 4 ? 4 : 8);
+    // lattice: float64 16 B / 1 row, float32 4 B / 2 rows, 16-bit 4 B / 4 rows
+    l.vb = l.esize == 8 ? 16 : 4;
     int ty_pref = l.esize == 8 ? 1 : (l.esize == 4 ? 2 : 4);
     bool scalar = false;
     if (p->kernel_vb == 1) scalar = true;                 // one column per lane
+    else if (p->kernel_vb == 2) l.staged = true;          // rows staged through LDS
     else if (p->kernel_vb > 1) l.vb = p->kernel_vb;       // 4, 8 or 16 bytes per lane
+    // the staged form moves 16-bit populations in pairs of columns
+    if (l.staged && l.esize == 2 && p->L % 2 != 0) l.staged = false;
+    if (l.staged) {
+        // tiles of the vector form with one dword (float64: one site) per lane
+        const StagedGeom G((int)l.esize);
+        l.vb = G.sites() * (int)l.esize;
+        ty_pref = 32;
+    }
     if ((size_t)l.vb < l.esize) l.vb = (int)l.esize;
     if (p->kernel_ty > 0) ty_pref = p->kernel_ty;
     const int V = (int)(l.vb / l.esize);
@@ -194,6 +204,7 @@ Layout make_layout(const lbm_params *p)
     l.cpt = l.vec ? V : 1;
     const int lanes = (p->L + l.cpt - 1) / l.cpt;
     l.nt = lanes <= 64 ? 64 : (lanes <= 128 ? 128 : 256);
+    if (l.staged) l.nt = 64 * StagedGeom((int)l.esize).waves();
     l.gx = (lanes + l.nt - 1) / l.nt;
     l.ty = pick_ty(l.gx, p->H, l.vec || p->kernel_ty > 0 ? ty_pref : 2, p->kernel_ty > 0);
     l.gy = (p->H + l.ty - 1) / l.ty;
@@ -322,6 +333,7 @@ void fill_step_args(const lbm_handle *h, StepArgs<S> &a)
     a.region = p.region;
     a.region_width = p.region_width;
     a.noise = p.sigma > 0.0;
+    a.xcd_rows = 1;   // one row strip of tiles per run (measured best)
     a.seed = p.seed;
     a.replica = p.replica;
     a.omega = (R)(1.0 / p.tau);
@@ -370,8 +382,9 @@ int do_step(lbm_handle *h, int64_t n)
         a.h_next = h->hslot(h->t + 1);
         a.h_clear = h->device_driven ? nullptr : h->hslot(h->t + 2);
         a.t = (uint32_t)h->t;
-        int rc = h->hip(l.vec ? launch_step_vec<S>(a, grid, l.nt, l.vb, h->stream)
-                              : launch_step<S>(a, grid, l.nt, l.rb, h->stream),
+        int rc = h->hip(l.staged ? launch_step_staged<S>(a, grid, h->stream)
+                        : l.vec  ? launch_step_vec<S>(a, grid, l.nt, l.vb, h->stream)
+                                 : launch_step<S>(a, grid, l.nt, l.rb, h->stream),
                         "step kernel");
         if (rc) return rc;
         if (h->device_driven) {

@@ -42,6 +42,24 @@ struct Tiles {
     }
 };
 
+// Geometry of the LDS-staged form of the step for element size ES bytes.
+// One wavefront owns SEG consecutive columns: each of its lanes copies one
+// dword (two for float64) of every population row it needs into LDS, so a
+// population row segment is 256 (float64: 512) bytes and a lane updates V
+// sites.  Rows are held RING deep per wave; NW waves form a block.
+struct StagedGeom {
+    int es;
+    __host__ __device__ constexpr StagedGeom(int e) : es(e) {}
+    __host__ __device__ constexpr int dwords() const { return es == 8 ? 2 : 1; }
+    __host__ __device__ constexpr int segb() const { return 256 * dwords(); }
+    __host__ __device__ constexpr int seg() const { return segb() / es; }
+    __host__ __device__ constexpr int sites() const { return seg() / 64; }
+    __host__ __device__ constexpr int stage_bytes() const { return 9 * segb() + 256; }
+    __host__ __device__ constexpr int loads() const { return 9 * dwords() + 1; }
+    __host__ __device__ constexpr int ring() const { return es == 8 ? 3 : 4; }
+    __host__ __device__ constexpr int waves() const { return es == 8 ? 2 : 4; }
+};
+
 // Device-resident run state (in the workspace).
 struct DevState {
     int64_t  y_wall;        // absolute row of window row 0
@@ -76,6 +94,7 @@ struct StepArgs {
     Tiles tl;
     int32_t mode, growth, region, region_width;
     int32_t noise;
+    int32_t xcd_rows;       // row strips per run of tiles given to one XCD (0: none)
     uint32_t t, seed, replica;
     R omega, kmu, rho_c, g, sigma;
     R w[9];
@@ -185,6 +204,9 @@ template <class S>
 hipError_t launch_batch_advance(BatchRep<S> *const *reps, int n, int K, hipStream_t s);
 template <class S>
 hipError_t launch_step_vec(const StepArgs<S> &a, dim3 grid, int nt, int vb, hipStream_t s);
+// LDS-staged form: grid.x blocks of StagedGeom(sizeof(S)).waves() waves.
+template <class S>
+hipError_t launch_step_staged(const StepArgs<S> &a, dim3 grid, hipStream_t s);
 template <class S>
 hipError_t launch_init(const InitArgs<S> &a, dim3 grid, int nt, hipStream_t s);
 template <class S>

@@ -275,11 +275,19 @@ __device__ __forceinline__ RowSrc row_sources(int mode, int j, int r0, int H, in
 // works on one contiguous part of the lattice, keeping the cache lines that
 // neighbouring blocks share in one L2.
 // ---------------------------------------------------------------------------
-// Block-to-tile order: dispatch goes round-robin over the 8 XCDs, so block
-// `lin` is renumbered to give each XCD one contiguous run of tiles.
-__device__ __forceinline__ int xcd_order(int lin, int nb)
+// Block-to-tile order.  Dispatch goes round-robin over the 8 XCDs (block
+// `lin` runs on XCD lin % 8), each with its own L2.  XCD x gets the runs x,
+// x + 8, x + 16, ... of ch consecutive tiles: neighbouring tiles, which share
+// the cache lines at their edges, mostly meet in one L2, and every XCD gets
+// its share of each part of the lattice (tissue rows cost far more than
+// empty ones; one XCD must not get them all).  ch <= 0: dispatch order.
+__device__ __forceinline__ int xcd_order(int lin, int nb, int ch)
 {
-    return ((nb & 7) == 0) ? (lin & 7) * (nb >> 3) + (lin >> 3) : lin;
+    if (ch <= 0) return lin;
+    const int full = nb - nb % (8 * ch);
+    if (lin >= full) return lin;
+    const int k = lin >> 3;
+    return ((k / ch) * 8 + (lin & 7)) * ch + k % ch;
 }
 
 // Per-step inputs of one tile: the buffers and front-height slots of this
@@ -430,7 +438,7 @@ template <class S, int NT, int RB>
 __global__ __launch_bounds__(NT) void step_kernel(StepArgs<S> a)
 {
     const int nbx = gridDim.x;
-    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y);
+    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
     const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
     step_scalar_tile<S, NT, RB>(a, io, lin % nbx, lin / nbx, nbx);
 }
@@ -469,7 +477,11 @@ __device__ __forceinline__ S get_el(const typename RawVec<ND>::type &v, int i)
     } else if constexpr (sizeof(S) == 4) {
         return __uint_as_float(v[i]);
     } else {
-        const unsigned short b = (unsigned short)((v[i >> 1] >> (16 * (i & 1))) & 0xFFFFu);
+        // (a select chain, so that i may also be a runtime index)
+        uint32_t w = v[0];
+#pragma unroll
+        for (int d = 1; d < ND; ++d) w = ((i >> 1) == d) ? v[d] : w;
+        const unsigned short b = (unsigned short)((w >> (16 * (i & 1))) & 0xFFFFu);
         S r;
         __builtin_memcpy(&r, &b, 2);
         return r;
@@ -489,7 +501,9 @@ __device__ __forceinline__ void put_el(typename RawVec<ND>::type &v, int i, S s)
         unsigned short b;
         __builtin_memcpy(&b, &s, 2);
         const int sh = 16 * (i & 1);
-        v[i >> 1] = (v[i >> 1] & ~(0xFFFFu << sh)) | ((uint32_t)b << sh);
+        const uint32_t m = 0xFFFFu << sh, bb = (uint32_t)b << sh;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) v[d] = ((i >> 1) == d) ? ((v[d] & ~m) | bb) : v[d];
     }
 }
 
@@ -566,6 +580,18 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
     R Wd[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Wd[i] = a.Wd[i];
+    // bits of an exactly empty population of each direction (0 for float64
+    // and float32, -W_i for the 16-bit offsets), as one dword of a vector
+    uint32_t epat[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        if constexpr (sizeof(S) == 2) {
+            const uint32_t b = to_mem<S>(Codec<S>::enc(R(0), Wd[i]));
+            epat[i] = b | (b << 16);
+        } else {
+            epat[i] = 0u;
+        }
+    }
 
     const Tiles tl = a.tl;
     const int tws = tl.tws;
@@ -606,7 +632,35 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
         const S n7 = from_right<S, ND>(A7, e7, edge_r);
         const S n6 = from_right<S, ND>(A6, e6, edge_r);
 
-        VT O[9];
+        // A neighbourhood whose every pulled value is exactly empty updates to
+        // empty (the void rule only reverses directions, and opposite
+        // directions share a weight): when that holds for the whole
+        // wavefront, the per-site update is skipped.
+        bool busy = false;
+        {
+            const VT *Av[9] = {&A0, &A1, &A2, &A3, &A4, &A5, &A6, &A7, &A8};
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+#pragma unroll
+                for (int d = 0; d < ND; ++d) busy = busy || ((*Av[q])[d] != epat[q]);
+            const S ev[6] = {e1, e3, e5, e6, e7, e8};
+            constexpr int eq[6] = {1, 3, 5, 6, 7, 8};
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                typename RawVec<ND>::type t;
+#pragma unroll
+                for (int d = 0; d < ND; ++d) t[d] = epat[eq[i]];
+                busy = busy || (to_mem<S>(ev[i]) != to_mem<S>(get_el<S, ND>(t, 0)));
+            }
+        }
+        VT O[9] = {};
+        uint32_t tmask = 0;
+        if (__builtin_amdgcn_ballot_w64(busy) == 0) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+#pragma unroll
+                for (int d = 0; d < ND; ++d) O[q][d] = epat[q];
+        } else {
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             S v[9];
@@ -646,8 +700,11 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
             S so[9];
             double m_site = 0.0, s_site = 0.0, x_site = 0.0;
             const uint32_t x = (uint32_t)(xv + k);
+            int32_t hpk = hp[0];
+#pragma unroll
+            for (int d = 1; d < V; ++d) hpk = (k == d) ? hp[d] : hpk;
             const bool tissue =
-                site_step<S>(a, io.t, v, fs, Wd, so, x, y, y_wall, hp[k], m_site, s_site, x_site);
+                site_step<S>(a, io.t, v, fs, Wd, so, x, y, y_wall, hpk, m_site, s_site, x_site);
 #pragma unroll
             for (int i = 0; i < 9; ++i) put_el<S, ND>(O[i], k, so[i]);
             if (active) {
@@ -655,11 +712,15 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
                 s_acc += s_site;
                 x_acc += x_site;
                 if (tissue) {
-                    jmax[k] = j;
+                    tmask |= 1u << k;
                     if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
                 }
             }
         }
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            if ((tmask >> k) & 1u) jmax[k] = j;
         if (active) {
             MemT<S> LBM_GLOBAL *rowg = G + (int64_t)s.r0 * tl.rs + cv;
 #pragma unroll
@@ -695,9 +756,349 @@ template <class S, int NT, int ND>
 __global__ __launch_bounds__(NT) void step_kernel_vec(StepArgs<S> a)
 {
     const int nbx = gridDim.x;
-    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y);
+    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
     const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
     step_vec_tile<S, NT, ND>(a, io, lin % nbx, lin / nbx, nbx);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged form of the step.  Each wavefront owns one segment of SEG
+// consecutive columns and marches up its block's rows.  The nine population
+// rows that the update of row y pulls from (rest, E, W from row y; N, NE, NW
+// from y - 1, or at the wall row its own S, SW, SE; S, SW, SE from y + 1)
+// are copied from HBM straight into LDS by asynchronous global-to-LDS loads
+// of one dword per lane, RING - 1 rows ahead of the row being updated: HBM
+// reads stay in flight while a row computes, and they hold no registers.  A
+// tenth load per row brings the six values that the segment's two edge
+// columns pull from the neighbouring segments; every other neighbour along x
+// is a plain LDS read one element over.  A wavefront reads only what it
+// loaded itself, so waves never wait for each other: each waits on its own
+// vector-memory counter, which retires loads and stores in issue order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void lds_load_dword(const void *g, void *l)
+{
+    __builtin_amdgcn_global_load_lds((const void LBM_GLOBAL *)g,
+                                     (__attribute__((address_space(3))) void *)l, 4, 0, 0);
+}
+
+// Wait until at most N of this wave's vector-memory operations are pending
+// (the counter holds at most 63).
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    constexpr int n = N < 63 ? N : 63;
+    __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
+    __asm__ volatile("" ::: "memory");
+}
+
+// wait_vm<A * M + B * MS>() for the runtime pair (a, b), 0 <= a < D, 0 <= b <= D.
+template <int M, int MS, int D, int A = 0, int B = 0>
+__device__ __forceinline__ void wait_vm_ab(int a, int b)
+{
+    if constexpr (A < D) {
+        if constexpr (B <= D) {
+            if (a == A && b == B) {
+                wait_vm<A * M + B * MS>();
+                return;
+            }
+            wait_vm_ab<M, MS, D, A, B + 1>(a, b);
+        } else {
+            wait_vm_ab<M, MS, D, A + 1, 0>(a, b);
+        }
+    }
+}
+
+// Nine LDS reads at byte addresses ad[] into v[], complete on return.  The
+// reads are written in assembly (and wait for themselves) because the
+// compiler, seeing an LDS read after an asynchronous global-to-LDS load,
+// would otherwise wait for every such load in flight, including the rows
+// being fetched ahead.
+template <class S>
+__device__ __forceinline__ void lds_read9(const uint32_t ad[9], S v[9])
+{
+    if constexpr (sizeof(S) == 8) {
+        uint64_t r[9];
+        __asm__ volatile(
+            "ds_read_b64 %0, %9\n\tds_read_b64 %1, %10\n\tds_read_b64 %2, %11\n\t"
+            "ds_read_b64 %3, %12\n\tds_read_b64 %4, %13\n\tds_read_b64 %5, %14\n\t"
+            "ds_read_b64 %6, %15\n\tds_read_b64 %7, %16\n\tds_read_b64 %8, %17\n\t"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]),
+              "=&v"(r[6]), "=&v"(r[7]), "=&v"(r[8])
+            : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]), "v"(ad[4]), "v"(ad[5]), "v"(ad[6]),
+              "v"(ad[7]), "v"(ad[8]));
+#pragma unroll
+        for (int i = 0; i < 9; ++i) v[i] = __longlong_as_double((long long)r[i]);
+    } else {
+        uint32_t r[9];
+        if constexpr (sizeof(S) == 4) {
+            __asm__ volatile(
+                "ds_read_b32 %0, %9\n\tds_read_b32 %1, %10\n\tds_read_b32 %2, %11\n\t"
+                "ds_read_b32 %3, %12\n\tds_read_b32 %4, %13\n\tds_read_b32 %5, %14\n\t"
+                "ds_read_b32 %6, %15\n\tds_read_b32 %7, %16\n\tds_read_b32 %8, %17\n\t"
+                "s_waitcnt lgkmcnt(0)"
+                : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]),
+                  "=&v"(r[6]), "=&v"(r[7]), "=&v"(r[8])
+                : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]), "v"(ad[4]), "v"(ad[5]),
+                  "v"(ad[6]), "v"(ad[7]), "v"(ad[8]));
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v[i] = __uint_as_float(r[i]);
+        } else {
+            __asm__ volatile(
+                "ds_read_u16 %0, %9\n\tds_read_u16 %1, %10\n\tds_read_u16 %2, %11\n\t"
+                "ds_read_u16 %3, %12\n\tds_read_u16 %4, %13\n\tds_read_u16 %5, %14\n\t"
+                "ds_read_u16 %6, %15\n\tds_read_u16 %7, %16\n\tds_read_u16 %8, %17\n\t"
+                "s_waitcnt lgkmcnt(0)"
+                : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]),
+                  "=&v"(r[6]), "=&v"(r[7]), "=&v"(r[8])
+                : "v"(ad[0]), "v"(ad[1]), "v"(ad[2]), "v"(ad[3]), "v"(ad[4]), "v"(ad[5]),
+                  "v"(ad[6]), "v"(ad[7]), "v"(ad[8]));
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const uint16_t b = (uint16_t)r[i];
+                __builtin_memcpy(&v[i], &b, 2);
+            }
+        }
+    }
+}
+
+// 32-bit LDS address of a pointer into shared memory.
+__device__ __forceinline__ uint32_t lds_addr(const void *p)
+{
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+
+template <class S>
+__device__ __forceinline__ void step_staged_tile(const StepArgs<S> &a, const StepIO<S> &io, int bx,
+                                                 int by, int nbx, unsigned char *lds_block)
+{
+    using R = typename Codec<S>::R;
+    constexpr StagedGeom G(sizeof(S));
+    constexpr int ES = (int)sizeof(S);
+    constexpr int P = G.dwords(), SEGB = G.segb(), SEG = G.seg(), V = G.sites();
+    constexpr int STAGE = G.stage_bytes(), RING = G.ring(), D = RING - 1;
+    constexpr int NT = 64 * G.waves();
+    constexpr int HALO = 9 * SEGB;                 // edge values: dword(s) per lane
+    constexpr int HS = 4 * (ES == 8 ? 2 : 1);      // bytes per edge value slot
+
+    const int L = a.L, H = a.H;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c0 = (bx * G.waves() + wave) * SEG;  // first column of this wave
+    const bool live = c0 < L;                      // (wave-uniform)
+
+    int64_t y_wall = 0, y_top = H, nrows = H;
+    if (a.mode == kModeDevice) {
+        y_wall = a.st->y_wall;
+        y_top = a.st->y_valid_top;
+        nrows = a.st->n_rows;
+    }
+    const int j0 = by * a.ty;
+    const int n = live ? (int)max((int64_t)0, min((int64_t)a.ty, nrows - j0)) : 0;
+
+    const Tiles tl = a.tl;
+    const int tws = tl.tws;
+    const int x_end = min(c0 + SEG, L);            // one past the last column
+    const int iR = x_end - 1 - c0;                 // local index of that column
+    const int xl = (c0 == 0) ? L - 1 : c0 - 1;     // left of the segment (periodic)
+    const int xr = (x_end == L) ? 0 : x_end;       // right of it
+
+    // byte offsets of this lane's dwords inside a population row (lanes past
+    // the last column reread a column in range and never use it)
+    int32_t dofs[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        if constexpr (ES == 8) {
+            const int xe = min(c0 + 32 * p + (lane >> 1), L - 1);
+            dofs[p] = (int32_t)(tl.col(xe) * 8 + 4 * (lane & 1));
+        } else if constexpr (ES == 4) {
+            dofs[p] = (int32_t)(tl.col(min(c0 + lane, L - 1)) * 4);
+        } else {
+            dofs[p] = (int32_t)(tl.col(min(c0 + 2 * lane, L - 2)) * 2);
+        }
+    }
+    // the tenth load: lane h (or lanes 2h, 2h + 1 for float64) brings edge
+    // value h: 0-2 from the left column (E, NE, SE), 3-5 from the right
+    // (W, NW, SW); the remaining lanes repeat value 0
+    int hv = (ES == 8) ? (lane >> 1) : lane;
+    hv = hv < 6 ? hv : 0;
+    const int hplane = (hv == 0) ? 1 : (hv == 1) ? 5 : (hv == 2) ? 8 : (hv == 3) ? 3 : (hv == 4) ? 6 : 7;
+    const int hrow = (hv == 0 || hv == 3) ? 0 : (hv == 1 || hv == 4) ? -1 : 1;
+    const int xh = hv < 3 ? xl : xr;
+    const int32_t hofs =
+        (int32_t)((tl.col(ES == 2 ? (xh & ~1) : xh) + ((int64_t)hplane << tws)) * ES +
+                  (ES == 8 ? 4 * (lane & 1) : 0));
+
+    double m_acc = 0.0, s_acc = 0.0, x_acc = 0.0;
+    int32_t jmax[V], hp[V];
+    const int xs = c0 + V * lane;                  // this lane's first site
+    const bool active = live && xs < L;            // (L even for 16-bit storage)
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        jmax[v] = -1;
+        hp[v] = (a.region == kRegionFrontBand && active) ? io.h_prev[xs + v] : 0;
+    }
+    R Wd[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Wd[i] = a.Wd[i];
+
+    const unsigned char *Fb = reinterpret_cast<const unsigned char *>(io.fin);
+    unsigned char LBM_GLOBAL *Gb = as_global(reinterpret_cast<unsigned char *>(io.fout));
+    const int64_t sofs = tl.col(active ? xs : 0) * ES;   // this lane's store offset in a row
+    const int64_t rowb = tl.rs * ES;
+    constexpr int64_t kOne = 1;
+    unsigned char *ring = lds_block + wave * (RING * STAGE);
+
+    int r_issue = (a.mode == kModeDevice) ? (int)((y_wall + j0) % H) : j0;
+    int r_comp = r_issue;
+    auto issue = [&](int k, unsigned char *st) {
+        const int j = j0 + k;
+        const RowSrc s = row_sources(a.mode, j, r_issue, H, y_wall + j, y_top);
+        r_issue = s.rp;
+        const unsigned char *b0 = Fb + (int64_t)s.r0 * rowb;
+        const unsigned char *bm = Fb + (int64_t)(s.below ? s.r0 : s.rm) * rowb;
+        const unsigned char *bp = Fb + (int64_t)s.rp * rowb;
+        auto ld = [&](int slot, const unsigned char *base, int plane) {
+            const unsigned char *pb = base + ((int64_t)plane << tws) * ES;
+#pragma unroll
+            for (int p = 0; p < P; ++p) lds_load_dword(pb + dofs[p], st + slot * SEGB + p * 256);
+        };
+        ld(0, b0, 0);
+        ld(1, b0, 1);
+        ld(3, b0, 3);
+        ld(2, bm, s.below ? 4 : 2);
+        ld(5, bm, s.below ? 7 : 5);
+        ld(6, bm, s.below ? 8 : 6);
+        ld(4, bp, 4);
+        ld(7, bp, 7);
+        ld(8, bp, 8);
+        const unsigned char *bh = hrow == 0 ? b0 : (hrow < 0 ? bm : bp);
+        lds_load_dword(bh + hofs, st + HALO);
+        __asm__ volatile("" ::: "memory");
+    };
+
+    for (int k = 0; k < D && k < n; ++k) issue(k, ring + k * STAGE);
+    // One row: start loading row k + D into the slot row k - 1 used, then
+    // update row k.
+    auto row = [&](int k, unsigned char *wr, const unsigned char *st) {
+        if (k + D < n) issue(k + D, wr);
+
+        const int j = j0 + k;
+        const int64_t y = y_wall + j;
+        const RowSrc s = row_sources(a.mode, j, r_comp, H, y, y_top);
+        r_comp = s.rp;
+        S out9[V][9];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int i = V * lane + v;
+            const bool le = (i == 0), re = (i == iR);
+            // LDS byte offset of slot q at local column c; edge values
+            const auto at = [&](int q, int c) { return q * SEGB + c * ES; };
+            constexpr int hl = ES == 2 ? 2 : 0;   // 16-bit: left value is the upper half
+            const uint32_t sb = lds_addr(st);
+            uint32_t ad[9];
+            ad[0] = sb + at(0, i);
+            ad[2] = sb + at(2, i);
+            ad[4] = sb + at(4, i);
+            ad[1] = sb + (le ? HALO + 0 * HS + hl : at(1, i - 1));
+            ad[8] = sb + (le ? HALO + 2 * HS + hl : at(8, i - 1));
+            ad[3] = sb + (re ? HALO + 3 * HS : at(3, i + 1));
+            ad[7] = sb + (re ? HALO + 5 * HS : at(7, i + 1));
+            ad[5] = sb + (s.below ? at(5, i) : (le ? HALO + 1 * HS + hl : at(5, i - 1)));
+            ad[6] = sb + (s.below ? at(6, i) : (re ? HALO + 4 * HS : at(6, i + 1)));
+            S vv[9];
+            lds_read9<S>(ad, vv);
+            R fs[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q) fs[q] = Codec<S>::dec(vv[q], Wd[q]);
+            // sources that hold no live data stream in nothing
+            if (!s.v0) {
+                vv[0] = Codec<S>::enc(R(0), Wd[0]);
+                vv[1] = vv[3] = Codec<S>::enc(R(0), Wd[1]);
+                fs[0] = fs[1] = fs[3] = R(0);
+            }
+            if (!s.below && !s.vm) {
+                vv[2] = Codec<S>::enc(R(0), Wd[2]);
+                vv[5] = vv[6] = Codec<S>::enc(R(0), Wd[5]);
+                fs[2] = fs[5] = fs[6] = R(0);
+            }
+            if (!s.vp) {
+                vv[4] = Codec<S>::enc(R(0), Wd[4]);
+                vv[7] = vv[8] = Codec<S>::enc(R(0), Wd[7]);
+                fs[4] = fs[7] = fs[8] = R(0);
+            }
+            double m_site = 0.0, s_site = 0.0, x_site = 0.0;
+            const bool tissue = site_step<S>(a, io.t, vv, fs, Wd, out9[v], (uint32_t)(c0 + i), y,
+                                             y_wall, hp[v], m_site, s_site, x_site);
+            if (active) {
+                m_acc += m_site;
+                s_acc += s_site;
+                x_acc += x_site;
+                if (tissue) {
+                    jmax[v] = j;
+                    if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
+                }
+            }
+        }
+        if (active) {
+            unsigned char LBM_GLOBAL *g = Gb + (int64_t)s.r0 * rowb + sofs;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                unsigned char LBM_GLOBAL *gq = g + ((kOne * q) << tws) * ES;
+                if constexpr (ES == 2) {
+                    uint32_t w = 0;
+                    __builtin_memcpy(&w, &out9[0][q], 2);
+                    uint16_t hi;
+                    __builtin_memcpy(&hi, &out9[1][q], 2);
+                    w |= (uint32_t)hi << 16;
+                    __builtin_nontemporal_store(w, reinterpret_cast<uint32_t LBM_GLOBAL *>(gq));
+                } else {
+                    __builtin_nontemporal_store(out9[0][q], reinterpret_cast<S LBM_GLOBAL *>(gq));
+                }
+            }
+        }
+    };
+    for (int k = 0; k < n; ++k) {
+        // stage k has landed once no more than the loads of the stages issued
+        // after it and the stores issued after it are pending
+        wait_vm_ab<G.loads(), 9, D>(min(D - 1, n - 1 - k), min(k, D));
+        row(k, ring + ((k + D) % RING) * STAGE, ring + (k % RING) * STAGE);
+    }
+
+    // ---- front heights -----------------------------------------------------
+    if (active) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            if (xs + v < L) {
+                if (jmax[v] >= 0) {
+                    const int32_t hv2 = (int32_t)(y_wall + jmax[v] + 1);
+                    atomicMax(io.h_next + xs + v, hv2);
+                    atomicMax(a.colmax + xs + v, hv2);
+                }
+                if (io.h_clear && by == 0) io.h_clear[xs + v] = 0;
+            }
+        }
+    }
+
+    // ---- per-block tallies (fixed order: deterministic) ------------------------
+    block_sum3<NT>(m_acc, s_acc, x_acc);
+    if (threadIdx.x == 0) {
+        double *pp = a.partials + 4 * (by * nbx + bx);
+        pp[0] = m_acc;
+        pp[1] += s_acc;
+        pp[2] += x_acc;
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(64 * StagedGeom(sizeof(S)).waves()) void step_kernel_staged(StepArgs<S> a)
+{
+    constexpr StagedGeom G(sizeof(S));
+    __shared__ __attribute__((aligned(16))) unsigned char lds[G.waves() * G.ring() * G.stage_bytes()];
+    const int nbx = gridDim.x;
+    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
+    const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
+    step_staged_tile<S>(a, io, lin % nbx, lin / nbx, nbx, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -967,7 +1368,7 @@ __global__ __launch_bounds__(NT) void step_batch(BatchRep<S> *const *reps, const
     const BatchRep<S> &R = *reinterpret_cast<const BatchRep<S> *>(stage);
     const int total = *count;
     for (int c = blockIdx.x; c < total; c += gridDim.x) {
-        const TileRef e = table[xcd_order(c, total)];
+        const TileRef e = table[xcd_order(c, total, 2)];
         stage_dwords<NT>(reps[e.rep], stage, (int)(sizeof(BatchRep<S>) / 4));
         const StepIO<S> io = batch_io(&R, k);
         for (int i = 0; i < e.n; ++i) {
@@ -1099,6 +1500,14 @@ hipError_t launch_step_vec(const StepArgs<S> &a, dim3 grid, int nt, int vb, hipS
     } else {
         launch_vec_nt<S, 4>(a, grid, nt, s);
     }
+    return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_step_staged(const StepArgs<S> &a, dim3 grid, hipStream_t s)
+{
+    constexpr StagedGeom G(sizeof(S));
+    hipLaunchKernelGGL((step_kernel_staged<S>), grid, dim3(64 * G.waves()), 0, s, a);
     return hipGetLastError();
 }
 
