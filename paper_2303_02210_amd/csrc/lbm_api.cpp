@@ -182,9 +182,9 @@ Layout make_layout(const lbm_params *p)
     l.fbytes = align_up(l.nelem * l.esize, kAlign);
     // vector kernel when the columns split evenly into lanes; bytes per lane
     // and rows per thread as measured best on MI355X for a 4096 x 4096
-    // lattice: float64 16 B / 1 row, float32 4 B / 2 rows, 16-bit 4 B / 4 rows
+    // lattice: float64 16 B / 1 row, float32 4 B / 1 row, 16-bit 4 B / 2 rows
     l.vb = l.esize == 8 ? 16 : 4;
-    int ty_pref = l.esize == 8 ? 1 : (l.esize == 4 ? 2 : 4);
+    int ty_pref = l.esize == 2 ? 2 : 1;
     bool scalar = false;
     if (p->kernel_vb == 1) scalar = true;                 // one column per lane
     else if (p->kernel_vb == 2) l.staged = true;          // rows staged through LDS
@@ -958,11 +958,12 @@ struct lbm_batch {
             if (g.windowed) {
                 g.grid = (int)std::min<int64_t>(g.tiles, kWindowGrid);
             } else {
-                // every tile, member by member, in runs of kTilesPerRun
+                // every tile, member by member, in runs stacked in y
                 for (size_t i = 0; i < g.m.size(); ++i) {
-                    const int nb = g.m[i]->lay.nblocks;
-                    for (int l = 0; l < nb; l += kTilesPerRun)
-                        tab.push_back(TileRef{(int32_t)i, l, std::min(kTilesPerRun, nb - l), 0});
+                    const Layout &ml = g.m[i]->lay;
+                    const int64_t nr = run_count(ml.gy, ml.gx, ml.ty);
+                    for (int64_t l = 0; l < nr; ++l)
+                        tab.push_back(run_ref((int)i, l, ml.gy, ml.gx, ml.ty));
                 }
                 cnt = (int32_t)tab.size();
                 g.grid = cnt;

@@ -174,16 +174,34 @@ struct BatchRep {
     int32_t pad2;
 };
 
-// Entry of a batch tile table: a run of n consecutive tiles of one member
-// (member index in its group, first tile number inside the member; tiles are
-// numbered row strip major, x fastest).
+// Entry of a batch tile table: a run of n tiles of one member stacked in y
+// (member index in its group, number of the run's lowest tile inside the
+// member; tiles are numbered row strip major, x fastest).  A run is updated
+// as one tile n row strips tall.
 struct TileRef {
     int32_t rep;
     int32_t local0;
     int32_t n;
     int32_t pad;
 };
-constexpr int kTilesPerRun = 8;
+// Rows per batch run (a member's row strips are grouped to about this many).
+constexpr int kRowsPerRun = 4;
+__host__ __device__ inline int run_strips(int ty) { return ty >= kRowsPerRun ? 1 : kRowsPerRun / ty; }
+// Runs covering the first `strips` row strips of a member gx tiles wide.
+__host__ __device__ inline int64_t run_count(int64_t strips, int gx, int ty)
+{
+    const int ry = run_strips(ty);
+    return (strips + ry - 1) / ry * gx;
+}
+// Run l of those: its lowest tile and its height in strips.
+__host__ __device__ inline TileRef run_ref(int rep, int64_t l, int64_t strips, int gx, int ty)
+{
+    const int ry = run_strips(ty);
+    const int64_t by0 = (l / gx) * ry;
+    const int64_t bx = l % gx;
+    const int64_t n = strips - by0 < ry ? strips - by0 : ry;
+    return TileRef{rep, (int32_t)(by0 * gx + bx), (int32_t)n, 0};
+}
 
 template <class S>
 hipError_t launch_step(const StepArgs<S> &a, dim3 grid, int nt, int rb, hipStream_t s);

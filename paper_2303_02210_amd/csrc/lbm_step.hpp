@@ -80,6 +80,14 @@ __device__ __forceinline__ R sum9(const R v[9])
     return s;
 }
 
+// Barrier for LDS traffic only: waits for this wave's LDS operations, not
+// for its global stores (__syncthreads would also wait for every store in
+// flight, which a tile that goes on to other work must not do).
+__device__ __forceinline__ void lds_barrier()
+{
+    __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -103,7 +111,7 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c)
         red[1][wave] = b;
         red[2][wave] = c;
     }
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) {
         a = red[0][0];
         b = red[1][0];
@@ -115,6 +123,7 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c)
             c += red[2][w];
         }
     }
+    lds_barrier();   // red is free again (a batch block goes on to more tiles)
 }
 
 // ---------------------------------------------------------------------------
@@ -304,7 +313,7 @@ struct StepIO {
 
 template <class S, int NT, int RB>
 __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const StepIO<S> &io, int bx,
-                                                 int by, int nbx)
+                                                 int by, int nbx, int nstrips = 1)
 {
     using R = typename Codec<S>::R;
 
@@ -322,7 +331,7 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
         nrows = a.st->n_rows;
     }
     const int j0 = by * a.ty;
-    const int jend = (int)min((int64_t)(j0 + a.ty), nrows);
+    const int jend = (int)min((int64_t)(j0 + nstrips * a.ty), nrows);
 
     double m_acc = 0.0, s_acc = 0.0, x_acc = 0.0;
     int64_t ymax = -1;
@@ -431,6 +440,9 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
         p[0] = m_acc;
         p[1] += s_acc;
         p[2] += x_acc;
+        // a batch run taller than one strip keeps its tallies in its lowest
+        // tile's slot; the mass slots of the strips above it hold nothing
+        for (int i = 1; i < nstrips; ++i) a.partials[4 * ((by + i) * nbx + bx)] = 0.0;
     }
 }
 
@@ -519,6 +531,65 @@ __device__ __forceinline__ void vstore(T LBM_GLOBAL *p, const typename RawVec<ND
     __builtin_nontemporal_store(v, reinterpret_cast<typename RawVec<ND>::type LBM_GLOBAL *>(p));
 }
 
+// Nontemporal store of a lane's vector through a buffer resource.  A lane
+// whose offset lies beyond the resource's range stores nothing, so lanes
+// past the last column need no branch around the store (a branch would make
+// the compiler treat the stores as possibly not issued, and then wait for
+// them before the next row's loads could be used).
+constexpr uint32_t kBufWord3 = 0x00020000u;   // raw buffer, 32-bit data format
+constexpr int kAuxNT = 2;                     // nontemporal cache policy
+constexpr uint32_t kOffNone = 0x7FFFFFFFu;    // offset beyond any row
+template <int ND>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff,
+                                       const typename RawVec<ND>::type &v)
+{
+    if constexpr (ND == 1) {
+        __builtin_amdgcn_raw_buffer_store_b32(v[0], r, off, soff, kAuxNT);
+    } else if constexpr (ND == 2) {
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, off, soff, kAuxNT);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, off, soff, kAuxNT);
+    }
+}
+
+// Loads through a buffer resource: the per-lane byte offset in a register,
+// the per-plane offset in a scalar register.
+template <int ND>
+__device__ __forceinline__ typename RawVec<ND>::type bload(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                                           uint32_t soff)
+{
+    typename RawVec<ND>::type v;
+    if constexpr (ND == 1) {
+        v[0] = __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, kAuxNT);
+    } else if constexpr (ND == 2) {
+        v = __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, kAuxNT);
+    } else {
+        v = __builtin_amdgcn_raw_buffer_load_b128(r, off, soff, kAuxNT);
+    }
+    return v;
+}
+// One element at a wave-uniform byte offset.
+template <class S>
+__device__ __forceinline__ S bload_el(__amdgpu_buffer_rsrc_t r, uint32_t soff)
+{
+    if constexpr (sizeof(S) == 8) {
+        typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+        const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, 0, soff, 0);
+        return __longlong_as_double((long long)((uint64_t)v[0] | ((uint64_t)v[1] << 32)));
+    } else if constexpr (sizeof(S) == 4) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, 0, soff, 0));
+    } else {
+        const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, 0, soff, 0);
+        S v;
+        __builtin_memcpy(&v, &b, 2);
+        return v;
+    }
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, int64_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, (int)kBufWord3);
+}
+
 // The left lane's last element (inside the wave) or the edge value.
 template <class S, int ND>
 __device__ __forceinline__ S from_left(const typename RawVec<ND>::type &own, S edge, bool use_edge)
@@ -544,7 +615,7 @@ __device__ __forceinline__ S from_right(const typename RawVec<ND>::type &own, S 
 // ND dwords per lane; WPE: waves per SIMD the register allocation aims for.
 template <class S, int NT, int ND>
 __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO<S> &io, int bx,
-                                              int by, int nbx)
+                                              int by, int nbx, int nstrips = 1)
 {
     using R = typename Codec<S>::R;
     using VT = typename RawVec<ND>::type;
@@ -568,7 +639,7 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
         nrows = a.st->n_rows;
     }
     const int j0 = by * a.ty;
-    const int jend = (int)min((int64_t)(j0 + a.ty), nrows);
+    const int jend = (int)min((int64_t)(j0 + nstrips * a.ty), nrows);
 
     double m_acc = 0.0, s_acc = 0.0, x_acc = 0.0;
     int32_t jmax[V], hp[V];
@@ -602,28 +673,77 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
     MemT<S> LBM_GLOBAL *__restrict__ G = as_global(reinterpret_cast<MemT<S> *>(io.fout));
     int r0 = (a.mode == kModeDevice) ? (int)((y_wall + j0) % H) : j0;
 
-    for (int j = j0; j < jend; ++j) {
-        const int64_t y = y_wall + j;
-        const RowSrc s = row_sources(a.mode, j, r0, H, y, y_top);
-        const MemT<S> LBM_GLOBAL *row0 = F + (int64_t)s.r0 * tl.rs;
-        const MemT<S> LBM_GLOBAL *rowm = F + (int64_t)(s.below ? s.r0 : s.rm) * tl.rs;
-        const MemT<S> LBM_GLOBAL *rowp = F + (int64_t)s.rp * tl.rs;
+    // ---- step 1: pull-stream.  The loads of one window row: the nine
+    // vectors and the six values at the wavefront's edges -------------------
+    struct Fetch {
+        VT A[9];
+        S e[6];   // E, W, NE, NW, SW, SE sources beyond the wave's edges
+    };
+    constexpr uint32_t EB = sizeof(MemT<S>);
+    const uint32_t loff = (uint32_t)(cv * EB);        // this lane's vector in a row
+    const int64_t rowbytes = tl.rs * EB;
+    const auto pl = [&](int q) { return ((uint32_t)q << tws) * EB; };
+    // (16-bit storage loads through buffer resources, which need fewer
+    // registers; the wider types measured faster with plain global loads)
+    auto fetch = [&](int j, int r, Fetch &f) {
+        const RowSrc s = row_sources(a.mode, j, r, H, y_wall + j, y_top);
+        if constexpr (sizeof(S) != 2) {
+            const MemT<S> LBM_GLOBAL *row0 = F + (int64_t)s.r0 * tl.rs;
+            const MemT<S> LBM_GLOBAL *rowm = F + (int64_t)(s.below ? s.r0 : s.rm) * tl.rs;
+            const MemT<S> LBM_GLOBAL *rowp = F + (int64_t)s.rp * tl.rs;
+            const int qn2 = s.below ? 4 : 2, qn5 = s.below ? 7 : 5, qn6 = s.below ? 8 : 6;
+            f.A[0] = vload<ND>(row0 + cv + (0 << tws));
+            f.A[1] = vload<ND>(row0 + cv + (1 << tws));
+            f.A[3] = vload<ND>(row0 + cv + (3 << tws));
+            f.A[2] = vload<ND>(rowm + cv + (qn2 << tws));
+            f.A[5] = vload<ND>(rowm + cv + (qn5 << tws));
+            f.A[6] = vload<ND>(rowm + cv + (qn6 << tws));
+            f.A[4] = vload<ND>(rowp + cv + (4 << tws));
+            f.A[7] = vload<ND>(rowp + cv + (7 << tws));
+            f.A[8] = vload<ND>(rowp + cv + (8 << tws));
+            f.e[0] = from_mem<S>(row0[cl + (1 << tws)]);
+            f.e[1] = from_mem<S>(row0[cr + (3 << tws)]);
+            f.e[2] = from_mem<S>(rowm[cl + (5 << tws)]);
+            f.e[3] = from_mem<S>(rowm[cr + (6 << tws)]);
+            f.e[4] = from_mem<S>(rowp[cr + (7 << tws)]);
+            f.e[5] = from_mem<S>(rowp[cl + (8 << tws)]);
+            return;
+        }
+        const __amdgpu_buffer_rsrc_t R0 =
+            row_rsrc((const void *)(F + (int64_t)s.r0 * tl.rs), rowbytes);
+        const __amdgpu_buffer_rsrc_t Rm =
+            row_rsrc((const void *)(F + (int64_t)(s.below ? s.r0 : s.rm) * tl.rs), rowbytes);
+        const __amdgpu_buffer_rsrc_t Rp =
+            row_rsrc((const void *)(F + (int64_t)s.rp * tl.rs), rowbytes);
         // directions feeding N, NE, NW: the row below, or this site reflected
         const int qn2 = s.below ? 4 : 2, qn5 = s.below ? 7 : 5, qn6 = s.below ? 8 : 6;
-
-        // ---- step 1: pull-stream (vector loads, all issued up front) ----
-        const VT A0 = vload<ND>(row0 + cv + (0 << tws));
-        const VT A1 = vload<ND>(row0 + cv + (1 << tws));
-        const VT A3 = vload<ND>(row0 + cv + (3 << tws));
-        const VT A2 = vload<ND>(rowm + cv + (qn2 << tws));
-        const VT A5 = vload<ND>(rowm + cv + (qn5 << tws));
-        const VT A6 = vload<ND>(rowm + cv + (qn6 << tws));
-        const VT A4 = vload<ND>(rowp + cv + (4 << tws));
-        const VT A7 = vload<ND>(rowp + cv + (7 << tws));
-        const VT A8 = vload<ND>(rowp + cv + (8 << tws));
-        const S e1 = from_mem<S>(row0[cl + (1 << tws)]), e3 = from_mem<S>(row0[cr + (3 << tws)]);
-        const S e5 = from_mem<S>(rowm[cl + (5 << tws)]), e6 = from_mem<S>(rowm[cr + (6 << tws)]);
-        const S e7 = from_mem<S>(rowp[cr + (7 << tws)]), e8 = from_mem<S>(rowp[cl + (8 << tws)]);
+        f.A[0] = bload<ND>(R0, loff, pl(0));
+        f.A[1] = bload<ND>(R0, loff, pl(1));
+        f.A[3] = bload<ND>(R0, loff, pl(3));
+        f.A[2] = bload<ND>(Rm, loff, pl(qn2));
+        f.A[5] = bload<ND>(Rm, loff, pl(qn5));
+        f.A[6] = bload<ND>(Rm, loff, pl(qn6));
+        f.A[4] = bload<ND>(Rp, loff, pl(4));
+        f.A[7] = bload<ND>(Rp, loff, pl(7));
+        f.A[8] = bload<ND>(Rp, loff, pl(8));
+        f.e[0] = bload_el<S>(R0, (uint32_t)(cl * EB) + pl(1));
+        f.e[1] = bload_el<S>(R0, (uint32_t)(cr * EB) + pl(3));
+        f.e[2] = bload_el<S>(Rm, (uint32_t)(cl * EB) + pl(5));
+        f.e[3] = bload_el<S>(Rm, (uint32_t)(cr * EB) + pl(6));
+        f.e[4] = bload_el<S>(Rp, (uint32_t)(cr * EB) + pl(7));
+        f.e[5] = bload_el<S>(Rp, (uint32_t)(cl * EB) + pl(8));
+    };
+    // The update of window row j (physical row r) from the loads in cur:
+    // the stored results go to O; returns where the row pulled from.
+    Fetch cur;
+    VT O[9];
+    auto update_row = [&](int j, int r) -> RowSrc {
+        const int64_t y = y_wall + j;
+        const RowSrc s = row_sources(a.mode, j, r, H, y, y_top);
+        const VT A0 = cur.A[0], A1 = cur.A[1], A2 = cur.A[2], A3 = cur.A[3], A4 = cur.A[4];
+        const VT A5 = cur.A[5], A6 = cur.A[6], A7 = cur.A[7], A8 = cur.A[8];
+        const S e1 = cur.e[0], e3 = cur.e[1], e5 = cur.e[2], e6 = cur.e[3], e7 = cur.e[4];
+        const S e8 = cur.e[5];
         // neighbours across lanes (E-type: from x-1, W-type: from x+1)
         const S n1 = from_left<S, ND>(A1, e1, edge_l);
         const S n8 = from_left<S, ND>(A8, e8, edge_l);
@@ -653,7 +773,6 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
                 busy = busy || (to_mem<S>(ev[i]) != to_mem<S>(get_el<S, ND>(t, 0)));
             }
         }
-        VT O[9] = {};
         uint32_t tmask = 0;
         if (__builtin_amdgcn_ballot_w64(busy) == 0) {
 #pragma unroll
@@ -721,12 +840,29 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
 #pragma unroll
         for (int k = 0; k < V; ++k)
             if ((tmask >> k) & 1u) jmax[k] = j;
-        if (active) {
-            MemT<S> LBM_GLOBAL *rowg = G + (int64_t)s.r0 * tl.rs + cv;
+        return s;
+    };
+    const uint32_t soff = active ? loff : kOffNone;
+    auto store_row = [&](const RowSrc &s) {
+        const __amdgpu_buffer_rsrc_t rr = row_rsrc((const void *)(G + (int64_t)s.r0 * tl.rs), rowbytes);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) vstore<ND>(rowg + (i << tws), O[i]);
+        for (int i = 0; i < 9; ++i) bstore<ND>(rr, soff, pl(i), O[i]);
+    };
+    // Each row's stores go out after the next row's loads: the memory counter
+    // retires in issue order, so waiting for those loads never waits for
+    // these stores.  (The first row is updated ahead of the loop, so every
+    // update inside it follows the same sequence of memory operations.)
+    if (j0 < jend) {
+        fetch(j0, r0, cur);
+        RowSrc s = update_row(j0, r0);
+        for (int j = j0 + 1; j < jend; ++j) {
+            __asm__ volatile("" ::: "memory");
+            fetch(j, s.rp, cur);
+            __asm__ volatile("" ::: "memory");
+            store_row(s);
+            s = update_row(j, s.rp);
         }
-        r0 = s.rp;
+        store_row(s);
     }
 
     // ---- front heights -----------------------------------------------------
@@ -749,11 +885,24 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
         p[0] = m_acc;
         p[1] += s_acc;
         p[2] += x_acc;
+        // a batch run taller than one strip keeps its tallies in its lowest
+        // tile's slot; the mass slots of the strips above it hold nothing
+        for (int i = 1; i < nstrips; ++i) a.partials[4 * ((by + i) * nbx + bx)] = 0.0;
     }
 }
 
+// Waves per SIMD the vector form's register allocation aims for (1 = no
+// target): the 16-bit storages at 4 bytes per lane fit 96 registers, which
+// lets 5 waves share a SIMD (measured faster than 4).
+template <class S, int ND>
+constexpr int vec_waves()
+{
+    return (sizeof(S) == 2 && ND == 1) ? 5 : 1;
+}
+
 template <class S, int NT, int ND>
-__global__ __launch_bounds__(NT) void step_kernel_vec(StepArgs<S> a)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vec_waves<S, ND>())))
+void step_kernel_vec(StepArgs<S> a)
 {
     const int nbx = gridDim.x;
     const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
@@ -1350,15 +1499,15 @@ template <int NT>
 __device__ __forceinline__ void stage_dwords(const void *src, uint32_t *lds, int ndw)
 {
     const uint32_t *g = reinterpret_cast<const uint32_t *>(src);
-    __syncthreads();
+    lds_barrier();
     for (int i = threadIdx.x; i < ndw; i += NT) lds[i] = g[i];
-    __syncthreads();
+    lds_barrier();
 }
 
-// Each table entry is a run of up to kTilesPerRun tiles of one member, so
-// a block fetches the member's descriptor once (through LDS, into scalar
-// registers) and then runs the tiles back to back.  Windowed groups launch a
-// fixed grid that strides over the entries.
+// Each table entry is a run of tiles of one member stacked in y, which a
+// block updates as one tall tile after fetching the member's descriptor
+// (through LDS).  Windowed groups launch a fixed grid that strides over the
+// entries.
 template <class S, int NT, int ND, bool VEC>
 __global__ __launch_bounds__(NT) void step_batch(BatchRep<S> *const *reps, const TileRef *table,
                                                  const int32_t *count, int k)
@@ -1371,11 +1520,9 @@ __global__ __launch_bounds__(NT) void step_batch(BatchRep<S> *const *reps, const
         const TileRef e = table[xcd_order(c, total, 2)];
         stage_dwords<NT>(reps[e.rep], stage, (int)(sizeof(BatchRep<S>) / 4));
         const StepIO<S> io = batch_io(&R, k);
-        for (int i = 0; i < e.n; ++i) {
-            const int local = e.local0 + i;
-            if constexpr (VEC) step_vec_tile<S, NT, ND>(R.a, io, local % R.gx, local / R.gx, R.gx);
-            else step_scalar_tile<S, NT, ND>(R.a, io, local % R.gx, local / R.gx, R.gx);
-        }
+        const int bx = e.local0 % R.gx, by = e.local0 / R.gx;
+        if constexpr (VEC) step_vec_tile<S, NT, ND>(R.a, io, bx, by, R.gx, e.n);
+        else step_scalar_tile<S, NT, ND>(R.a, io, bx, by, R.gx, e.n);
     }
 }
 
@@ -1406,7 +1553,7 @@ __global__ __launch_bounds__(kRedThreads) void plan_batch(BatchRep<S> *const *re
         if (i < n) {
             const BatchRep<S> *R = reps[i];
             live = live_tiles(R->gx, R->ty, R->nblocks, R->window, R->a.st->n_rows);
-            c = (live + kTilesPerRun - 1) / kTilesPerRun;      // runs of this member
+            c = (int)run_count(live / R->gx, R->gx, R->ty);    // runs of this member
         }
         live_sh[threadIdx.x] = live;
         // inclusive scan of this chunk (Hillis-Steele)
@@ -1425,10 +1572,9 @@ __global__ __launch_bounds__(kRedThreads) void plan_batch(BatchRep<S> *const *re
             const int cm = pre[m] - (m ? pre[m - 1] : 0);
             const int s0 = carry + (m ? pre[m - 1] : 0);
             const int live = live_sh[m];
-            for (int l = threadIdx.x; l < cm; l += kRedThreads) {
-                const int first = l * kTilesPerRun;
-                table[s0 + l] = TileRef{base + m, first, min(kTilesPerRun, live - first), 0};
-            }
+            const BatchRep<S> *Rm = reps[base + m];
+            for (int l = threadIdx.x; l < cm; l += kRedThreads)
+                table[s0 + l] = run_ref(base + m, l, live / Rm->gx, Rm->gx, Rm->ty);
             // tiles that ran last step but not this one: their mass tally
             // would otherwise stay behind (a solo launch writes 0 there)
             BatchRep<S> *R = reps[base + m];
