@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=600, help="served: trace length")
     ap.add_argument("--time-limit", type=float, default=300.0, help="served: wall-clock limit (s)")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="ensemble/served: skip the one-run-at-a-time comparison")
     ap.add_argument("--out", default=None, help="precision: write the curves to this JSON file")
     ap.add_argument("--workload", default="bulk",
                     choices=["bulk", "edge", "ensemble", "served", "precision"],
@@ -246,7 +248,7 @@ def bench_ensemble(args):
     log(f"batched: {t_batch:.3f} s; mean W {sum(W) / len(W):.3f}")
     # the same runs, one after another, each on its own
     t_seq = 0.0
-    for c in cfgs:
+    for c in ([] if args.no_sequential else cfgs):
         sim = Sim(c)
         sim.step(args.warmup)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -272,9 +274,10 @@ def bench_ensemble(args):
                      "frac": round(sites * bpu / (t_batch / K) / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": None},
         "runs_per_hour": round(len(cfgs) / (t_batch * full_steps / K) * 3600, 1),
-        "sequential": {"value": round(sites * K / t_seq / 1e6, 1), "unit": "MLUPS",
-                       "runs_per_hour": round(len(cfgs) / (t_seq * full_steps / K) * 3600, 1)},
-        "speedup_vs_sequential": round(t_seq / t_batch, 3),
+        "sequential": None if not t_seq else {
+            "value": round(sites * K / t_seq / 1e6, 1), "unit": "MLUPS",
+            "runs_per_hour": round(len(cfgs) / (t_seq * full_steps / K) * 3600, 1)},
+        "speedup_vs_sequential": round(t_seq / t_batch, 3) if t_seq else None,
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
@@ -296,6 +299,14 @@ def bench_served(args):
     summ = srv.serve(reqs, time_limit=args.time_limit, log=log)
     srv.close()
     log(json.dumps(summ))
+    seq = None
+    if not args.no_sequential:
+        # the same trace through a plain queue: one run at a time, alone
+        import torch
+        from paper_2303_02210_amd.serve import serve_sequential
+        torch.cuda.empty_cache()
+        seq = serve_sequential(reqs, time_limit=args.time_limit, tick_steps=100, log=log)
+        log("sequential: " + json.dumps(seq))
     out = {
         "metric": METRIC, "value": round(summ["runs_per_hour"], 1), "unit": "runs/hour",
         "n_gpus": 1, "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
@@ -310,6 +321,12 @@ def bench_served(args):
         "completed": summ["completed"], "unfinished": summ["running"] + summ["queued"],
         "mlups_nominal": round(summ["mlups_nominal"], 1),
         "gpu_busy_frac": round(summ["gpu_busy_frac"], 4), "wall_s": round(summ["wall_s"], 2),
+        "sequential": None if seq is None else {
+            "runs_per_hour": round(seq["runs_per_hour"], 1), "completed": seq["completed"],
+            "p50_latency_s": seq["p50_latency_s"], "p99_latency_s": seq["p99_latency_s"],
+            "mlups_nominal": round(seq["mlups_nominal"], 1), "wall_s": round(seq["wall_s"], 2)},
+        "speedup_vs_sequential": None if seq is None or not seq["runs_per_hour"] else
+            round(summ["runs_per_hour"] / seq["runs_per_hour"], 3),
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

@@ -165,3 +165,65 @@ class Server:
                 r.sim.close()
         self.running = []
         self.ens.close()
+
+
+def serve_sequential(requests, time_limit: float | None = None, tick_steps: int = 100,
+                     device: str = "cuda:0", clock=time.perf_counter, log=None) -> dict:
+    """The same trace served one run at a time, in arrival order, each run
+    stepped alone (no batching): the plain queue that continuous batching is
+    measured against.  Front heights are streamed back every tick_steps
+    steps, as in Server.  Returns a summary with the same fields."""
+    from .sim import Sim
+    torch = _torch()
+    reqs = sorted(requests, key=lambda q: q.get("arrival_s", 0.0))
+    t0 = clock()
+    lat, site_updates, busy = [], 0.0, 0.0
+    done = 0
+    for i, req in enumerate(reqs):
+        now = clock() - t0
+        if time_limit is not None and now > time_limit:
+            break
+        wait = req.get("arrival_s", 0.0) - now
+        if wait > 0:
+            time.sleep(wait)
+        sim = Sim(req, device=device)
+        pinned = torch.empty(int(req["L"]), dtype=torch.int32).pin_memory()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(sim.stream)
+        left = int(req["steps"])
+        cut = False
+        while left > 0:
+            k = min(tick_steps, left)
+            sim.step(k)
+            sim.front_heights_async(pinned)
+            left -= k
+            if time_limit is not None and clock() - t0 > time_limit:
+                cut = True
+                break
+        ev1.record(sim.stream)
+        sim.stream.synchronize()
+        sim.diagnostics()                      # raises if the run latched an error
+        busy += ev0.elapsed_time(ev1) / 1e3
+        site_updates += float(req["L"]) * float(req["H"]) * (int(req["steps"]) - left)
+        sim.close()
+        if cut:
+            break
+        lat.append(clock() - t0 - req.get("arrival_s", 0.0))
+        done += 1
+        if log and done % 50 == 0:
+            log(f"sequential: t={clock() - t0:.1f}s done={done}")
+    wall = clock() - t0
+    lat = np.array(lat) if lat else np.zeros(0)
+    return {
+        "completed": done, "running": 0, "queued": len(reqs) - done, "wall_s": wall,
+        "runs_per_hour": done / wall * 3600 if wall > 0 else 0.0,
+        "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
+        "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
+        "mean_latency_s": float(lat.mean()) if lat.size else None,
+        "site_updates": site_updates,
+        "mlups_nominal": site_updates / wall / 1e6 if wall > 0 else 0.0,
+        "gpu_busy_frac": busy / wall if wall > 0 else 0.0,
+        "ticks": None,
+    }
+
