@@ -83,7 +83,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 }
 
 /* Random streams: the fourth counter word is 4*stream + call. */
-enum { STREAM_NOISE = 0, STREAM_INIT = 1 };
+enum { STREAM_NOISE = 0, STREAM_INIT = 1, STREAM_DIVISION = 2 };
 
 static double u24(uint32_t k24)
 {
@@ -126,6 +126,52 @@ double orc_init_uniform(uint32_t seed, uint32_t replica, int32_t x, int64_t y_ab
     return u24(r[0] >> 8);
 }
 
+void orc_division_draws(uint32_t seed, uint32_t replica, int64_t t, int32_t x,
+                        int64_t y_abs, double *U_out, uint64_t *axes_out)
+{
+    uint32_t key[2] = {seed, replica};
+    uint32_t ctr[4] = {(uint32_t)x, (uint32_t)y_abs, (uint32_t)t, 4u * STREAM_DIVISION + 0u};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    /* 26 + 26 bits of the first two words; n + 1/2 is exact in double */
+    uint64_t n = ((uint64_t)(r[0] >> 6) << 26) | (uint64_t)(r[1] >> 6);
+    *U_out = ((double)n + 0.5) * (1.0 / 4503599627370496.0);
+    *axes_out = ((uint64_t)r[3] << 32) | (uint64_t)r[2];
+}
+
+/* ----------------------------------------------------------------------- */
+/* Poisson counts for the division laws                                      */
+/* ----------------------------------------------------------------------- */
+double orc_exp_neg(double lam)
+{
+    /* e^-lam = (e^-m)^16 with m = lam / 16 <= 1/2: the Taylor series of e^-m
+     * through the m^17 term, by Horner's rule
+     *   e^-m = 1 - (m/1)(1 - (m/2)(1 - (m/3)(... (1 - m/17)))),
+     * then squared four times */
+    double m = lam * 0.0625;
+    double r = 1.0;
+    for (int n = 17; n >= 1; --n) {
+        double q = m / (double)n;
+        r = 1.0 - q * r;
+    }
+    for (int i = 0; i < 4; ++i) r = r * r;
+    return r;
+}
+
+int orc_poisson_k(double U, double lam)
+{
+    /* smallest k with U <= P(0) + ... + P(k), P(k) = e^-lam lam^k / k! */
+    double pk = orc_exp_neg(lam);
+    double cdf = pk;
+    int k = 0;
+    while (U > cdf && k < 32) {
+        k = k + 1;
+        pk = pk * lam / (double)k;
+        cdf = cdf + pk;
+    }
+    return k;
+}
+
 /* ----------------------------------------------------------------------- */
 /* Eq. 3 on D2Q9                                                             */
 /* ----------------------------------------------------------------------- */
@@ -157,6 +203,8 @@ struct orc_state {
     int64_t    h_hi;
     double     mass, src_total, fix_total, retired, hbar, W;
     uint32_t   status;
+    double     lam;        /* division laws: lam of the next step              */
+    int64_t    divisions;  /* cumulative divisions                             */
 };
 
 static size_t idx(const orc_params *p, int i, int32_t j, int32_t x)
@@ -174,7 +222,11 @@ static int params_valid(const orc_params *p)
     if (!(p->init_amp >= 0.0 && p->init_amp < 1.0)) return 0;
     if (!(p->rho_init >= 0.0)) return 0;
     if (p->init_rows < 0 || p->init_rows > p->H) return 0;
-    if (p->growth != ORC_GROWTH_NONE && p->growth != ORC_GROWTH_BULK) return 0;
+    if (p->growth < ORC_GROWTH_NONE || p->growth > ORC_GROWTH_DIVISION_DENSITY) return 0;
+    if ((p->growth == ORC_GROWTH_DIVISION || p->growth == ORC_GROWTH_DIVISION_DENSITY) &&
+        !(p->rho_cell > 0.0))
+        return 0;
+    if (p->growth == ORC_GROWTH_DIVISION_DENSITY && !(p->rho0 > p->rho_c)) return 0;
     if (p->region < ORC_REGION_ALL || p->region > ORC_REGION_REAR_BAND) return 0;
     if (p->region != ORC_REGION_ALL && p->region_width < 0) return 0;
     if (p->ybc < ORC_Y_WALL_FIXED || p->ybc > ORC_Y_PERIODIC) return 0;
@@ -222,17 +274,66 @@ static double sum9(const double v[9])
     return s;
 }
 
+static int division_law(const orc_params *p)
+{
+    return p->growth == ORC_GROWTH_DIVISION || p->growth == ORC_GROWTH_DIVISION_DENSITY;
+}
+
+/* Division laws: whether a tissue site of density rho may divide, and its
+ * acceptance probability q (1 for the uniform draw; Eq. 5 for the density
+ * law: 1 - rho / rho0 above rho_c, none otherwise). */
+static int division_eligible(const orc_params *p, double rho, int in_reg, double *q)
+{
+    *q = 1.0;
+    if (!division_law(p) || !in_reg) return 0;
+    if (p->growth == ORC_GROWTH_DIVISION_DENSITY) {
+        *q = 1.0 - rho / p->rho0;
+        return rho > p->rho_c && *q > 0.0;
+    }
+    return 1;
+}
+
+/* The site's weight in the normaliser of the next step's rate: 1 per
+ * eligible site, or its acceptance probability in units of 2^-24 (integers,
+ * so that the sum does not depend on its order). */
+static int64_t division_weight(const orc_params *p, double q)
+{
+    return p->growth == ORC_GROWTH_DIVISION ? 1 : (int64_t)(q * 16777216.0);
+}
+
+/* A site's density in units of 2^-24, truncated (the mass m_tot of the
+ * division laws is summed in these integers). */
+static int64_t mass_fx(double rho)
+{
+    return (int64_t)(rho * 16777216.0);
+}
+
+/* Expected divisions per unit weight: n_s = g m_tot / rho_cell divisions
+ * (Sec. II) shared by the total weight of the eligible sites. */
+static double division_lam(const orc_params *p, int64_t mfx, int64_t wsum)
+{
+    if (!division_law(p) || wsum <= 0) return 0.0;
+    double m_tot = (double)mfx * (1.0 / 16777216.0);
+    double ns = p->growth_rate * m_tot / p->rho_cell;
+    double wt = (p->growth == ORC_GROWTH_DIVISION) ? (double)wsum
+                                                   : (double)wsum * (1.0 / 16777216.0);
+    return ns / wt;
+}
+
 /* ----------------------------------------------------------------------- */
 /* Steps 2-7 at one site                                                     */
 /* ----------------------------------------------------------------------- */
 int orc_update_site(const orc_params *p, const double fstar_in[9], int64_t t,
                     int32_t x, int64_t y_abs, int32_t h_prev_x, int64_t y_wall,
-                    int force, double out[9], double *S_out, double *dfix_out)
+                    int force, double lam, double out[9], double *S_out,
+                    double *dfix_out, int32_t *ndiv_out, int64_t *wfx_out)
 {
     double fs[9];
     for (int i = 0; i < 9; ++i) fs[i] = fstar_in[i];
     *S_out = 0.0;
     *dfix_out = 0.0;
+    *ndiv_out = 0;
+    *wfx_out = 0;
 
     /* step 2: density and momentum of the streamed populations (Eq. 1) */
     double rho_star = sum9(fs);
@@ -256,6 +357,36 @@ int orc_update_site(const orc_params *p, const double fstar_in[9], int64_t t,
         S = p->growth_rate * rho_star;
     double s8 = S * 0.125;
     for (int i = 1; i < 9; ++i) fs[i] = fs[i] + s8;
+    /* step 3, division laws: the paper injects rho_cell / 2 into both
+     * directions of a randomly oriented axis at n_s sites drawn with
+     * replacement (accepted with probability q under Eq. 5).  Drawing each
+     * site's number of divisions from a Poisson law with mean lam q, site by
+     * site and independently, gives the same expected divisions per site;
+     * lam spreads n_s over the eligible sites' total weight. */
+    double q;
+    if (division_eligible(p, rho_star, in_region(p, y_abs, h_prev_x, y_wall), &q)) {
+        *wfx_out = division_weight(p, q);
+        double l = lam * q;
+        if (l > 8.0) l = 8.0;
+        if (l > 0.0) {
+            double U;
+            uint64_t axes;
+            orc_division_draws(p->seed, p->replica, t, x, y_abs, &U, &axes);
+            int k = orc_poisson_k(U, l);
+            /* two bits per division choose the axis: 1-3, 2-4, 5-7 or 6-8 */
+            static const int AXIS[4] = {1, 2, 5, 6};
+            int count[4] = {0, 0, 0, 0};
+            for (int d = 0; d < k; ++d) count[(axes >> (2 * d)) & 3u] += 1;
+            double half = p->rho_cell * 0.5;
+            for (int a = 0; a < 4; ++a) {
+                double amount = (double)count[a] * half;
+                fs[AXIS[a]] = fs[AXIS[a]] + amount;
+                fs[OPP[AXIS[a]]] = fs[OPP[AXIS[a]]] + amount;
+            }
+            S = (double)k * p->rho_cell;
+            *ndiv_out = k;
+        }
+    }
     double rho = rho_star + S;
     *S_out = S;
 
@@ -343,6 +474,40 @@ static double window_mass(const orc_state *s)
     return m;
 }
 
+/* Window mass in units of 2^-24, site by site (see mass_fx). */
+static int64_t window_mass_fx(const orc_state *s)
+{
+    const orc_params *p = &s->p;
+    int64_t m = 0;
+    for (int32_t j = 0; j < p->H; ++j)
+        for (int32_t x = 0; x < p->L; ++x) {
+            double v[9];
+            for (int i = 0; i < 9; ++i) v[i] = s->f[idx(p, i, j, x)];
+            m += mass_fx(sum9(v));
+        }
+    return m;
+}
+
+/* Division laws on a state given as populations (the initial state, or one
+ * set from outside): its sites count as eligible by their own density, with
+ * the current front heights. */
+static void division_rates_from_state(orc_state *s)
+{
+    const orc_params *p = &s->p;
+    int64_t wsum = 0;
+    for (int32_t j = 0; j < p->H; ++j)
+        for (int32_t x = 0; x < p->L; ++x) {
+            double v[9];
+            for (int i = 0; i < 9; ++i) v[i] = s->f[idx(p, i, j, x)];
+            double rho = sum9(v), q;
+            int64_t y_abs = s->y_wall + j;
+            if (rho >= p->rho_c &&
+                division_eligible(p, rho, in_region(p, y_abs, s->h[x], s->y_wall), &q))
+                wsum += division_weight(p, q);
+        }
+    s->lam = division_lam(p, window_mass_fx(s), wsum);
+}
+
 static void check_front(orc_state *s)
 {
     const orc_params *p = &s->p;
@@ -399,6 +564,7 @@ orc_state *orc_create(const orc_params *p)
     s->h_hi = 0;
     s->mass = window_mass(s);
     width_of(s, &s->hbar, &s->W);
+    division_rates_from_state(s);
     check_front(s);
     return s;
 }
@@ -451,18 +617,23 @@ int orc_step(orc_state *s, int64_t nsteps)
     for (int64_t n = 0; n < nsteps; ++n) {
         if (s->status & ORC_ST_DOMAIN_FULL) return -4;
         double src = 0.0, fix = 0.0;
+        int64_t wsum = 0;
         int32_t *h_new = (int32_t *)malloc((size_t)p->L * sizeof(int32_t));
         for (int32_t x = 0; x < p->L; ++x) h_new[x] = (int32_t)s->y_wall;
         for (int32_t j = 0; j < p->H; ++j) {
             int64_t y_abs = s->y_wall + j;
             for (int32_t x = 0; x < p->L; ++x) {
                 double fstar[9], out[9], S, dfix;
+                int32_t ndiv;
+                int64_t wfx;
                 orc_pull_site(p, s->f, x, j, fstar);
-                int tissue = orc_update_site(p, fstar, s->t, x, y_abs, s->h[x],
-                                             s->y_wall, -1, out, &S, &dfix);
+                int tissue = orc_update_site(p, fstar, s->t, x, y_abs, s->h[x], s->y_wall, -1,
+                                             s->lam, out, &S, &dfix, &ndiv, &wfx);
                 for (int i = 0; i < 9; ++i) s->fn[idx(p, i, j, x)] = out[i];
                 src += S;
                 fix += dfix;
+                s->divisions += ndiv;
+                wsum += wfx;
                 if (tissue && y_abs + 1 > h_new[x]) h_new[x] = (int32_t)(y_abs + 1);
             }
         }
@@ -478,6 +649,10 @@ int orc_step(orc_state *s, int64_t nsteps)
             advance_wall(s);
             width_of(s, &s->hbar, &s->W);
         }
+        /* division laws: the next step shares g m_tot / rho_cell divisions
+         * over the weight of the sites eligible at this step (the sites
+         * eligible at the next step are known only as it runs) */
+        s->lam = division_lam(p, window_mass_fx(s), wsum);
         check_front(s);
     }
     return (s->status & ORC_ST_DOMAIN_FULL) ? -4 : 0;
@@ -495,6 +670,8 @@ void orc_diagnostics(const orc_state *s, orc_diag *d)
     d->y_wall = s->y_wall;
     d->h_hi = s->h_hi;
     d->status = s->status;
+    d->lam = s->lam;
+    d->divisions = s->divisions;
 }
 
 void orc_front_heights(const orc_state *s, int32_t *h_out)
@@ -511,12 +688,14 @@ void orc_set_populations(orc_state *s, const double *f_in)
 {
     memcpy(s->f, f_in, 9u * (size_t)s->p.L * (size_t)s->p.H * sizeof(double));
     s->mass = window_mass(s);
+    division_rates_from_state(s);
 }
 
 void orc_set_front_heights(orc_state *s, const int32_t *h_in)
 {
     memcpy(s->h, h_in, (size_t)s->p.L * sizeof(int32_t));
     width_of(s, &s->hbar, &s->W);
+    division_rates_from_state(s);
 }
 
 void orc_set_step(orc_state *s, int64_t t)

@@ -23,8 +23,13 @@
 extern "C" {
 #endif
 
-/* growth law (Sec. II, mass injection between streaming and redistribution) */
-enum { ORC_GROWTH_NONE = 0, ORC_GROWTH_BULK = 1 };
+/* growth law (Sec. II, mass injection between streaming and redistribution):
+ * none; the expectation of the paper's injection spread over every tissue
+ * site (bulk); or the paper's discrete cell divisions, at tissue sites drawn
+ * uniformly (division) or accepted with the density-dependent probability of
+ * Eq. 5 (division_density) */
+enum { ORC_GROWTH_NONE = 0, ORC_GROWTH_BULK = 1, ORC_GROWTH_DIVISION = 2,
+       ORC_GROWTH_DIVISION_DENSITY = 3 };
 /* proliferating region: everywhere, a band of width ell below the front, or a
  * band of width d above the rear wall (Appendix B) */
 enum { ORC_REGION_ALL = 0, ORC_REGION_FRONT_BAND = 1, ORC_REGION_REAR_BAND = 2 };
@@ -52,6 +57,8 @@ typedef struct {
     double   wall_w_factor;  /*   the mean front height (Appendix A)          */
     uint32_t seed;           /* Philox key word 0                             */
     uint32_t replica;        /* Philox key word 1                             */
+    double   rho_cell;       /* mass of one cell (division laws), Sec. II     */
+    double   rho0;           /* density above which division stops, Eq. 5     */
 } orc_params;
 
 typedef struct {
@@ -64,6 +71,9 @@ typedef struct {
     int64_t  y_wall;         /* absolute row of the first live row            */
     int64_t  h_hi;           /* largest front height seen so far              */
     uint32_t status;         /* ORC_ST_* bits                                 */
+    double   lam;            /* division laws: expected divisions per drawn
+                                site (unit weight) at the next step           */
+    int64_t  divisions;      /* cumulative number of cell divisions           */
 } orc_diag;
 
 typedef struct orc_state orc_state;
@@ -80,6 +90,18 @@ void orc_noise_uniforms(uint32_t seed, uint32_t replica, int64_t t, int32_t x,
 /* Uniform of the initial-density draw at (x, y). */
 double orc_init_uniform(uint32_t seed, uint32_t replica, int32_t x, int64_t y_abs);
 
+/* Division draws of one site at step t: a uniform U = (n + 1/2) 2^-52 on
+ * (0, 1) from 52 random bits (the Poisson count) and 64 bits of division
+ * axes, two per division. */
+void orc_division_draws(uint32_t seed, uint32_t replica, int64_t t, int32_t x,
+                        int64_t y_abs, double *U_out, uint64_t *axes_out);
+/* e^-lam for 0 <= lam <= 8 from basic arithmetic only (so that any two IEEE
+ * implementations agree bit for bit). */
+double orc_exp_neg(double lam);
+/* Poisson(lam) count by inversion of its distribution function at U,
+ * capped at 32. */
+int orc_poisson_k(double U, double lam);
+
 /* Lattice constants as used by the oracle (for the closed-form pins). */
 void orc_lattice(int32_t cx[9], int32_t cy[9], int32_t opp[9], double w[9]);
 
@@ -94,11 +116,16 @@ void orc_pull_site(const orc_params *p, const double *f, int32_t x, int32_t j,
 
 /* Steps 2-7 of Appendix A at one site, given its streamed populations.
  * force: -1 classify by density, 0 force the void branch, 1 force tissue.
+ * lam: the division laws' expected divisions per unit weight at this step.
  * Returns 1 if the site was classified tissue.  S_out: injected mass,
- * dfix_out: mass change of the negative-value fix. */
+ * dfix_out: mass change of the negative-value fix, ndiv_out: divisions at
+ * the site, wfx_out: the site's weight for the division laws' normaliser
+ * (1 per eligible site, or 2^24 x its acceptance probability; 0 if not
+ * eligible). */
 int orc_update_site(const orc_params *p, const double fstar[9], int64_t t,
                     int32_t x, int64_t y_abs, int32_t h_prev_x, int64_t y_wall,
-                    int force, double out[9], double *S_out, double *dfix_out);
+                    int force, double lam, double out[9], double *S_out,
+                    double *dfix_out, int32_t *ndiv_out, int64_t *wfx_out);
 
 size_t     orc_state_bytes(const orc_params *p);
 orc_state *orc_create(const orc_params *p);        /* NULL if p invalid */

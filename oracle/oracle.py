@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "lbm_oracle.c")
 _LIB = os.environ.get("LBM_ORACLE_LIB") or os.path.join(_HERE, "liblbm_oracle.so")
 
-GROWTH = {"none": 0, "bulk": 1}
+GROWTH = {"none": 0, "bulk": 1, "division": 2, "division_density": 3}
 REGION = {"all": 0, "front_band": 1, "rear_band": 2}
 YBC = {"fixed": 0, "follow": 1, "periodic": 2}
 ST_DOMAIN_FULL = 1
@@ -51,6 +51,7 @@ class _Params(ctypes.Structure):
         ("ybc", ctypes.c_int32), ("wall_min_gap", ctypes.c_int32),
         ("wall_w_factor", ctypes.c_double),
         ("seed", ctypes.c_uint32), ("replica", ctypes.c_uint32),
+        ("rho_cell", ctypes.c_double), ("rho0", ctypes.c_double),
     ]
 
 
@@ -61,6 +62,7 @@ class _Diag(ctypes.Structure):
         ("hbar", ctypes.c_double), ("W", ctypes.c_double),
         ("step", ctypes.c_int64), ("y_wall", ctypes.c_int64), ("h_hi", ctypes.c_int64),
         ("status", ctypes.c_uint32),
+        ("lam", ctypes.c_double), ("divisions", ctypes.c_int64),
     ]
 
 
@@ -89,8 +91,16 @@ def lib():
                                     ctypes.c_int32, dp]
         L.orc_update_site.argtypes = [ctypes.POINTER(_Params), dp, ctypes.c_int64,
                                       ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
-                                      ctypes.c_int64, ctypes.c_int, dp, dp, dp]
+                                      ctypes.c_int64, ctypes.c_int, ctypes.c_double, dp, dp, dp,
+                                      i32p, ctypes.POINTER(ctypes.c_int64)]
         L.orc_update_site.restype = ctypes.c_int
+        L.orc_division_draws.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
+                                         ctypes.c_int32, ctypes.c_int64, dp,
+                                         ctypes.POINTER(ctypes.c_uint64)]
+        L.orc_exp_neg.argtypes = [ctypes.c_double]
+        L.orc_exp_neg.restype = ctypes.c_double
+        L.orc_poisson_k.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_poisson_k.restype = ctypes.c_int
         L.orc_create.argtypes = [ctypes.POINTER(_Params)]
         L.orc_create.restype = ctypes.c_void_p
         L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
@@ -130,6 +140,8 @@ def make_params(cfg: dict) -> _Params:
     p.wall_w_factor = float(cfg.get("wall_w_factor", 10.0))
     p.seed = int(cfg.get("seed", 0)) & 0xFFFFFFFF
     p.replica = int(cfg.get("replica", 0)) & 0xFFFFFFFF
+    p.rho_cell = float(cfg.get("rho_cell", 0.1))
+    p.rho0 = float(cfg.get("rho0", 1.5))
     return p
 
 
@@ -158,6 +170,22 @@ def init_uniform(seed, replica, x, y) -> float:
     return float(lib().orc_init_uniform(seed, replica, x, y))
 
 
+def division_draws(seed, replica, t, x, y):
+    """(U, axes): the Poisson uniform and the 64 axis bits of one site."""
+    U = ctypes.c_double()
+    ax = ctypes.c_uint64()
+    lib().orc_division_draws(seed, replica, t, x, y, ctypes.byref(U), ctypes.byref(ax))
+    return U.value, ax.value
+
+
+def exp_neg(lam: float) -> float:
+    return float(lib().orc_exp_neg(float(lam)))
+
+
+def poisson_k(U: float, lam: float) -> int:
+    return int(lib().orc_poisson_k(float(U), float(lam)))
+
+
 def lattice():
     cx = np.zeros(9, np.int32)
     cy = np.zeros(9, np.int32)
@@ -184,18 +212,25 @@ def pull_site(cfg_or_params, f: np.ndarray, x: int, j: int) -> np.ndarray:
     return out
 
 
-def update_site(cfg_or_params, fstar, t, x, y_abs, h_prev_x, y_wall=0, force=-1):
-    """Steps 2-7 at one site.  Returns (f_out[9], tissue, S, dfix)."""
+def update_site_ex(cfg_or_params, fstar, t, x, y_abs, h_prev_x, y_wall=0, force=-1, lam=0.0):
+    """Steps 2-7 at one site.  Returns (f_out[9], tissue, S, dfix, ndiv, wfx)."""
     p = cfg_or_params if isinstance(cfg_or_params, _Params) else make_params(cfg_or_params)
     fs = np.ascontiguousarray(fstar, dtype=np.float64)
     out = np.zeros(9, np.float64)
     S = ctypes.c_double()
     dfix = ctypes.c_double()
+    nd = ctypes.c_int32()
+    wfx = ctypes.c_int64()
     tissue = lib().orc_update_site(ctypes.byref(p), _ptr(fs, ctypes.c_double), int(t),
                                    int(x), int(y_abs), int(h_prev_x), int(y_wall), int(force),
-                                   _ptr(out, ctypes.c_double), ctypes.byref(S),
-                                   ctypes.byref(dfix))
-    return out, bool(tissue), S.value, dfix.value
+                                   float(lam), _ptr(out, ctypes.c_double), ctypes.byref(S),
+                                   ctypes.byref(dfix), ctypes.byref(nd), ctypes.byref(wfx))
+    return out, bool(tissue), S.value, dfix.value, nd.value, wfx.value
+
+
+def update_site(cfg_or_params, fstar, t, x, y_abs, h_prev_x, y_wall=0, force=-1, lam=0.0):
+    """Steps 2-7 at one site.  Returns (f_out[9], tissue, S, dfix)."""
+    return update_site_ex(cfg_or_params, fstar, t, x, y_abs, h_prev_x, y_wall, force, lam)[:4]
 
 
 class Oracle:

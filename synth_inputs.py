@@ -35,6 +35,10 @@ BASE = dict(
     seed=0,
     replica=0,
     precision="fp64",
+    # division laws (Sec. II, Eq. 5): mass of one cell and the density above
+    # which division stops, from the paper's 0.01 and 0.15 at rho_init = 0.1
+    rho_cell=0.1,
+    rho0=1.5,
 )
 
 
