@@ -108,6 +108,10 @@ def main():
                     help="bulk: 4096 x 4096 bulk growth (default); edge: 2048 x 8192 growth "
                          "within 8 rows of the front; ensemble: 256 replicas of uneven size, "
                          "batched, against the same runs stepped one after another")
+    ap.add_argument("--growth", default=None, choices=["bulk", "division", "division_density"],
+                    help="bulk / edge: the growth law (default: the workload's own, a "
+                         "continuous source); division draws discrete cell divisions per site, "
+                         "division_density accepts them with Eq. 5's density weight")
     ap.add_argument("--tuned", action="store_true", help="launch shapes from the autotuner cache")
     ap.add_argument("--shape", default=None, help="force a launch shape: kernel_vb,kernel_ty")
     args = ap.parse_args()
@@ -130,6 +134,8 @@ def main():
         return bench_precision(args)
     base = si.BULK_4096_FP32 if args.workload == "bulk" else si.EDGE_2048x8192
     cfg = dict(base, precision=args.precision)
+    if args.growth and args.growth != cfg["growth"]:
+        cfg.update(growth=args.growth, name=f"{cfg['name']}_{args.growth}")
     if args.tuned:
         from paper_2303_02210_amd import autotune
         cfg = autotune.apply(cfg)
@@ -188,7 +194,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[args.precision], "data": "synthetic",
         "config": {"workload": cfg["name"], "L": L, "H": H, "precision": args.precision,
-                   "growth": cfg["region"] if cfg["region"] != "all" else "bulk",
+                   "growth": cfg["growth"], "region": cfg["region"],
                    "growth_rate": cfg["growth_rate"], "tau": cfg["tau"], "sigma": cfg["sigma"],
                    "init_rows": cfg["init_rows"], "h_every": every, "sweep": "full",
                    "bytes_per_update": bpu,

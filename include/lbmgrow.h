@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1u
+#define LBM_ABI_VERSION 2u
 
 typedef struct lbm_handle lbm_handle;
 typedef struct lbm_batch lbm_batch;
@@ -67,7 +67,15 @@ typedef enum {
 /* Growth law (Sec. II, mass injection between streaming and redistribution). */
 typedef enum {
     LBM_GROWTH_NONE = 0,
-    LBM_GROWTH_BULK = 1      /* every tissue site of the region gains g rho*  */
+    LBM_GROWTH_BULK = 1,     /* every tissue site of the region gains g rho*
+                                (the expectation of the paper's injection)    */
+    LBM_GROWTH_DIVISION = 2, /* discrete divisions: rho_cell / 2 on both
+                                directions of a random axis, at a Poisson
+                                number per tissue site of the region, n_s =
+                                g m_tot / rho_cell per step in expectation    */
+    LBM_GROWTH_DIVISION_DENSITY = 3  /* as DIVISION, each site weighted by
+                                the probability 1 - rho / rho0 of Eq. 5 (rho
+                                the streamed density; none at or below rho_c) */
 } lbm_growth;
 
 /* Proliferating region. */
@@ -106,7 +114,14 @@ typedef enum {
  *                 [0, 1); rows above empty.
  *   growth, growth_rate
  *                 lbm_growth and the rate g >= 0 (mass per unit tissue mass per
- *                 step; Sec. II).
+ *                 step; Sec. II).  The division laws draw each eligible site's
+ *                 divisions from a Poisson law of mean lam q (q = 1, or Eq. 5's
+ *                 probability), lam = n_s over the total q of the sites eligible
+ *                 at the previous step; m_tot is the window mass then.  They
+ *                 run the per-step device bookkeeping (as the follow wall does).
+ *   rho_cell, rho0
+ *                 division laws: the mass of one cell (> 0), and the density
+ *                 at which division stops (Eq. 5; > rho_c).
  *   region, region_width
  *                 lbm_region and its width (>= 0).
  *   sigma         noise amplitude of Eq. 4, sigma >= 0.
@@ -151,6 +166,8 @@ typedef struct {
     uint32_t seed, replica;
     int32_t  kernel_vb;
     int32_t  kernel_ty;
+    double   rho_cell;
+    double   rho0;
 } lbm_params;
 
 /* Diagnostics after the last enqueued step (all reductions in float64). */
@@ -165,6 +182,8 @@ typedef struct {
     int64_t  h_hi;        /* highest front height seen since creation         */
     uint32_t status;      /* LBM_ST_* bits latched on the device              */
     uint32_t reserved;
+    double   lam;         /* division laws: lam of the next step              */
+    int64_t  divisions;   /* division laws: cell divisions since creation     */
 } lbm_diag;
 
 #define LBM_ST_DOMAIN_FULL 1u

@@ -702,3 +702,8 @@ void orc_set_step(orc_state *s, int64_t t)
 {
     s->t = t;
 }
+
+void orc_set_lam(orc_state *s, double lam)
+{
+    s->lam = lam;
+}

@@ -140,6 +140,9 @@ void       orc_set_populations(orc_state *s, const double *f_in);
 void       orc_set_front_heights(orc_state *s, const int32_t *h_in);
 /* set the step counter (the noise of the next step is drawn at counter t) */
 void       orc_set_step(orc_state *s, int64_t t);
+/* division laws: set lam of the next step (it otherwise comes from the
+ * previous step, or from the state's own densities after a set) */
+void       orc_set_lam(orc_state *s, double lam);
 
 #ifdef __cplusplus
 }

@@ -112,6 +112,7 @@ def lib():
         L.orc_set_populations.argtypes = [ctypes.c_void_p, dp]
         L.orc_set_front_heights.argtypes = [ctypes.c_void_p, i32p]
         L.orc_set_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        L.orc_set_lam.argtypes = [ctypes.c_void_p, ctypes.c_double]
     return _lib
 
 
@@ -286,3 +287,6 @@ class Oracle:
 
     def set_step(self, t: int) -> None:
         lib().orc_set_step(self._h, int(t))
+
+    def set_lam(self, lam: float) -> None:
+        lib().orc_set_lam(self._h, float(lam))

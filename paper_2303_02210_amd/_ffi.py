@@ -12,7 +12,7 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblbmgrow.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 OK = 0
 E_INVALID, E_NOMEM, E_DEVICE, E_DOMAIN_FULL, E_NONFINITE, E_UNSUPPORTED, E_STATE = (
@@ -23,7 +23,7 @@ ERROR_NAMES = {0: "OK", -1: "LBM_E_INVALID", -2: "LBM_E_NOMEM", -3: "LBM_E_DEVIC
 
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 STORAGE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
-GROWTH = {"none": 0, "bulk": 1}
+GROWTH = {"none": 0, "bulk": 1, "division": 2, "division_density": 3}
 REGION = {"all": 0, "front_band": 1, "rear_band": 2}
 YBC = {"fixed": 0, "follow": 1, "periodic": 2}
 FLAG_WINDOW = 1
@@ -46,6 +46,7 @@ class Params(ctypes.Structure):
         ("wall_w_factor", ctypes.c_double), ("rho_ref", ctypes.c_double),
         ("seed", ctypes.c_uint32), ("replica", ctypes.c_uint32),
         ("kernel_vb", ctypes.c_int32), ("kernel_ty", ctypes.c_int32),
+        ("rho_cell", ctypes.c_double), ("rho0", ctypes.c_double),
     ]
 
 
@@ -56,6 +57,7 @@ class Diag(ctypes.Structure):
         ("hbar", ctypes.c_double), ("W", ctypes.c_double),
         ("step", ctypes.c_int64), ("y_wall", ctypes.c_int64), ("h_hi", ctypes.c_int64),
         ("status", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("lam", ctypes.c_double), ("divisions", ctypes.c_int64),
     ]
 
 
@@ -137,6 +139,8 @@ def make_params(cfg: dict) -> Params:
     p.flags = FLAG_WINDOW if cfg.get("window", False) else 0
     p.kernel_vb = int(cfg.get("kernel_vb", 0))
     p.kernel_ty = int(cfg.get("kernel_ty", 0))
+    p.rho_cell = float(cfg.get("rho_cell", 0.1))
+    p.rho0 = float(cfg.get("rho0", 1.5))
     return p
 
 

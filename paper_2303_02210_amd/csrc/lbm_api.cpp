@@ -136,7 +136,11 @@ bool params_ok(const lbm_params *p, std::string *why)
     if (!(p->rho_init >= 0.0) || !std::isfinite(p->rho_init)) return bad("rho_init must be >= 0");
     if (!(p->init_amp >= 0.0 && p->init_amp < 1.0)) return bad("init_amp must be in [0, 1)");
     if (p->init_rows < 0 || p->init_rows > p->H) return bad("init_rows out of range");
-    if (p->growth != LBM_GROWTH_NONE && p->growth != LBM_GROWTH_BULK) return bad("bad growth");
+    if (p->growth < LBM_GROWTH_NONE || p->growth > LBM_GROWTH_DIVISION_DENSITY) return bad("bad growth");
+    if (p->growth >= LBM_GROWTH_DIVISION && (!(p->rho_cell > 0.0) || !std::isfinite(p->rho_cell)))
+        return bad("rho_cell must be > 0");
+    if (p->growth == LBM_GROWTH_DIVISION_DENSITY && (!(p->rho0 > p->rho_c) || !std::isfinite(p->rho0)))
+        return bad("rho0 must be > rho_c");
     if (!(p->growth_rate >= 0.0) || !std::isfinite(p->growth_rate)) return bad("growth_rate must be >= 0");
     if (p->region < LBM_REGION_ALL || p->region > LBM_REGION_REAR_BAND) return bad("bad region");
     if (p->region_width < 0) return bad("region_width must be >= 0");
@@ -216,7 +220,7 @@ Layout make_layout(const lbm_params *p)
     const size_t hb = align_up((size_t)p->L * 4, kAlign);
     for (int k = 0; k < 3; ++k) { l.off_h[k] = o; o += hb; }
     l.off_colmax = o; o += hb;
-    l.off_partials = o; o += align_up((size_t)l.nblocks * 4 * 8, kAlign);
+    l.off_partials = o; o += align_up((size_t)l.nblocks * kPartialSlots * 8, kAlign);
     l.off_state = o; o += align_up(sizeof(DevState), kAlign);
     l.off_diag = o; o += align_up(sizeof(DiagOut), kAlign);
     l.off_rep = o; o += align_up(sizeof(BatchRep<double>), kAlign);
@@ -282,7 +286,12 @@ int do_init(lbm_handle *h)
     if ((rc = h->hip(launch_fill_i32(h->hslot(0), (int64_t)(l.off_partials - l.off_h[0]) / 4, 0, s),
                      "fill")))
         return rc;
-    if ((rc = h->hip(launch_fill_f64(h->partials(), (int64_t)l.nblocks * 4, 0.0, s), "fill")))
+    if ((rc = h->hip(launch_fill_f64(h->partials(), (int64_t)l.nblocks * kPartialSlots, 0.0, s), "fill")))
+        return rc;
+    // the device state, division tallies and counts included
+    if ((rc = h->hip(launch_fill_i32(reinterpret_cast<int32_t *>(h->st()),
+                                     (int64_t)(sizeof(DevState) / 4), 0, s),
+                     "fill")))
         return rc;
     if ((rc = h->hip(launch_state_set(h->st(), 0, p.H, p.H, 0, s), "state")))
         return rc;
@@ -341,6 +350,8 @@ void fill_step_args(const lbm_handle *h, StepArgs<S> &a)
     a.rho_c = (R)p.rho_c;
     a.g = (R)p.growth_rate;
     a.sigma = (R)p.sigma;
+    a.rho_cell = p.rho_cell;
+    a.rho0 = p.rho0;
     for (int i = 0; i < 9; ++i) {
         a.w[i] = (R)kW[i];
         a.Wd[i] = (R)h->Wd[i];
@@ -363,6 +374,9 @@ void fill_finalize_args(const lbm_handle *h, FinalizeArgs<S> &fa)
     fa.min_gap = p.wall_min_gap;
     fa.w_factor = p.wall_w_factor;
     for (int i = 0; i < 9; ++i) fa.Wd[i] = (R)h->Wd[i];
+    fa.growth = p.growth;
+    fa.g = p.growth_rate;
+    fa.rho_cell = p.rho_cell;
 }
 
 template <class S>
@@ -413,9 +427,19 @@ int do_mass(lbm_handle *h)
     a.ty = h->lay.ty;
     a.cpt = h->lay.cpt;
     a.tl = h->lay.tl;
+    a.h = h->hslot(h->t);
+    a.growth = h->p.growth;
+    a.region = h->p.region;
+    a.region_width = h->p.region_width;
+    a.rho_c = h->p.rho_c;
+    a.rho0 = h->p.rho0;
     for (int i = 0; i < 9; ++i) a.Wd[i] = (R)h->Wd[i];
-    return h->hip(launch_mass<S>(a, dim3(h->lay.gx, h->lay.gy), h->lay.nt, h->stream),
-                  "mass kernel");
+    int rc = h->hip(launch_mass<S>(a, dim3(h->lay.gx, h->lay.gy), h->lay.nt, h->stream),
+                    "mass kernel");
+    if (rc || h->p.growth < LBM_GROWTH_DIVISION) return rc;
+    // division laws: the next step's rate from this state
+    return h->hip(launch_rates(h->p.growth, h->p.growth_rate, h->p.rho_cell, h->st(), h->stream),
+                  "rates kernel");
 }
 
 #define LBM_DISPATCH(prec, fn, ...)                                   \
@@ -544,7 +568,10 @@ int lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *hip_str
     h->ws = reinterpret_cast<char *>(dev_ws);
     h->ws_bytes = ws_bytes;
     h->lay = lay;
-    h->device_driven = p->ybc == LBM_Y_WALL_FOLLOW || (p->flags & LBM_FLAG_WINDOW);
+    // (the division laws take their rate from the previous step's tallies,
+    // which the per-step finalize reduces)
+    h->device_driven = p->ybc == LBM_Y_WALL_FOLLOW || (p->flags & LBM_FLAG_WINDOW) ||
+                       p->growth >= LBM_GROWTH_DIVISION;
     h->mode = p->ybc == LBM_Y_PERIODIC ? kModePeriodic : (h->device_driven ? kModeDevice : kModeFixed);
     for (int i = 0; i < 9; ++i) h->Wd[i] = offset_base(p->precision, i, p->rho_ref);
     int rc = LBM_DISPATCH(p->precision, do_init, h);
@@ -555,6 +582,8 @@ int lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *hip_str
         if (nr < 1) nr = 1;
         rc = h->hip(launch_state_set(h->st(), 0, p->H, nr, 0, h->stream), "state");
     }
+    if (rc == LBM_OK && p->growth >= LBM_GROWTH_DIVISION)
+        rc = LBM_DISPATCH(p->precision, do_mass, h);   // the first step's division rate
     if (rc != LBM_OK) {
         delete h;
         return rc;
@@ -623,6 +652,8 @@ int lbm_diagnostics(lbm_handle *h, lbm_diag *out)
     out->h_hi = d.h_hi;
     out->status = d.status;
     out->reserved = 0;
+    out->lam = d.lam;
+    out->divisions = d.divisions;
     if (d.status & kStDomainFull) h->fail(LBM_E_DOMAIN_FULL, "front reached the top row of the window");
     if (d.status & kStNonFinite) h->fail(LBM_E_NONFINITE, "total mass is not finite");
     return LBM_OK;
@@ -700,6 +731,9 @@ int lbm_set_front_heights(lbm_handle *h, const int32_t *host_h)
                                h->stream),
                 "front heights copy");
     if (rc) return rc;
+    // the division laws' eligible sites may depend on the front (front band)
+    if (h->p.growth >= LBM_GROWTH_DIVISION && (rc = LBM_DISPATCH(h->p.precision, do_mass, h)))
+        return rc;
     return h->hip(hipStreamSynchronize(h->stream), "synchronize");
 }
 
@@ -708,7 +742,7 @@ size_t lbm_state_bytes(const lbm_handle *h)
     if (!h) return 0;
     const Layout &l = h->lay;
     return sizeof(BlobHeader) + l.nelem * l.esize + 2 * (size_t)h->p.L * 4 +
-           (size_t)l.nblocks * 4 * 8 + sizeof(DevState);
+           (size_t)l.nblocks * kPartialSlots * 8 + sizeof(DevState);
 }
 
 int lbm_get_state(lbm_handle *h, void *host_blob, size_t bytes)
@@ -725,7 +759,7 @@ int lbm_get_state(lbm_handle *h, void *host_blob, size_t bytes)
     hd.t = h->t;
     hd.fbytes = (uint64_t)(l.nelem * l.esize);
     hd.hbytes = (uint64_t)h->p.L * 4;
-    hd.pbytes = (uint64_t)l.nblocks * 4 * 8;
+    hd.pbytes = (uint64_t)l.nblocks * kPartialSlots * 8;
     std::memcpy(b, &hd, sizeof hd);
     size_t o = sizeof hd;
     struct Piece {
@@ -810,7 +844,7 @@ constexpr int kMaxGroups = 16;
 constexpr int kWindowGrid = 8192;   // blocks of a windowed group's launch
 
 struct BatchGroup {
-    int prec = 0, vec = 0, nt = 0, vbrb = 0, ty = 0, windowed = 0;   // kernel form
+    int prec = 0, vec = 0, nt = 0, vbrb = 0, ty = 0, windowed = 0, div = 0;   // kernel form
     std::vector<lbm_handle *> m;
     int64_t tiles = 0;                           // tiles over all members
     int grid = 0;                                // blocks per step launch
@@ -864,7 +898,7 @@ hipError_t enqueue_group_step(const BatchGroup &g, int k, hipStream_t s)
                                  g.table, g.count, s);
     if (e != hipSuccess) return e;
     return launch_step_batch<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps), g.table, g.count,
-                                g.grid, g.vec, g.nt, g.vbrb, k, s);
+                                g.grid, g.vec, g.nt, g.vbrb, g.div, k, s);
 }
 template <class S>
 hipError_t enqueue_group_finalize(const BatchGroup &g, int k, hipStream_t s)
@@ -916,10 +950,11 @@ struct lbm_batch {
         for (lbm_handle *h : members) {
             const int vbrb = h->lay.vec ? h->lay.vb : h->lay.rb;
             const int win = (h->p.flags & LBM_FLAG_WINDOW) ? 1 : 0;
+            const int div = h->p.growth >= LBM_GROWTH_DIVISION ? 1 : 0;
             BatchGroup *g = nullptr;
             for (BatchGroup &c : groups)
                 if (c.prec == h->p.precision && c.vec == (int)h->lay.vec && c.nt == h->lay.nt &&
-                    c.vbrb == vbrb && c.ty == h->lay.ty && c.windowed == win)
+                    c.vbrb == vbrb && c.ty == h->lay.ty && c.windowed == win && c.div == div)
                     g = &c;
             if (!g) {
                 if ((int)groups.size() == kMaxGroups) return LBM_E_INVALID;
@@ -931,6 +966,7 @@ struct lbm_batch {
                 g->vbrb = vbrb;
                 g->ty = h->lay.ty;
                 g->windowed = win;
+                g->div = div;
             }
             g->m.push_back(h);
         }

@@ -29,31 +29,56 @@ __global__ void state_set_kernel(DevState *st, int64_t y_wall, int64_t y_valid_t
         st->retired_total = 0.0;
         st->retired_last = 0.0;
         st->status = 0u;
+        st->lam = 0.0;
+        st->p0 = 1.0;
     }
+}
+
+// Division laws: the rate of the next step from the tallies of a state set
+// from outside (its creation or lbm_set_populations); nothing is retired and
+// no division is counted.
+__global__ __launch_bounds__(kRedThreads) void rates_kernel(int growth, double g, double rho_cell,
+                                                            DevState *st)
+{
+    __shared__ long long shi[2][kRedWaves];
+    long long v[2] = {0, 0};   // fixed-point mass, weight
+    long long ndiv = 0;
+    take_div_slots(st, v[0], v[1], ndiv);
+    block_reduce(v, shi);
+    if (threadIdx.x == 0)
+        set_division_rate(st, growth, division_lam(growth == kGrowthDivision, g, rho_cell, v[0], v[1]),
+                          0);
+}
+
+hipError_t launch_rates(int growth, double g, double rho_cell, DevState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(rates_kernel, dim3(1), dim3(kRedThreads), 0, s, growth, g, rho_cell, st);
+    return hipGetLastError();
 }
 
 // Diagnostics of the current state.
 __global__ __launch_bounds__(kRedThreads) void diag_kernel(DiagArgs a)
 {
-    __shared__ double shd[kRedThreads / 64];
-    __shared__ long long shi[kRedThreads / 64];
-    double m = 0.0, s = 0.0, fx = 0.0;
+    __shared__ double shd[3][kRedWaves];
+    __shared__ long long shi[2][kRedWaves];
+    double v[3] = {0.0, 0.0, 0.0};   // mass, injected, fix
     for (int b = threadIdx.x; b < a.nblocks; b += kRedThreads) {
-        m += a.partials[4 * b + 0];
-        s += a.partials[4 * b + 1];
-        fx += a.partials[4 * b + 2];
+        const double *p = a.partials + kPartialSlots * b;
+        v[0] += p[0];
+        v[1] += p[1];
+        v[2] += p[2];
     }
-    m = block_sum_d(m, shd);
-    s = block_sum_d(s, shd);
-    fx = block_sum_d(fx, shd);
+    block_reduce(v, shd);
+    const double m = v[0], s = v[1], fx = v[2];
     const int64_t y_wall = a.st->y_wall;
+    long long si[2] = {0, 0};
+    long long hm[1] = {LLONG_MIN};
+    height_sums(a.h_cur, a.colmax, a.L, y_wall, si[0], si[1], hm[0]);
+    block_reduce(si, shi);
+    block_reduce(hm, shi, OpMax());
     double hbar, W;
-    long long hmax;
-    height_stats(a.h_cur, a.L, y_wall, shi, hbar, W, hmax);
-    long long hi = LLONG_MIN;
-    for (int x = threadIdx.x; x < a.L; x += kRedThreads)
-        hi = (long long)a.colmax[x] > hi ? (long long)a.colmax[x] : hi;
-    hi = block_max_i(hi, shi);
+    height_stats(si[0], si[1], a.L, y_wall, hbar, W);
+    const long long hi = hm[0];
     if (threadIdx.x == 0) {
         DiagOut *o = a.out;
         const double mass = m - a.st->retired_last;
@@ -71,6 +96,8 @@ __global__ __launch_bounds__(kRedThreads) void diag_kernel(DiagArgs a)
         o->y_wall = y_wall;
         o->h_hi = hi;
         o->status = st;
+        o->lam = a.st->lam;
+        o->divisions = a.st->divisions;
     }
 }
 

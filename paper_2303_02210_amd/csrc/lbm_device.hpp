@@ -48,7 +48,7 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
 }
 
 // Counter word 3 is 4 * stream + call.
-enum : uint32_t { kStreamNoise = 0, kStreamInit = 1 };
+enum : uint32_t { kStreamNoise = 0, kStreamInit = 1, kStreamDivision = 2 };
 
 // Nine 24-bit draws for the noise of site (x, y) at step t: the top 24 bits of
 // the eight words of calls 0 and 1, and the low bytes of call 0's words 0-2.
@@ -72,6 +72,81 @@ __device__ __forceinline__ void noise_factors(uint32_t seed, uint32_t replica, u
         const int n = (int)(2u * k[i] + 1u) - (1 << 24);   // odd, |n| < 2^24: exact
         v[i] = (R)n * (R)(1.0 / 16777216.0);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Discrete cell divisions (Sec. II; Eq. 5).  Each eligible site draws its
+// number of divisions from a Poisson law: a uniform U = (n + 1/2) 2^-52 from
+// 52 random bits inverts the distribution function, whose terms use only
+// basic IEEE arithmetic (so every implementation draws the same count), and
+// two further random bits per division pick its axis.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void division_draws(uint32_t seed, uint32_t replica, uint32_t t,
+                                               uint32_t x, uint32_t y, double &U, uint64_t &axes)
+{
+    const U4 a = philox10(x, y, t, 4u * kStreamDivision + 0u, seed, replica);
+    const uint64_t n = ((uint64_t)(a.v[0] >> 6) << 26) | (uint64_t)(a.v[1] >> 6);
+    U = ((double)n + 0.5) * (1.0 / 4503599627370496.0);
+    axes = ((uint64_t)a.v[3] << 32) | (uint64_t)a.v[2];
+}
+
+// e^-lam, 0 <= lam <= 8: (e^-m)^16 with m = lam / 16 and e^-m from its
+// Taylor series through m^17 by Horner's rule.
+__device__ __forceinline__ double exp_neg(double lam)
+{
+    const double m = lam * 0.0625;
+    double r = 1.0;
+#pragma unroll
+    for (int n = 17; n >= 1; --n) {
+        const double q = m / (double)n;
+        r = 1.0 - q * r;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r = r * r;
+    return r;
+}
+
+// Smallest k with U <= P(0) + ... + P(k) for the Poisson law of mean lam,
+// capped at 32, given p0 = exp_neg(lam).
+__device__ __forceinline__ int poisson_k_from(double U, double lam, double p0)
+{
+    double pk = p0;
+    double cdf = pk;
+    int k = 0;
+    while (U > cdf && k < 32) {
+        k = k + 1;
+        pk = pk * lam / (double)k;
+        cdf = cdf + pk;
+    }
+    return k;
+}
+
+__device__ __forceinline__ int poisson_k(double U, double lam)
+{
+    return poisson_k_from(U, lam, exp_neg(lam));
+}
+
+// poisson_k(U, lam) without the exponential when U is plainly below P(0):
+// e^-lam > 1 - lam, and exp_neg's relative error (under 1e-14) is far inside
+// the margin 2^-40, so U < (1 - lam)(1 - 2^-40) implies U < exp_neg(lam) and
+// the count is 0.  At small means nearly every site takes this exit.
+__device__ __forceinline__ int poisson_k_small(double U, double lam)
+{
+    if (U < (1.0 - lam) * (1.0 - 0x1p-40)) return 0;
+    return poisson_k(U, lam);
+}
+
+// Expected divisions per unit weight: n_s = g m_tot / rho_cell divisions
+// (Sec. II) shared by the eligible sites' total weight; m_tot and the weight
+// are integers in units of 2^-24 (the uniform law weighs each site 1).
+__host__ __device__ inline double division_lam(bool uniform, double g, double rho_cell,
+                                               long long mfx, long long wsum)
+{
+    if (wsum <= 0) return 0.0;
+    const double m_tot = (double)mfx * (1.0 / 16777216.0);
+    const double ns = g * m_tot / rho_cell;
+    const double wt = uniform ? (double)wsum : (double)wsum * (1.0 / 16777216.0);
+    return ns / wt;
 }
 
 // Uniform (k + 1/2) 2^-24 of the initial density at (x, y).

@@ -21,6 +21,20 @@ template <>
 struct Real<__hip_bfloat16> { using type = float; };
 
 enum : int { kModeFixed = 0, kModeDevice = 1, kModePeriodic = 2 };
+enum : int { kGrowthNone = 0, kGrowthBulk = 1, kGrowthDivision = 2, kGrowthDivisionDensity = 3 };
+
+// Per-block tallies, kPartialSlots doubles per block: [0] mass of the block's
+// sites after the step, [1] injected mass and [2] mass change of the negative
+// fix (both accumulated over steps), [3] unused.
+constexpr int kPartialSlots = 4;
+// Division-law tallies of one step (integers, so their sum does not depend on
+// the order of the additions): blocks add theirs atomically to one of
+// kDivSlots slots of kDivSlotWords words (one 64-byte line each, to spread
+// the atomics), words [0] mass in units of 2^-24, [1] weight of the eligible
+// sites, [2] divisions.  The kernel that turns them into the next step's rate
+// clears them again.
+constexpr int kDivSlots = 64, kDivSlotWords = 8;
+constexpr double kFx = 16777216.0;      // 2^24: fixed-point unit of masses and weights
 enum : int { kRegionAll = 0, kRegionFrontBand = 1, kRegionRearBand = 2 };
 enum : uint32_t { kStDomainFull = 1u, kStNonFinite = 2u };
 
@@ -70,6 +84,10 @@ struct DevState {
     double   retired_last;  // ... by the last wall move
     uint32_t status;        // kSt* bits
     uint32_t pad;
+    double   lam;           // division laws: expected divisions per unit weight this step
+    double   p0;            // uniform division law: e^-min(lam, 8), no division at a site
+    int64_t  divisions;     // divisions so far
+    unsigned long long div_acc[kDivSlots][kDivSlotWords];
 };
 
 // Diagnostics record written by diag_kernel (layout of lbm_diag).
@@ -77,6 +95,8 @@ struct DiagOut {
     double   mass, src_total, fix_total, retired, hbar, W;
     int64_t  step, y_wall, h_hi;
     uint32_t status, reserved;
+    double   lam;
+    int64_t  divisions;
 };
 
 template <class S>
@@ -88,7 +108,7 @@ struct StepArgs {
     int32_t *h_next;
     int32_t *h_clear;       // slot to reset to the wall row (fixed modes), or null
     int32_t *colmax;        // per-column highest front
-    double *partials;       // [nblocks][4]: mass, injected, fix, spare
+    double *partials;       // [nblocks][kPartialSlots]: mass, injected, fix, spare
     DevState *st;
     int32_t L, H, ty;
     Tiles tl;
@@ -99,6 +119,7 @@ struct StepArgs {
     R omega, kmu, rho_c, g, sigma;
     R w[9];
     R Wd[9];
+    double rho_cell, rho0;  // division laws: cell mass, density where division stops
 };
 
 template <class S>
@@ -123,10 +144,13 @@ struct MassArgs {
     using R = typename Real<S>::type;
     const S *f;
     double *partials;
-    const DevState *st;
+    DevState *st;           // (division laws: the tallies are added to its slots)
+    const int32_t *h;       // front heights (division laws' front band)
     int32_t L, H, ty;
     int32_t cpt;            // columns per thread
     Tiles tl;
+    int32_t growth, region, region_width;
+    double rho_c, rho0;
     R Wd[9];
 };
 
@@ -143,6 +167,9 @@ struct FinalizeArgs {
     int32_t follow, window, min_gap;
     double w_factor;
     R Wd[9];
+    // division laws: the rate of the next step from the step's tallies
+    int32_t growth;
+    double g, rho_cell;
 };
 
 struct DiagArgs {
@@ -205,13 +232,14 @@ __host__ __device__ inline TileRef run_ref(int rep, int64_t l, int64_t strips, i
 
 template <class S>
 hipError_t launch_step(const StepArgs<S> &a, dim3 grid, int nt, int rb, hipStream_t s);
-// A batch group: n members with the same storage type and kernel form.
+// A batch group: n members with the same storage type and kernel form (div:
+// the members grow by the division laws).
 // reps: device array of member descriptors; table: the group's tiles;
 // count: device word holding how many table entries the next launch runs.
 // grid: blocks launched (each runs table entries blockIdx.x + i * grid).
 template <class S>
 hipError_t launch_step_batch(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
-                             int grid, int vec, int nt, int vb_or_rb, int k, hipStream_t s);
+                             int grid, int vec, int nt, int vb_or_rb, int div, int k, hipStream_t s);
 // Rebuild the table of a windowed group from its members' live rows.
 template <class S>
 hipError_t launch_plan_batch(BatchRep<S> *const *reps, int n, TileRef *table, int32_t *count,
@@ -232,6 +260,9 @@ hipError_t launch_mass(const MassArgs<S> &a, dim3 grid, int nt, hipStream_t s);
 template <class S>
 hipError_t launch_finalize(const FinalizeArgs<S> &a, hipStream_t s);
 hipError_t launch_diag(const DiagArgs &a, hipStream_t s);
+// Division laws: the rate of the next step from the tallies of a state set
+// from outside (creation, lbm_set_populations), nothing retired.
+hipError_t launch_rates(int growth, double g, double rho_cell, DevState *st, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_state_set(DevState *st, int64_t y_wall, int64_t y_valid_top, int64_t n_rows,

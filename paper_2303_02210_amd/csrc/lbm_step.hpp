@@ -88,28 +88,114 @@ __device__ __forceinline__ void lds_barrier()
     __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-__device__ __forceinline__ double wave_sum(double v)
+// Wavefront reductions by DPP lane moves, which stay in the vector ALU (a
+// shuffle through ds_bpermute costs an LDS round trip per 32 bits and level):
+// neighbours, pairs of neighbours, the mirrored half of each group of 8 and of
+// each row of 16 lanes, after which every lane of a row holds the row's
+// result; the four rows' results are then read from lanes 0, 16, 32 and 48.
+// The order of the operations is fixed, so float sums are deterministic.
+// Every lane of the wavefront must be active.
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp_move(uint64_t v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
 }
 
-// Deterministic block sum of three values (fixed tree), result in thread 0.
-template <int NT>
-__device__ __forceinline__ void block_sum3(double &a, double &b, double &c)
+__device__ __forceinline__ uint64_t read_lane(uint64_t v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+struct OpAdd {
+    template <class T>
+    __device__ __forceinline__ T operator()(T a, T b) const { return a + b; }
+};
+struct OpMax {
+    template <class T>
+    __device__ __forceinline__ T operator()(T a, T b) const { return a > b ? a : b; }
+};
+
+// (8-byte T: double or long long)
+template <class T, class Op = OpAdd>
+__device__ __forceinline__ T wave_reduce(T v, Op op = Op())
+{
+    static_assert(sizeof(T) == 8, "64-bit lanes");
+    constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kHalfMirror = 0x141, kMirror = 0x140;
+    v = op(v, __builtin_bit_cast(T, dpp_move<kXor1>(__builtin_bit_cast(uint64_t, v))));
+    v = op(v, __builtin_bit_cast(T, dpp_move<kXor2>(__builtin_bit_cast(uint64_t, v))));
+    v = op(v, __builtin_bit_cast(T, dpp_move<kHalfMirror>(__builtin_bit_cast(uint64_t, v))));
+    v = op(v, __builtin_bit_cast(T, dpp_move<kMirror>(__builtin_bit_cast(uint64_t, v))));
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const T r0 = __builtin_bit_cast(T, read_lane(u, 0));
+    const T r1 = __builtin_bit_cast(T, read_lane(u, 16));
+    const T r2 = __builtin_bit_cast(T, read_lane(u, 32));
+    const T r3 = __builtin_bit_cast(T, read_lane(u, 48));
+    return op(op(op(r0, r1), r2), r3);
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return wave_reduce(v); }
+
+// Division-law state of a thread: this step's mean per unit weight and, for
+// the uniform law, the chance e^-lam of no division (both read once from the
+// device state), and the tallies of its sites: the weight of the eligible
+// ones and the divisions they made.
+struct DivTally {
+    long long w = 0, n = 0;
+    double lam = 0.0, p0 = 1.0;
+};
+
+__device__ __forceinline__ DivTally div_begin(const DevState *st)
+{
+    DivTally d;
+    d.lam = st->lam;
+    d.p0 = st->p0;
+    return d;
+}
+
+__device__ __forceinline__ DivTally div_site(const DivTally &d)
+{
+    DivTally s;
+    s.lam = d.lam;
+    s.p0 = d.p0;
+    return s;
+}
+
+// Deterministic block sums of a tile's tallies (fixed tree), one LDS round:
+// the three masses end in thread 0; with the division laws, thread 0 also
+// adds the block's fixed-point mass, weight and divisions to one of the
+// step's slots in the device state.  Called by every thread of the block.
+template <int NT, bool DIV>
+__device__ __forceinline__ void block_tallies(double &a, double &b, double &c, long long mfx,
+                                              const DivTally &dv, DevState *st, int block)
 {
     constexpr int NW = NT / 64;
     __shared__ double red[3][NW];
+    __shared__ long long redi[3][NW];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     a = wave_sum(a);
     b = wave_sum(b);
     c = wave_sum(c);
+    long long i0 = 0, i1 = 0, i2 = 0;
+    if constexpr (DIV) {
+        i0 = wave_reduce(mfx);
+        i1 = wave_reduce(dv.w);
+        i2 = wave_reduce(dv.n);
+    }
     if (lane == 0) {
         red[0][wave] = a;
         red[1][wave] = b;
         red[2][wave] = c;
+        if constexpr (DIV) {
+            redi[0][wave] = i0;
+            redi[1][wave] = i1;
+            redi[2][wave] = i2;
+        }
     }
     lds_barrier();
     if (threadIdx.x == 0) {
@@ -122,8 +208,27 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c)
             b += red[1][w];
             c += red[2][w];
         }
+        if constexpr (DIV) {
+            long long t[3] = {0, 0, 0};
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                t[0] += redi[0][w];
+                t[1] += redi[1][w];
+                t[2] += redi[2][w];
+            }
+            unsigned long long *slot = st->div_acc[block & (kDivSlots - 1)];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (t[k] != 0) atomicAdd(slot + k, (unsigned long long)t[k]);
+        }
     }
-    lds_barrier();   // red is free again (a batch block goes on to more tiles)
+    lds_barrier();   // the arrays are free again (a batch block goes on to more tiles)
+}
+
+template <int NT>
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c)
+{
+    block_tallies<NT, false>(a, b, c, 0, DivTally(), nullptr, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -131,26 +236,62 @@ __device__ __forceinline__ void block_sum3(double &a, double &b, double &c)
 // given its streamed populations fs.  S_acc / x_acc collect the injected mass
 // and the mass change of the negative-population fix.
 // ---------------------------------------------------------------------------
-template <class S>
+template <class S, bool DIV>
 __device__ __forceinline__ void tissue_update(const StepArgs<S> &a, uint32_t t, typename Codec<S>::R fs[9],
                                               typename Codec<S>::R rho_s,
                                               typename Codec<S>::R out[9], uint32_t x, int64_t y,
                                               int64_t y_wall, int32_t hp, double &s_acc,
-                                              double &x_acc)
+                                              double &x_acc, DivTally &dv)
 {
     using R = typename Codec<S>::R;
     // ---- step 2 (rest): momentum ----------------------------------------------
     const R jx = ((((fs[1] - fs[3]) + fs[5]) - fs[6]) - fs[7]) + fs[8];
     const R jy = ((((fs[2] - fs[4]) + fs[5]) + fs[6]) - fs[7]) - fs[8];
-    // ---- step 3: growth source, shared by the 8 moving directions (opposite
-    // pairs receive equal amounts: no momentum) --------------------------------
-    bool grow = a.growth != 0;
-    if (a.region == kRegionFrontBand) grow = grow && (y >= (int64_t)hp - a.region_width);
-    else if (a.region == kRegionRearBand) grow = grow && (y < y_wall + a.region_width);
-    const R S_ = grow ? a.g * rho_s : R(0);
+    // ---- step 3: growth source.  Bulk law: its expectation, shared by the 8
+    // moving directions (opposite pairs receive equal amounts: no momentum) --
+    bool in_reg = true;
+    if (a.region == kRegionFrontBand) in_reg = (y >= (int64_t)hp - a.region_width);
+    else if (a.region == kRegionRearBand) in_reg = (y < y_wall + a.region_width);
+    R S_ = (a.growth == kGrowthBulk && in_reg) ? a.g * rho_s : R(0);
     const R s8 = S_ * R(0.125);
 #pragma unroll
     for (int i = 1; i < 9; ++i) fs[i] = fs[i] + s8;
+    // Division laws (Sec. II; Eq. 5): a Poisson number of divisions with mean
+    // lam q, each putting rho_cell / 2 on both directions of a drawn axis
+    if constexpr (DIV) if (in_reg) {
+        double q = 1.0;
+        bool elig = true;
+        if (a.growth == kGrowthDivisionDensity) {
+            q = 1.0 - (double)rho_s / a.rho0;
+            elig = rho_s > a.rho_c && q > 0.0;
+        }
+        if (elig) {
+            const bool uniform = a.growth == kGrowthDivision;
+            dv.w += uniform ? 1 : (long long)(q * kFx);
+            double l = dv.lam * q;
+            if (l > 8.0) l = 8.0;
+            if (l > 0.0) {
+                double U;
+                uint64_t axes;
+                division_draws(a.seed, a.replica, t, x, (uint32_t)y, U, axes);
+                // (uniform law: one mean for every site, its e^-lam precomputed)
+                const int k = uniform ? poisson_k_from(U, l, dv.p0) : poisson_k_small(U, l);
+                int count[4] = {0, 0, 0, 0};
+                for (int d = 0; d < k; ++d) count[(axes >> (2 * d)) & 3u] += 1;
+                const double half = a.rho_cell * 0.5;
+                constexpr int axis[4] = {1, 2, 5, 6};
+                constexpr int rev[4] = {3, 4, 7, 8};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const double amount = (double)count[c] * half;
+                    fs[axis[c]] = fs[axis[c]] + (R)amount;
+                    fs[rev[c]] = fs[rev[c]] + (R)amount;
+                }
+                S_ = (R)((double)k * a.rho_cell);
+                dv.n += k;
+            }
+        }
+    }
     const R rho = rho_s + S_;
     s_acc += (double)S_;
 
@@ -220,25 +361,43 @@ __device__ __forceinline__ void tissue_update(const StepArgs<S> &a, uint32_t t, 
 // validity already applied to fs (the decoded values).  The void branch of
 // step 5 only reverses directions, so it forwards the stored values as they
 // are.  Writes the stored result to so[9]; returns true for tissue.
-template <class S>
+// The division laws' fixed-point mass of a site: its density in units of
+// 2^-24, truncated (summed as integers, so in any order).
+__device__ __forceinline__ long long mass_fx(double rho)
+{
+    const double v = rho * kFx;
+    return fabs(v) < 2147483648.0 ? (long long)(int)v : (long long)v;
+}
+
+// (the same for a float density: scaling by 2^24 is exact in float too)
+__device__ __forceinline__ long long mass_fx(float rho)
+{
+    const float v = rho * 16777216.0f;
+    return fabsf(v) < 2147483648.0f ? (long long)(int)v : mass_fx((double)rho);
+}
+
+template <class S, bool DIV>
 __device__ __forceinline__ bool site_step(const StepArgs<S> &a, uint32_t t, const S v[9],
                                           typename Codec<S>::R fs[9], const typename Codec<S>::R Wd[9],
                                           S so[9], uint32_t x, int64_t y, int64_t y_wall, int32_t hp,
-                                          double &m_acc, double &s_acc, double &x_acc)
+                                          double &m_acc, double &s_acc, double &x_acc,
+                                          long long &mfx_acc, DivTally &dv)
 {
     using R = typename Codec<S>::R;
     // ---- step 2: density ---------------------------------------------------------
     const R rho_s = sum9(fs);
     if (rho_s >= a.rho_c) {
         R out[9];
-        tissue_update<S>(a, t, fs, rho_s, out, x, y, y_wall, hp, s_acc, x_acc);
+        tissue_update<S, DIV>(a, t, fs, rho_s, out, x, y, y_wall, hp, s_acc, x_acc, dv);
         R kept[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             so[i] = Codec<S>::enc(out[i], Wd[i]);
             kept[i] = Codec<S>::dec(so[i], Wd[i]);
         }
-        m_acc += (double)sum9(kept);
+        const R m = sum9(kept);
+        m_acc += (double)m;
+        if constexpr (DIV) mfx_acc += mass_fx(m);
         return true;
     }
     // ---- step 5 (void): reverse every direction ------------------------------------
@@ -246,6 +405,13 @@ __device__ __forceinline__ bool site_step(const StepArgs<S> &a, uint32_t t, cons
 #pragma unroll
     for (int i = 0; i < 9; ++i) so[i] = v[opp[i]];
     m_acc += (double)rho_s;
+    if constexpr (DIV) {
+        // the stored (reversed) values, summed in their stored order
+        R m = fs[opp[0]];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) m = m + fs[opp[i]];
+        mfx_acc += mass_fx(m);
+    }
     return false;
 }
 
@@ -311,7 +477,7 @@ struct StepIO {
     uint32_t t;
 };
 
-template <class S, int NT, int RB>
+template <class S, int NT, int RB, bool DIV>
 __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const StepIO<S> &io, int bx,
                                                  int by, int nbx, int nstrips = 1)
 {
@@ -334,6 +500,9 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
     const int jend = (int)min((int64_t)(j0 + nstrips * a.ty), nrows);
 
     double m_acc = 0.0, s_acc = 0.0, x_acc = 0.0;
+    long long mfx_acc = 0;     // division laws: fixed-point mass
+    DivTally dv;
+    if constexpr (DIV) dv = div_begin(a.st);
     int64_t ymax = -1;
     const int32_t hp = (a.region == kRegionFrontBand) ? io.h_prev[x] : 0;
     R Wd[9];
@@ -406,8 +575,10 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
             }
             S so[9];
             double m_site = 0.0, s_site = 0.0, x_site = 0.0;
-            const bool tissue =
-                site_step<S>(a, io.t, v, fs, Wd, so, x, y, y_wall, hp, m_site, s_site, x_site);
+            long long mfx_site = 0;
+            DivTally dv_site = div_site(dv);
+            const bool tissue = site_step<S, DIV>(a, io.t, v, fs, Wd, so, x, y, y_wall, hp, m_site,
+                                             s_site, x_site, mfx_site, dv_site);
             MemT<S> LBM_GLOBAL *rowg = G + (int64_t)s.r0 * tl.rs + cx;
             if (active) {
 #pragma unroll
@@ -415,6 +586,9 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
                 m_acc += m_site;
                 s_acc += s_site;
                 x_acc += x_site;
+                mfx_acc += mfx_site;
+                dv.w += dv_site.w;
+                dv.n += dv_site.n;
                 if (tissue) {
                     ymax = y;
                     if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
@@ -434,25 +608,28 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
     }
 
     // ---- per-block tallies (fixed order: deterministic) ------------------------
-    block_sum3<NT>(m_acc, s_acc, x_acc);
+    block_tallies<NT, DIV>(m_acc, s_acc, x_acc, mfx_acc, dv, a.st, by * nbx + bx);
+    double *pb = a.partials + kPartialSlots * (by * nbx + bx);
     if (threadIdx.x == 0) {
-        double *p = a.partials + 4 * (by * nbx + bx);
-        p[0] = m_acc;
-        p[1] += s_acc;
-        p[2] += x_acc;
+        pb[0] = m_acc;
+        pb[1] += s_acc;
+        pb[2] += x_acc;
         // a batch run taller than one strip keeps its tallies in its lowest
-        // tile's slot; the mass slots of the strips above it hold nothing
-        for (int i = 1; i < nstrips; ++i) a.partials[4 * ((by + i) * nbx + bx)] = 0.0;
+        // tile's slots; the per-step slots of the strips above it hold nothing
+        for (int i = 1; i < nstrips; ++i) {
+            double *q = a.partials + kPartialSlots * ((by + i) * nbx + bx);
+            q[0] = 0.0;
+        }
     }
 }
 
-template <class S, int NT, int RB>
+template <class S, int NT, int RB, bool DIV>
 __global__ __launch_bounds__(NT) void step_kernel(StepArgs<S> a)
 {
     const int nbx = gridDim.x;
     const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
     const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
-    step_scalar_tile<S, NT, RB>(a, io, lin % nbx, lin / nbx, nbx);
+    step_scalar_tile<S, NT, RB, DIV>(a, io, lin % nbx, lin / nbx, nbx);
 }
 
 // ---------------------------------------------------------------------------
@@ -613,7 +790,7 @@ __device__ __forceinline__ S from_right(const typename RawVec<ND>::type &own, S 
 }
 
 // ND dwords per lane; WPE: waves per SIMD the register allocation aims for.
-template <class S, int NT, int ND>
+template <class S, int NT, int ND, bool DIV>
 __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO<S> &io, int bx,
                                               int by, int nbx, int nstrips = 1)
 {
@@ -642,6 +819,9 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
     const int jend = (int)min((int64_t)(j0 + nstrips * a.ty), nrows);
 
     double m_acc = 0.0, s_acc = 0.0, x_acc = 0.0;
+    long long mfx_acc = 0;     // division laws: fixed-point mass
+    DivTally dv;
+    if constexpr (DIV) dv = div_begin(a.st);
     int32_t jmax[V], hp[V];
 #pragma unroll
     for (int i = 0; i < V; ++i) {
@@ -822,14 +1002,19 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
             int32_t hpk = hp[0];
 #pragma unroll
             for (int d = 1; d < V; ++d) hpk = (k == d) ? hp[d] : hpk;
-            const bool tissue =
-                site_step<S>(a, io.t, v, fs, Wd, so, x, y, y_wall, hpk, m_site, s_site, x_site);
+            long long mfx_site = 0;
+            DivTally dv_site = div_site(dv);
+            const bool tissue = site_step<S, DIV>(a, io.t, v, fs, Wd, so, x, y, y_wall, hpk, m_site,
+                                             s_site, x_site, mfx_site, dv_site);
 #pragma unroll
             for (int i = 0; i < 9; ++i) put_el<S, ND>(O[i], k, so[i]);
             if (active) {
                 m_acc += m_site;
                 s_acc += s_site;
                 x_acc += x_site;
+                mfx_acc += mfx_site;
+                dv.w += dv_site.w;
+                dv.n += dv_site.n;
                 if (tissue) {
                     tmask |= 1u << k;
                     if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
@@ -879,35 +1064,38 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
     }
 
     // ---- per-block tallies (fixed order: deterministic) ------------------------
-    block_sum3<NT>(m_acc, s_acc, x_acc);
+    block_tallies<NT, DIV>(m_acc, s_acc, x_acc, mfx_acc, dv, a.st, by * nbx + bx);
+    double *pb = a.partials + kPartialSlots * (by * nbx + bx);
     if (threadIdx.x == 0) {
-        double *p = a.partials + 4 * (by * nbx + bx);
-        p[0] = m_acc;
-        p[1] += s_acc;
-        p[2] += x_acc;
+        pb[0] = m_acc;
+        pb[1] += s_acc;
+        pb[2] += x_acc;
         // a batch run taller than one strip keeps its tallies in its lowest
-        // tile's slot; the mass slots of the strips above it hold nothing
-        for (int i = 1; i < nstrips; ++i) a.partials[4 * ((by + i) * nbx + bx)] = 0.0;
+        // tile's slots; the per-step slots of the strips above it hold nothing
+        for (int i = 1; i < nstrips; ++i) {
+            double *q = a.partials + kPartialSlots * ((by + i) * nbx + bx);
+            q[0] = 0.0;
+        }
     }
 }
 
 // Waves per SIMD the vector form's register allocation aims for (1 = no
 // target): the 16-bit storages at 4 bytes per lane fit 96 registers, which
 // lets 5 waves share a SIMD (measured faster than 4).
-template <class S, int ND>
+template <class S, int ND, bool DIV>
 constexpr int vec_waves()
 {
-    return (sizeof(S) == 2 && ND == 1) ? 5 : 1;
+    return (sizeof(S) == 2 && ND == 1 && !DIV) ? 5 : 1;
 }
 
-template <class S, int NT, int ND>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vec_waves<S, ND>())))
+template <class S, int NT, int ND, bool DIV>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vec_waves<S, ND, DIV>())))
 void step_kernel_vec(StepArgs<S> a)
 {
     const int nbx = gridDim.x;
     const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
     const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
-    step_vec_tile<S, NT, ND>(a, io, lin % nbx, lin / nbx, nbx);
+    step_vec_tile<S, NT, ND, DIV>(a, io, lin % nbx, lin / nbx, nbx);
 }
 
 // ---------------------------------------------------------------------------
@@ -1017,7 +1205,7 @@ __device__ __forceinline__ uint32_t lds_addr(const void *p)
     return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
 }
 
-template <class S>
+template <class S, bool DIV>
 __device__ __forceinline__ void step_staged_tile(const StepArgs<S> &a, const StepIO<S> &io, int bx,
                                                  int by, int nbx, unsigned char *lds_block)
 {
@@ -1079,6 +1267,9 @@ __device__ __forceinline__ void step_staged_tile(const StepArgs<S> &a, const Ste
                   (ES == 8 ? 4 * (lane & 1) : 0));
 
     double m_acc = 0.0, s_acc = 0.0, x_acc = 0.0;
+    long long mfx_acc = 0;     // division laws: fixed-point mass
+    DivTally dv;
+    if constexpr (DIV) dv = div_begin(a.st);
     int32_t jmax[V], hp[V];
     const int xs = c0 + V * lane;                  // this lane's first site
     const bool active = live && xs < L;            // (L even for 16-bit storage)
@@ -1177,12 +1368,18 @@ __device__ __forceinline__ void step_staged_tile(const StepArgs<S> &a, const Ste
                 fs[4] = fs[7] = fs[8] = R(0);
             }
             double m_site = 0.0, s_site = 0.0, x_site = 0.0;
-            const bool tissue = site_step<S>(a, io.t, vv, fs, Wd, out9[v], (uint32_t)(c0 + i), y,
-                                             y_wall, hp[v], m_site, s_site, x_site);
+            long long mfx_site = 0;
+            DivTally dv_site = div_site(dv);
+            const bool tissue = site_step<S, DIV>(a, io.t, vv, fs, Wd, out9[v], (uint32_t)(c0 + i),
+                                                  y, y_wall, hp[v], m_site, s_site, x_site,
+                                                  mfx_site, dv_site);
             if (active) {
                 m_acc += m_site;
                 s_acc += s_site;
                 x_acc += x_site;
+                mfx_acc += mfx_site;
+                dv.w += dv_site.w;
+                dv.n += dv_site.n;
                 if (tissue) {
                     jmax[v] = j;
                     if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
@@ -1230,16 +1427,16 @@ __device__ __forceinline__ void step_staged_tile(const StepArgs<S> &a, const Ste
     }
 
     // ---- per-block tallies (fixed order: deterministic) ------------------------
-    block_sum3<NT>(m_acc, s_acc, x_acc);
+    block_tallies<NT, DIV>(m_acc, s_acc, x_acc, mfx_acc, dv, a.st, by * nbx + bx);
+    double *pp = a.partials + kPartialSlots * (by * nbx + bx);
     if (threadIdx.x == 0) {
-        double *pp = a.partials + 4 * (by * nbx + bx);
         pp[0] = m_acc;
         pp[1] += s_acc;
         pp[2] += x_acc;
     }
 }
 
-template <class S>
+template <class S, bool DIV>
 __global__ __launch_bounds__(64 * StagedGeom(sizeof(S)).waves()) void step_kernel_staged(StepArgs<S> a)
 {
     constexpr StagedGeom G(sizeof(S));
@@ -1247,7 +1444,7 @@ __global__ __launch_bounds__(64 * StagedGeom(sizeof(S)).waves()) void step_kerne
     const int nbx = gridDim.x;
     const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
     const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
-    step_staged_tile<S>(a, io, lin % nbx, lin / nbx, nbx, lds);
+    step_staged_tile<S, DIV>(a, io, lin % nbx, lin / nbx, nbx, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1291,7 +1488,7 @@ __global__ __launch_bounds__(NT) void init_kernel(InitArgs<S> a)
     }
     block_sum3<NT>(m_acc, z1, z2);
     if (threadIdx.x == 0) {
-        double *p = a.partials + 4 * (blockIdx.y * gridDim.x + blockIdx.x);
+        double *p = a.partials + kPartialSlots * (blockIdx.y * gridDim.x + blockIdx.x);
         p[0] = m_acc;
         p[1] = 0.0;
         p[2] = 0.0;
@@ -1307,6 +1504,8 @@ __global__ __launch_bounds__(NT) void mass_kernel(MassArgs<S> a)
     using R = typename Codec<S>::R;
     const int j0 = blockIdx.y * a.ty;
     double m_acc = 0.0, z1 = 0.0, z2 = 0.0;
+    long long mfx = 0;
+    DivTally dv;
     const int64_t y_wall = a.st->y_wall, y_top = a.st->y_valid_top;
     for (int c = 0; c < a.cpt; ++c) {
         const int x = (blockIdx.x * NT + threadIdx.x) * a.cpt + c;
@@ -1320,77 +1519,119 @@ __global__ __launch_bounds__(NT) void mass_kernel(MassArgs<S> a)
 #pragma unroll
             for (int i = 0; i < 9; ++i)
                 v[i] = Codec<S>::dec(a.f[a.tl.at(i, r, x)], a.Wd[i]);
-            m_acc += (double)sum9(v);
+            const R rho = sum9(v);
+            m_acc += (double)rho;
+            if (a.growth >= kGrowthDivision) {
+                // the division laws' tallies of a state given as populations:
+                // its sites count as eligible by their own density
+                mfx += mass_fx((double)rho);
+                bool in_reg = true;
+                if (a.region == kRegionFrontBand) in_reg = y >= (int64_t)a.h[x] - a.region_width;
+                else if (a.region == kRegionRearBand) in_reg = y < y_wall + a.region_width;
+                if (rho >= (R)a.rho_c && in_reg) {
+                    if (a.growth == kGrowthDivision) {
+                        dv.w += 1;
+                    } else {
+                        const double q = 1.0 - (double)rho / a.rho0;
+                        if (rho > (R)a.rho_c && q > 0.0) dv.w += (long long)(q * kFx);
+                    }
+                }
+            }
         }
     }
-    block_sum3<NT>(m_acc, z1, z2);
-    if (threadIdx.x == 0) a.partials[4 * (blockIdx.y * gridDim.x + blockIdx.x)] = m_acc;
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    if (a.growth >= kGrowthDivision) block_tallies<NT, true>(m_acc, z1, z2, mfx, dv, a.st, blk);
+    else block_sum3<NT>(m_acc, z1, z2);
+    if (threadIdx.x == 0) a.partials[kPartialSlots * blk] = m_acc;
 }
 
 // ---------------------------------------------------------------------------
 // Small single-block kernels.
 // ---------------------------------------------------------------------------
 constexpr int kRedThreads = 1024;
+constexpr int kRedWaves = kRedThreads / 64;
 
-// Deterministic reductions of one block of kRedThreads threads.
-__device__ __forceinline__ double block_sum_d(double v, double *sh)
+// Deterministic reductions of one block of kRedThreads threads: N values at
+// once, one LDS round, results in every thread.
+template <int N, class T, class Op = OpAdd>
+__device__ __forceinline__ void block_reduce(T (&v)[N], T (*sh)[kRedWaves], Op op = Op())
 {
-    v = wave_sum(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[w];
-    return s;
-}
-
-__device__ __forceinline__ long long block_sum_i(long long v, long long *sh)
-{
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    long long s = 0;
-    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[w];
-    return s;
-}
-
-__device__ __forceinline__ long long block_max_i(long long v, long long *sh)
-{
+    for (int k = 0; k < N; ++k) v[k] = wave_reduce(v[k], op);
+    __syncthreads();   // (sh may still be read by an earlier reduction)
+    if (lane == 0) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const long long o = __shfl_xor(v, off, 64);
-        v = o > v ? o : v;
+        for (int k = 0; k < N; ++k) sh[k][wave] = v[k];
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    long long s = sh[0];
-    for (int w = 1; w < kRedThreads / 64; ++w) s = sh[w] > s ? sh[w] : s;
-    return s;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        T r = sh[k][0];
+        for (int w = 1; w < kRedWaves; ++w) r = op(r, sh[k][w]);
+        v[k] = r;
+    }
 }
 
-// hbar and w of Sec. III from integer sums relative to the wall row:
-// hbar = y_wall + S1 / L, w = sqrt(L S2 - S1^2) / L (exact sums, so the
-// result does not depend on the order of summation).
-__device__ __forceinline__ void height_stats(const int32_t *h, int L, int64_t y_wall,
-                                             long long *sh, double &hbar, double &W,
-                                             long long &hmax)
+// Division laws: this thread's share of the step's tallies from the device
+// state's slots, which it clears for the next step (words: fixed-point mass,
+// weight, divisions).
+__device__ __forceinline__ void take_div_slots(DevState *st, long long &mfx, long long &wsum,
+                                               long long &ndiv)
 {
-    long long s1 = 0, s2 = 0, mx = LLONG_MIN;
-    for (int x = threadIdx.x; x < L; x += kRedThreads) {
-        const long long d = (long long)h[x] - y_wall;
-        s1 += d;
-        s2 += d * d;
-        mx = (long long)h[x] > mx ? (long long)h[x] : mx;
+    if (threadIdx.x < kDivSlots) {
+        unsigned long long *slot = st->div_acc[threadIdx.x];
+        mfx += (long long)slot[0];
+        wsum += (long long)slot[1];
+        ndiv += (long long)slot[2];
+        slot[0] = slot[1] = slot[2] = 0ull;
     }
-    const long long S1 = block_sum_i(s1, sh);
-    const long long S2 = block_sum_i(s2, sh);
-    hmax = block_max_i(mx, sh);
+}
+
+// The next step's mean per unit weight and, for the uniform law, its chance
+// of no division at a site (thread 0).
+__device__ __forceinline__ void set_division_rate(DevState *st, int growth, double lam,
+                                                  long long ndiv)
+{
+    st->lam = lam;
+    st->p0 = growth == kGrowthDivision ? exp_neg(lam < 8.0 ? lam : 8.0) : 1.0;
+    st->divisions += ndiv;
+}
+
+// This thread's share of the front-height sums relative to the wall row,
+// S1 = sum (h - y_wall) and S2 = sum (h - y_wall)^2, and of the highest entry
+// of colmax (four columns' loads in flight at a time).
+__device__ __forceinline__ void height_sums(const int32_t *h, const int32_t *colmax, int L,
+                                            int64_t y_wall, long long &s1, long long &s2,
+                                            long long &cm)
+{
+    constexpr int U = 4;
+    for (int x0 = threadIdx.x; x0 < L; x0 += U * kRedThreads) {
+        int32_t hv[U], cv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int x = x0 + u * kRedThreads;
+            hv[u] = x < L ? h[x] : 0;
+            cv[u] = x < L ? colmax[x] : INT_MIN;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (x0 + u * kRedThreads < L) {
+                const long long d = (long long)hv[u] - y_wall;
+                s1 += d;
+                s2 += d * d;
+                cm = (long long)cv[u] > cm ? (long long)cv[u] : cm;
+            }
+        }
+    }
+}
+
+// hbar and w of Sec. III from the exact integer sums (so the result does not
+// depend on the order of summation): hbar = y_wall + S1 / L,
+// w = sqrt(L S2 - S1^2) / L.
+__device__ __forceinline__ void height_stats(long long S1, long long S2, int L, int64_t y_wall,
+                                             double &hbar, double &W)
+{
     const long long num = (long long)L * S2 - S1 * S1;
     hbar = (double)y_wall + (double)S1 / (double)L;
     W = sqrt((double)num) / (double)L;
@@ -1404,14 +1645,21 @@ template <class S>
 __device__ __forceinline__ void finalize_body(const FinalizeArgs<S> &a)
 {
     using R = typename Codec<S>::R;
-    __shared__ double shd[kRedThreads / 64];
-    __shared__ long long shi[kRedThreads / 64];
+    __shared__ long long shi[5][kRedWaves];
+    __shared__ double shd[1][kRedWaves];
     DevState *st = a.st;
     const int64_t y_wall = st->y_wall;
     const int64_t nrows_done = st->n_rows;
+    // front-height sums, division-law tallies (integers: order-free) and the
+    // highest front so far, in two block reductions
+    long long si[5] = {0, 0, 0, 0, 0};   // S1, S2, mass (2^-24), weight, divisions
+    long long cm[1] = {LLONG_MIN};
+    height_sums(a.h_next, a.colmax, a.L, y_wall, si[0], si[1], cm[0]);
+    if (a.growth >= kGrowthDivision) take_div_slots(st, si[2], si[3], si[4]);
+    block_reduce(si, shi);
+    block_reduce(cm, shi, OpMax());
     double hbar, W;
-    long long hmax;
-    height_stats(a.h_next, a.L, y_wall, shi, hbar, W, hmax);
+    height_stats(si[0], si[1], a.L, y_wall, hbar, W);
 
     int64_t k = 0;
     if (a.follow) {
@@ -1421,7 +1669,8 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs<S> &a)
         if (target > y_wall) k = target - y_wall;
         if (k > a.H - 1) k = a.H - 1;
     }
-    double gone = 0.0;
+    double gone[1] = {0.0};
+    long long gone_fx[1] = {0};
     if (k > 0) {
         const int64_t n = k * (int64_t)a.L;
         for (int64_t e = threadIdx.x; e < n; e += kRedThreads) {
@@ -1432,26 +1681,31 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs<S> &a)
 #pragma unroll
             for (int i = 0; i < 9; ++i)
                 v[i] = Codec<S>::dec(a.f[a.tl.at(i, r, x)], a.Wd[i]);
-            gone += (double)sum9(v);
+            const R m = sum9(v);
+            gone[0] += (double)m;
+            gone_fx[0] += mass_fx((double)m);
         }
+        block_reduce(gone, shd);
+        block_reduce(gone_fx, shi);
     }
-    gone = block_sum_d(gone, shd);
+    // division laws: the next step's rate from this step's tallies, less the
+    // rows the wall leaves behind
+    const double lam_next =
+        a.growth >= kGrowthDivision
+            ? division_lam(a.growth == kGrowthDivision, a.g, a.rho_cell, si[2] - gone_fx[0], si[3])
+            : 0.0;
     const int64_t y_new = y_wall + k;
     // highest front so far and the rows the next step must sweep
-    long long cm = LLONG_MIN;
-    for (int x = threadIdx.x; x < a.L; x += kRedThreads)
-        cm = (long long)a.colmax[x] > cm ? (long long)a.colmax[x] : cm;
-    cm = block_max_i(cm, shi);
-    const long long hi = st->h_hi > cm ? st->h_hi : cm;
-    (void)hmax;
+    const long long hi = st->h_hi > cm[0] ? st->h_hi : cm[0];
     for (int x = threadIdx.x; x < a.L; x += kRedThreads) {
         if (a.h_next[x] < y_new) a.h_next[x] = (int32_t)y_new;
         a.h_clear[x] = (int32_t)y_new;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        st->retired_last = gone;
-        st->retired_total += gone;
+        if (a.growth >= kGrowthDivision) set_division_rate(st, a.growth, lam_next, si[4]);
+        st->retired_last = gone[0];
+        st->retired_total += gone[0];
         st->y_valid_top = y_wall + nrows_done;
         st->y_wall = y_new;
         st->h_hi = hi;
@@ -1508,7 +1762,7 @@ __device__ __forceinline__ void stage_dwords(const void *src, uint32_t *lds, int
 // block updates as one tall tile after fetching the member's descriptor
 // (through LDS).  Windowed groups launch a fixed grid that strides over the
 // entries.
-template <class S, int NT, int ND, bool VEC>
+template <class S, int NT, int ND, bool VEC, bool DIV>
 __global__ __launch_bounds__(NT) void step_batch(BatchRep<S> *const *reps, const TileRef *table,
                                                  const int32_t *count, int k)
 {
@@ -1521,8 +1775,8 @@ __global__ __launch_bounds__(NT) void step_batch(BatchRep<S> *const *reps, const
         stage_dwords<NT>(reps[e.rep], stage, (int)(sizeof(BatchRep<S>) / 4));
         const StepIO<S> io = batch_io(&R, k);
         const int bx = e.local0 % R.gx, by = e.local0 / R.gx;
-        if constexpr (VEC) step_vec_tile<S, NT, ND>(R.a, io, bx, by, R.gx, e.n);
-        else step_scalar_tile<S, NT, ND>(R.a, io, bx, by, R.gx, e.n);
+        if constexpr (VEC) step_vec_tile<S, NT, ND, DIV>(R.a, io, bx, by, R.gx, e.n);
+        else step_scalar_tile<S, NT, ND, DIV>(R.a, io, bx, by, R.gx, e.n);
     }
 }
 
@@ -1579,7 +1833,8 @@ __global__ __launch_bounds__(kRedThreads) void plan_batch(BatchRep<S> *const *re
             // would otherwise stay behind (a solo launch writes 0 there)
             BatchRep<S> *R = reps[base + m];
             const int last = R->last_live;
-            for (int b = live + threadIdx.x; b < last; b += kRedThreads) R->a.partials[4 * b] = 0.0;
+            for (int b = live + threadIdx.x; b < last; b += kRedThreads)
+                R->a.partials[kPartialSlots * b] = 0.0;
             __syncthreads();
             if (threadIdx.x == 0) R->last_live = live;
         }
@@ -1621,17 +1876,29 @@ __global__ void batch_advance(BatchRep<S> *const *reps, int n, int K)
 template <class S, int RB>
 void launch_step_rb(const StepArgs<S> &a, dim3 grid, int nt, hipStream_t s)
 {
-    if (nt == 256) hipLaunchKernelGGL((step_kernel<S, 256, RB>), grid, dim3(256), 0, s, a);
-    else if (nt == 128) hipLaunchKernelGGL((step_kernel<S, 128, RB>), grid, dim3(128), 0, s, a);
-    else hipLaunchKernelGGL((step_kernel<S, 64, RB>), grid, dim3(64), 0, s, a);
+    if (a.growth >= kGrowthDivision) {
+        if (nt == 256) hipLaunchKernelGGL((step_kernel<S, 256, RB, true>), grid, dim3(256), 0, s, a);
+        else if (nt == 128) hipLaunchKernelGGL((step_kernel<S, 128, RB, true>), grid, dim3(128), 0, s, a);
+        else hipLaunchKernelGGL((step_kernel<S, 64, RB, true>), grid, dim3(64), 0, s, a);
+    } else {
+        if (nt == 256) hipLaunchKernelGGL((step_kernel<S, 256, RB, false>), grid, dim3(256), 0, s, a);
+        else if (nt == 128) hipLaunchKernelGGL((step_kernel<S, 128, RB, false>), grid, dim3(128), 0, s, a);
+        else hipLaunchKernelGGL((step_kernel<S, 64, RB, false>), grid, dim3(64), 0, s, a);
+    }
 }
 
 template <class S, int ND>
 void launch_vec_nt(const StepArgs<S> &a, dim3 grid, int nt, hipStream_t s)
 {
-    if (nt == 256) hipLaunchKernelGGL((step_kernel_vec<S, 256, ND>), grid, dim3(256), 0, s, a);
-    else if (nt == 128) hipLaunchKernelGGL((step_kernel_vec<S, 128, ND>), grid, dim3(128), 0, s, a);
-    else hipLaunchKernelGGL((step_kernel_vec<S, 64, ND>), grid, dim3(64), 0, s, a);
+    if (a.growth >= kGrowthDivision) {
+        if (nt == 256) hipLaunchKernelGGL((step_kernel_vec<S, 256, ND, true>), grid, dim3(256), 0, s, a);
+        else if (nt == 128) hipLaunchKernelGGL((step_kernel_vec<S, 128, ND, true>), grid, dim3(128), 0, s, a);
+        else hipLaunchKernelGGL((step_kernel_vec<S, 64, ND, true>), grid, dim3(64), 0, s, a);
+    } else {
+        if (nt == 256) hipLaunchKernelGGL((step_kernel_vec<S, 256, ND, false>), grid, dim3(256), 0, s, a);
+        else if (nt == 128) hipLaunchKernelGGL((step_kernel_vec<S, 128, ND, false>), grid, dim3(128), 0, s, a);
+        else hipLaunchKernelGGL((step_kernel_vec<S, 64, ND, false>), grid, dim3(64), 0, s, a);
+    }
 }
 
 // vb: bytes per lane (4, 8 or 16).
@@ -1653,7 +1920,10 @@ template <class S>
 hipError_t launch_step_staged(const StepArgs<S> &a, dim3 grid, hipStream_t s)
 {
     constexpr StagedGeom G(sizeof(S));
-    hipLaunchKernelGGL((step_kernel_staged<S>), grid, dim3(64 * G.waves()), 0, s, a);
+    if (a.growth >= kGrowthDivision)
+        hipLaunchKernelGGL((step_kernel_staged<S, true>), grid, dim3(64 * G.waves()), 0, s, a);
+    else
+        hipLaunchKernelGGL((step_kernel_staged<S, false>), grid, dim3(64 * G.waves()), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1690,34 +1960,44 @@ hipError_t launch_finalize(const FinalizeArgs<S> &a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <class S, int NT>
-void launch_batch_nt(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
-                     int grid, int vec, int vb_or_rb, int k, hipStream_t s)
+template <class S, int NT, bool DIV>
+void launch_batch_div(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
+                      int grid, int vec, int vb_or_rb, int k, hipStream_t s)
 {
     const dim3 g(grid), b(NT);
     if (vec) {
         if (vb_or_rb == 4) {
             if constexpr (sizeof(S) <= 4)
-                hipLaunchKernelGGL((step_batch<S, NT, 1, true>), g, b, 0, s, reps, table, count, k);
+                hipLaunchKernelGGL((step_batch<S, NT, 1, true, DIV>), g, b, 0, s, reps, table, count, k);
         } else if (vb_or_rb == 8) {
-            hipLaunchKernelGGL((step_batch<S, NT, 2, true>), g, b, 0, s, reps, table, count, k);
+            hipLaunchKernelGGL((step_batch<S, NT, 2, true, DIV>), g, b, 0, s, reps, table, count, k);
         } else {
-            hipLaunchKernelGGL((step_batch<S, NT, 4, true>), g, b, 0, s, reps, table, count, k);
+            hipLaunchKernelGGL((step_batch<S, NT, 4, true, DIV>), g, b, 0, s, reps, table, count, k);
         }
     } else {
-        if (vb_or_rb >= 2) hipLaunchKernelGGL((step_batch<S, NT, 2, false>), g, b, 0, s, reps, table, count, k);
-        else hipLaunchKernelGGL((step_batch<S, NT, 1, false>), g, b, 0, s, reps, table, count, k);
+        if (vb_or_rb >= 2)
+            hipLaunchKernelGGL((step_batch<S, NT, 2, false, DIV>), g, b, 0, s, reps, table, count, k);
+        else
+            hipLaunchKernelGGL((step_batch<S, NT, 1, false, DIV>), g, b, 0, s, reps, table, count, k);
     }
+}
+
+template <class S, int NT>
+void launch_batch_nt(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
+                     int grid, int vec, int vb_or_rb, int div, int k, hipStream_t s)
+{
+    if (div) launch_batch_div<S, NT, true>(reps, table, count, grid, vec, vb_or_rb, k, s);
+    else launch_batch_div<S, NT, false>(reps, table, count, grid, vec, vb_or_rb, k, s);
 }
 
 template <class S>
 hipError_t launch_step_batch(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
-                             int grid, int vec, int nt, int vb_or_rb, int k, hipStream_t s)
+                             int grid, int vec, int nt, int vb_or_rb, int div, int k, hipStream_t s)
 {
     if (grid <= 0) return hipSuccess;
-    if (nt == 256) launch_batch_nt<S, 256>(reps, table, count, grid, vec, vb_or_rb, k, s);
-    else if (nt == 128) launch_batch_nt<S, 128>(reps, table, count, grid, vec, vb_or_rb, k, s);
-    else launch_batch_nt<S, 64>(reps, table, count, grid, vec, vb_or_rb, k, s);
+    if (nt == 256) launch_batch_nt<S, 256>(reps, table, count, grid, vec, vb_or_rb, div, k, s);
+    else if (nt == 128) launch_batch_nt<S, 128>(reps, table, count, grid, vec, vb_or_rb, div, k, s);
+    else launch_batch_nt<S, 64>(reps, table, count, grid, vec, vb_or_rb, div, k, s);
     return hipGetLastError();
 }
 

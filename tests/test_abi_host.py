@@ -82,6 +82,8 @@ def test_workspace_bytes_scales_with_precision():
     dict(tau=0.5), dict(tau=float("nan")), dict(rho_c=0.0), dict(L=1), dict(H=3),
     dict(sigma=-1.0), dict(growth_rate=-1e-3), dict(init_rows=65), dict(mu=1.5),
     dict(init_amp=1.0), dict(region_width=-1), dict(precision="fp64", window=True, ybc="periodic"),
+    dict(growth="division", rho_cell=0.0), dict(growth="division_density", rho_cell=float("inf")),
+    dict(growth="division_density", rho0=0.5), dict(growth="division_density", rho0=0.4),
 ])
 def test_invalid_parameters_rejected_on_host(bad):
     c = dict(si.SMALL_FP64)

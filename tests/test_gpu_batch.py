@@ -24,7 +24,7 @@ def _same(member, ref, tag):
     assert np.array_equal(member.populations(), f), tag
     assert np.array_equal(member.front_heights(), h), tag
     dm = member.diagnostics()
-    for k in ("step", "y_wall", "h_hi", "status", "hbar", "W"):
+    for k in ("step", "y_wall", "h_hi", "status", "hbar", "W", "divisions", "lam"):
         assert dm[k] == d[k], (tag, k, dm[k], d[k])
     for k in ("mass", "src_total", "fix_total", "retired"):
         assert abs(dm[k] - d[k]) <= 1e-12 * max(1.0, abs(d["mass"])), (tag, k)
@@ -57,6 +57,37 @@ def test_batch_members_match_solo_runs_bitwise():
     ens.synchronize()
     for i, (c, m) in enumerate(zip(MIXED, ens.members)):
         _same(m, _solo(c, 37), i)
+
+
+DIVISION = [
+    si.cfg(L=128, H=192, init_rows=48, growth="division", growth_rate=5e-3, sigma=1e-3,
+           precision="fp32", seed=11),
+    si.cfg(L=128, H=192, init_rows=48, growth_rate=5e-3, sigma=1e-3, precision="fp32", seed=11),
+    si.cfg(L=96, H=96, init_rows=30, growth="division_density", growth_rate=1e-2, sigma=1e-2,
+           precision="fp64", seed=12),
+    si.cfg(L=130, H=128, init_rows=30, tau=0.8, growth="division", growth_rate=5e-3, sigma=1e-3,
+           region="front_band", region_width=6, precision="fp16", seed=13),
+    si.cfg(L=96, H=160, init_rows=100, sigma=1e-2, growth="division", growth_rate=1e-2,
+           ybc="follow", wall_min_gap=10, window=True, precision="fp64", seed=14),
+    si.cfg(L=200, H=96, init_rows=30, growth="division_density", growth_rate=5e-3, sigma=1e-3,
+           precision="bf16", seed=15),
+]
+
+
+def test_batch_division_members_match_solo_runs_bitwise():
+    """Division-law members (their per-step rate is reduced on the device from
+    the previous step's tallies) batched beside a bulk-growth member of the
+    same kernel form."""
+    from paper_2303_02210_amd import Ensemble
+    ens = Ensemble(DIVISION)
+    for n in (8, 8, 13):
+        ens.step(n)
+    ens.synchronize()
+    for i, (c, m) in enumerate(zip(DIVISION, ens.members)):
+        ref = _solo(c, 29)
+        _same(m, ref, i)
+        if c["growth"] != "bulk":
+            assert ref[2]["divisions"] > 0, i
 
 
 def test_batch_membership_changes_and_solo_steps():

@@ -198,6 +198,7 @@ def _one_step_check(sim, cfg, prec):
     f0 = sim.populations()
     h0 = sim.front_heights()
     t = sim.last_step
+    lam = sim.diagnostics()["lam"]
     sim.step(1)
     f1 = sim.populations()
     h1 = sim.front_heights()
@@ -205,6 +206,7 @@ def _one_step_check(sim, cfg, prec):
     o.set_populations(f0)
     o.set_front_heights(h0)
     o.set_step(t)
+    o.set_lam(lam)
     o.step(1)
     fr = o.populations()
     rho_s = d2q9.stream_pull(f0).sum(0)
@@ -231,7 +233,7 @@ def _one_step_check(sim, cfg, prec):
         fs = orc.pull_site(o.p, f0, int(x), int(y))
         ok = False
         for force in (0, 1):
-            out, _, _, _ = orc.update_site(o.p, fs, t, int(x), int(y), int(h0[x]), 0, force)
+            out, _, _, _ = orc.update_site(o.p, fs, t, int(x), int(y), int(h0[x]), 0, force, lam)
             ok = ok or np.all(np.abs(f1[:, y, x] - out) <= tol[:, y, x] + 1e-6)
         assert ok, (prec, t, y, x)
     cols = ~near.any(0)
