@@ -104,7 +104,7 @@ def main():
                     help="ensemble/served: skip the one-run-at-a-time comparison")
     ap.add_argument("--out", default=None, help="precision: write the curves to this JSON file")
     ap.add_argument("--workload", default="bulk",
-                    choices=["bulk", "edge", "ensemble", "served", "precision"],
+                    choices=["bulk", "edge", "ensemble", "served", "precision", "appb"],
                     help="bulk: 4096 x 4096 bulk growth (default); edge: 2048 x 8192 growth "
                          "within 8 rows of the front; ensemble: 256 replicas of uneven size, "
                          "batched, against the same runs stepped one after another")
@@ -132,6 +132,8 @@ def main():
         return bench_served(args)
     if args.workload == "precision":
         return bench_precision(args)
+    if args.workload == "appb":
+        return bench_appb(args)
     base = si.BULK_4096_FP32 if args.workload == "bulk" else si.EDGE_2048x8192
     cfg = dict(base, precision=args.precision)
     if args.growth and args.growth != cfg["growth"]:
@@ -342,7 +344,7 @@ def _curves(sims, steps, every, stream_sync):
     """Advance sims together and record hbar(t), W(t) and mass every `every`
     steps (sims: an Ensemble)."""
     import numpy as np
-    rec = {"t": [], "hbar": [], "W": [], "mass": []}
+    rec = {"t": [], "hbar": [], "W": [], "mass": [], "wmass": []}
     done = 0
     while done < steps:
         n = min(every, steps - done)
@@ -354,7 +356,81 @@ def _curves(sims, steps, every, stream_sync):
         rec["hbar"].append([d["hbar"] for d in ds])
         rec["W"].append([d["W"] for d in ds])
         rec["mass"].append([d["mass"] - d["src_total"] - d["fix_total"] + d["retired"] for d in ds])
+        rec["wmass"].append([d["mass"] for d in ds])
     return {k: np.asarray(v) for k, v in rec.items()}
+
+
+def bench_appb(args):
+    """Appendix B: w(t) and the front profile at L = 640 under the
+    density-dependent division law (Eq. 5) and under uniform divisions held
+    to the 30 rows above the rear wall, 4 seeds each, batched (float32, wall
+    following the front).  Reports w(t) per regime (mean and 95% interval
+    over seeds), the final profiles h(x) - hbar, and the batch throughput."""
+    import numpy as np
+    import torch
+    import synth_inputs as si
+    from paper_2303_02210_amd import Ensemble
+
+    nseed = 4
+    cfgs = si.appendix_b(nseed)
+    steps = args.steps
+    every = max(100, steps // 200)
+    log(f"appendix B: {len(cfgs)} runs of {cfgs[0]['L']}x{cfgs[0]['H']}, {steps} steps")
+    ens = Ensemble(cfgs)
+    t0 = time.perf_counter()
+    c = _curves(ens, steps, every, ens.synchronize)
+    wall = time.perf_counter() - t0
+    prof = [m.front_heights().astype(np.float64) for m in ens.members]
+    dg = [m.diagnostics() for m in ens.members]
+    ens.close()
+    for m in ens.members:
+        m.close()
+    W = c["W"]
+    regimes = {"density_dependent": slice(0, nseed), "rear_band_30": slice(nseed, 2 * nseed)}
+    res = {}
+    for name, sl in regimes.items():
+        w = W[:, sl]
+        ci = 1.96 * w.std(1, ddof=1) / np.sqrt(nseed)
+        res[name] = {
+            "W_mean": np.round(w.mean(1), 4).tolist(), "W_ci95": np.round(ci, 4).tolist(),
+            "W_final_mean": float(w[-1].mean()), "W_final_ci95": float(ci[-1]),
+            "hbar_final_mean": float(c["hbar"][-1, sl].mean()),
+            "divisions_mean": float(np.mean([d["divisions"] for d in dg[sl]])),
+            # mass budget: what the divisions and the negative-population fix
+            # (App. A step 7) added, and the window's mass at the end against
+            # its start (a run whose window mass grows without bound has left
+            # the lattice Boltzmann regime)
+            "src_total_mean": float(np.mean([d["src_total"] for d in dg[sl]])),
+            "fix_total_mean": float(np.mean([d["fix_total"] for d in dg[sl]])),
+            "window_mass_growth_max": float(np.max(c["wmass"][-1, sl] / c["wmass"][0, sl])),
+            "profile_seed0": np.round(prof[sl.start] - prof[sl.start].mean(), 2).tolist(),
+        }
+        log(f"{name}: W(final) {res[name]['W_final_mean']:.3f} +- {res[name]['W_final_ci95']:.3f}, "
+            f"hbar {res[name]['hbar_final_mean']:.1f}")
+    sites = sum(cf["L"] * cf["H"] for cf in cfgs)
+    out = {
+        "metric": "appendix_b_w_final_ratio",
+        "value": round(res["density_dependent"]["W_final_mean"] /
+                       max(res["rear_band_30"]["W_final_mean"], 1e-12), 3),
+        "unit": "ratio", "n_gpus": 1, "steps": steps, "warmup": 0,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "appendix_b_640", "L": cfgs[0]["L"], "H": cfgs[0]["H"],
+                   "seeds": nseed, "every": every,
+                   "params": {k: cfgs[0][k] for k in ("tau", "mu", "rho_c", "rho_init", "init_amp",
+                                                      "sigma", "growth_rate", "rho_cell", "rho0",
+                                                      "wall_min_gap", "wall_w_factor")}},
+        "t": c["t"].tolist(), "regimes": res,
+        "batch_lattice_mlups": round(sites * steps / wall / 1e6, 1),
+        "wall_s": round(wall, 2),
+    }
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump(out, fh)
+        log(f"wrote {args.out}")
+    out.pop("t")
+    for r in out["regimes"].values():
+        r.pop("W_mean"), r.pop("W_ci95"), r.pop("profile_seed0")
+    print(json.dumps(out), flush=True)
 
 
 def bench_precision(args):

@@ -31,7 +31,10 @@ def _pow2(n: int) -> int:
 
 
 def key(cfg: dict) -> str:
-    return f"{cfg.get('precision', 'fp64')}/L{_pow2(int(cfg['L']))}/H{_pow2(int(cfg['H']))}"
+    """Storage, width and height rounded up to powers of two, and whether a
+    division law runs (its kernels hold more registers)."""
+    div = "/div" if str(cfg.get("growth", "bulk")).startswith("division") else ""
+    return f"{cfg.get('precision', 'fp64')}/L{_pow2(int(cfg['L']))}/H{_pow2(int(cfg['H']))}{div}"
 
 
 def candidates(cfg: dict):
@@ -117,6 +120,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
     work = [dict(si.BULK_4096_FP32, precision=p) for p in ("fp64", "fp32", "fp16", "bf16")]
     work += [dict(si.EDGE_2048x8192, precision=p) for p in ("fp32", "fp16", "bf16")]
+    work += [dict(si.BULK_4096_FP32, precision=p, growth="division")
+             for p in ("fp64", "fp32", "fp16", "bf16")]
     seen = set()
     for c in si.ensemble():
         if c["L"] not in seen:

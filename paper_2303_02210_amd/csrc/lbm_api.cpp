@@ -187,8 +187,9 @@ Layout make_layout(const lbm_params *p)
     // vector kernel when the columns split evenly into lanes; bytes per lane
     // and rows per thread as measured best on MI355X for a 4096 x 4096
     // lattice: float64 16 B / 1 row, float32 4 B / 1 row, 16-bit 4 B / 2 rows
+    // (4 rows with a division law)
     l.vb = l.esize == 8 ? 16 : 4;
-    int ty_pref = l.esize == 2 ? 2 : 1;
+    int ty_pref = l.esize == 2 ? (p->growth >= LBM_GROWTH_DIVISION ? 4 : 2) : 1;
     bool scalar = false;
     if (p->kernel_vb == 1) scalar = true;                 // one column per lane
     else if (p->kernel_vb == 2) l.staged = true;          // rows staged through LDS

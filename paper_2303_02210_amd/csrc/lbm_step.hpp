@@ -120,9 +120,10 @@ struct OpMax {
     __device__ __forceinline__ T operator()(T a, T b) const { return a > b ? a : b; }
 };
 
-// (8-byte T: double or long long)
+// Every lane gets the result over its row of 16 lanes (8-byte T: double or
+// long long).
 template <class T, class Op = OpAdd>
-__device__ __forceinline__ T wave_reduce(T v, Op op = Op())
+__device__ __forceinline__ T row_reduce(T v, Op op = Op())
 {
     static_assert(sizeof(T) == 8, "64-bit lanes");
     constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kHalfMirror = 0x141, kMirror = 0x140;
@@ -130,6 +131,14 @@ __device__ __forceinline__ T wave_reduce(T v, Op op = Op())
     v = op(v, __builtin_bit_cast(T, dpp_move<kXor2>(__builtin_bit_cast(uint64_t, v))));
     v = op(v, __builtin_bit_cast(T, dpp_move<kHalfMirror>(__builtin_bit_cast(uint64_t, v))));
     v = op(v, __builtin_bit_cast(T, dpp_move<kMirror>(__builtin_bit_cast(uint64_t, v))));
+    return v;
+}
+
+// The result over the whole wavefront, in every lane.
+template <class T, class Op = OpAdd>
+__device__ __forceinline__ T wave_reduce(T v, Op op = Op())
+{
+    v = row_reduce(v, op);
     const uint64_t u = __builtin_bit_cast(uint64_t, v);
     const T r0 = __builtin_bit_cast(T, read_lane(u, 0));
     const T r1 = __builtin_bit_cast(T, read_lane(u, 16));
@@ -767,14 +776,26 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, int
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, (int)kBufWord3);
 }
 
+// Lane i's copy of lane i - 1's (wave_shr:1) or lane i + 1's (wave_shl:1)
+// dword, by a DPP move within the vector ALU; lanes 0 and 63 get no
+// neighbour's value (their callers take an edge value instead).
+__device__ __forceinline__ uint32_t lane_from_left(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t lane_from_right(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, false);
+}
+
 // The left lane's last element (inside the wave) or the edge value.
 template <class S, int ND>
 __device__ __forceinline__ S from_left(const typename RawVec<ND>::type &own, S edge, bool use_edge)
 {
     constexpr int NV = ND * 4 / (int)sizeof(S);
     typename RawVec<ND>::type t;
-    t[ND - 1] = (uint32_t)__shfl_up((int)own[ND - 1], 1, 64);
-    if constexpr (sizeof(S) == 8) t[ND - 2] = (uint32_t)__shfl_up((int)own[ND - 2], 1, 64);
+    t[ND - 1] = lane_from_left(own[ND - 1]);
+    if constexpr (sizeof(S) == 8) t[ND - 2] = lane_from_left(own[ND - 2]);
     const S n = get_el<S, ND>(t, NV - 1);
     return use_edge ? edge : n;
 }
@@ -783,8 +804,8 @@ template <class S, int ND>
 __device__ __forceinline__ S from_right(const typename RawVec<ND>::type &own, S edge, bool use_edge)
 {
     typename RawVec<ND>::type t;
-    t[0] = (uint32_t)__shfl_down((int)own[0], 1, 64);
-    if constexpr (sizeof(S) == 8) t[1] = (uint32_t)__shfl_down((int)own[1], 1, 64);
+    t[0] = lane_from_right(own[0]);
+    if constexpr (sizeof(S) == 8) t[1] = lane_from_right(own[1]);
     const S n = get_el<S, ND>(t, 0);
     return use_edge ? edge : n;
 }
@@ -1080,12 +1101,18 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
 }
 
 // Waves per SIMD the vector form's register allocation aims for (1 = no
-// target): the 16-bit storages at 4 bytes per lane fit 96 registers, which
-// lets 5 waves share a SIMD (measured faster than 4).
+// target), as measured fastest on a 4096 x 4096 lattice: the 16-bit storages
+// at 4 bytes per lane fit 96 registers, so 5 waves share a SIMD (faster than
+// 4); with the division laws they take 4 (at 5 they spill heavily), and
+// float32 at 4 bytes per lane takes 6 (the few registers spilled belong to
+// the rarely taken division branch).
 template <class S, int ND, bool DIV>
 constexpr int vec_waves()
 {
-    return (sizeof(S) == 2 && ND == 1 && !DIV) ? 5 : 1;
+    if constexpr (ND != 1) return 1;
+    else if constexpr (sizeof(S) == 2) return DIV ? 4 : 5;
+    else if constexpr (sizeof(S) == 4) return DIV ? 6 : 1;
+    else return 1;
 }
 
 template <class S, int NT, int ND, bool DIV>
@@ -1552,10 +1579,12 @@ constexpr int kRedThreads = 1024;
 constexpr int kRedWaves = kRedThreads / 64;
 
 // Deterministic reductions of one block of kRedThreads threads: N values at
-// once, one LDS round, results in every thread.
+// once, one LDS round, results in every thread.  The 16 waves' results are
+// combined by each row of 16 lanes reading them one per lane.
 template <int N, class T, class Op = OpAdd>
 __device__ __forceinline__ void block_reduce(T (&v)[N], T (*sh)[kRedWaves], Op op = Op())
 {
+    static_assert(kRedWaves == 16, "one wave's result per lane of a row");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < N; ++k) v[k] = wave_reduce(v[k], op);
@@ -1566,11 +1595,7 @@ __device__ __forceinline__ void block_reduce(T (&v)[N], T (*sh)[kRedWaves], Op o
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-        T r = sh[k][0];
-        for (int w = 1; w < kRedWaves; ++w) r = op(r, sh[k][w]);
-        v[k] = r;
-    }
+    for (int k = 0; k < N; ++k) v[k] = row_reduce(sh[k][lane & 15], op);
 }
 
 // Division laws: this thread's share of the step's tallies from the device

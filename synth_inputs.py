@@ -115,3 +115,28 @@ def served_trace(n: int = 600, rate_hz: float = 20.0, seed: int = 0,
             c.update(growth_rate=1e-4)
         out.append(c)
     return out
+
+
+# Appendix B: the density-dependent division law (Eq. 5) against divisions
+# held to a band of 30 rows above the rear wall, uniform within it, at
+# L = 640 with the paper's Appendix A parameters rescaled to rho_init = 1
+# (sigma 0.01 -> 0.1, rho_cell 0.01 -> 0.1, rho0 0.15 -> 1.5; initial density
+# uniform on [0.9, 1.1] rho_init), the rear wall kept max(50, 10 w) behind
+# the mean front, float32.  Height and initial tissue rows are this build's
+# choice: room for the wall gap and a front several w rough.
+APPB_BASE = dict(BASE, L=640, H=2048, init_rows=100, init_amp=0.1, sigma=0.1,
+                 growth_rate=1e-3, ybc="follow", wall_min_gap=50, wall_w_factor=10.0,
+                 window=True, precision="fp32")
+
+
+def appendix_b(nseed: int = 4) -> list[dict]:
+    """nseed runs of each regime: density-dependent divisions everywhere,
+    then uniform divisions in the 30-row rear band."""
+    runs = []
+    for sd in range(nseed):
+        runs.append(dict(APPB_BASE, name=f"appb_density_s{sd}", growth="division_density",
+                         seed=500 + sd, replica=sd))
+    for sd in range(nseed):
+        runs.append(dict(APPB_BASE, name=f"appb_rearband_s{sd}", growth="division",
+                         region="rear_band", region_width=30, seed=600 + sd, replica=sd))
+    return runs
