@@ -16,6 +16,12 @@
  * the growth axis (rows); the rear wall sits half a lattice unit below the
  * first live row.
  *
+ * The paper's own lattice, D2Q7 (Sec. II), is the second option: six unit
+ * directions at multiples of pi/3 plus rest, weights 1/2 (rest) and 1/12,
+ * c_s^2 = 1/4, so Eq. 3 reads w_i rho (1 + 4 e.u* + 8 (e.u*)^2 - 2 |u*|^2) and
+ * Eq. 4 subtracts the mean over 7 directions.  Its rows are horizontal with
+ * odd rows shifted by half a unit (see the header).
+ *
  * Compile with -ffp-contract=off: every product and sum below is rounded on
  * its own, in the order written.
  */
@@ -38,6 +44,21 @@ static double weight(int i)
     if (i <= 4) return 1.0 / 9.0;
     return 1.0 / 36.0;
 }
+
+/* D2Q7: 0 rest, 1 E, 2 NE, 3 NW, 4 W, 5 SW, 6 SE */
+static const int32_t OPP7[7] = {0, 4, 5, 6, 1, 2, 3};
+static const double SQRT3_2 = 0.86602540378443864676;   /* sin(pi/3) */
+
+static double weight7(int i)
+{
+    return (i == 0) ? 1.0 / 2.0 : 1.0 / 12.0;
+}
+
+int orc_q(const orc_params *p)
+{
+    return p->lattice == ORC_LATTICE_D2Q7 ? 7 : 9;
+}
+
 
 void orc_lattice(int32_t cx[9], int32_t cy[9], int32_t opp[9], double w[9])
 {
@@ -190,6 +211,34 @@ void orc_fss(double rho, double ux, double uy, double out[9])
     }
 }
 
+/* Eq. 3 on D2Q7.  e_i . u* from the components: a = ux/2, b = sqrt(3)/2 uy;
+ * E: ux, NE: a + b, NW: b - a, and the reverse directions their negatives. */
+void orc_fss7(double rho, double ux, double uy, double out[7])
+{
+    double usq = ux * ux + uy * uy;
+    double a = 0.5 * ux;
+    double b = SQRT3_2 * uy;
+    double cu[7];
+    cu[0] = 0.0;
+    cu[1] = ux;
+    cu[2] = a + b;
+    cu[3] = b - a;
+    cu[4] = -cu[1];
+    cu[5] = -cu[2];
+    cu[6] = -cu[3];
+    for (int i = 0; i < 7; ++i) {
+        double wr = weight7(i) * rho;
+        out[i] = wr * (((1.0 + 4.0 * cu[i]) + 8.0 * (cu[i] * cu[i])) - 2.0 * usq);
+    }
+}
+
+/* Eq. 3 at rest on either lattice: w_i rho */
+static void fss_rest(const orc_params *p, double rho, double out[9])
+{
+    if (p->lattice == ORC_LATTICE_D2Q7) orc_fss7(rho, 0.0, 0.0, out);
+    else orc_fss(rho, 0.0, 0.0, out);
+}
+
 /* ----------------------------------------------------------------------- */
 /* Window storage                                                            */
 /* ----------------------------------------------------------------------- */
@@ -231,14 +280,67 @@ static int params_valid(const orc_params *p)
     if (p->region != ORC_REGION_ALL && p->region_width < 0) return 0;
     if (p->ybc < ORC_Y_WALL_FIXED || p->ybc > ORC_Y_PERIODIC) return 0;
     if (p->ybc == ORC_Y_WALL_FOLLOW && (p->wall_min_gap < 0 || !(p->wall_w_factor >= 0.0))) return 0;
+    if (p->lattice != ORC_LATTICE_D2Q9 && p->lattice != ORC_LATTICE_D2Q7) return 0;
+    /* a periodic D2Q7 column of rows must keep the row parity across the seam */
+    if (p->lattice == ORC_LATTICE_D2Q7 && p->ybc == ORC_Y_PERIODIC && p->H % 2 != 0) return 0;
     return 1;
 }
 
 /* ----------------------------------------------------------------------- */
 /* Step 1: streaming, pulled to the receiving site                           */
 /* ----------------------------------------------------------------------- */
+/* D2Q7 pull sources: the upstream neighbour of (x, y) along -e_i.  With odd
+ * rows shifted by +1/2, the neighbour half a unit to the left in the row
+ * below or above is at column x - 1 + par, and half a unit to the right at
+ * x + par, par = y mod 2.  Row offsets and those column choices: */
+static void pull_source7(int i, int par, int32_t *dx, int32_t *dy)
+{
+    switch (i) {
+    case 1: *dx = -1; *dy = 0; break;            /* E from the left            */
+    case 2: *dx = par - 1; *dy = -1; break;      /* NE from below-left         */
+    case 3: *dx = par; *dy = -1; break;          /* NW from below-right        */
+    case 4: *dx = 1; *dy = 0; break;             /* W from the right           */
+    case 5: *dx = par; *dy = 1; break;           /* SW from above-right        */
+    case 6: *dx = par - 1; *dy = 1; break;       /* SE from above-left         */
+    default: *dx = 0; *dy = 0; break;            /* rest                       */
+    }
+}
+
+static void pull_site7(const orc_params *p, const double *f, int32_t x, int32_t j, int64_t y_abs,
+                       double fstar[7])
+{
+    const int par = (int)(y_abs & 1);
+    for (int i = 0; i < 7; ++i) {
+        int32_t dx, dy;
+        pull_source7(i, par, &dx, &dy);
+        int32_t xs = ((x + dx) % p->L + p->L) % p->L;   /* periodic in x */
+        int32_t js = j + dy;
+        if (p->ybc == ORC_Y_PERIODIC) {
+            js = (js % p->H + p->H) % p->H;
+            fstar[i] = f[idx(p, i, js, xs)];
+        } else if (js < 0) {
+            /* rear wall: what left this site towards it comes back reversed */
+            fstar[i] = f[idx(p, OPP7[i], j, x)];
+        } else if (js >= p->H) {
+            fstar[i] = 0.0;
+        } else {
+            fstar[i] = f[idx(p, i, js, xs)];
+        }
+    }
+}
+
 void orc_pull_site(const orc_params *p, const double *f, int32_t x, int32_t j, double fstar[9])
 {
+    orc_pull_site_abs(p, f, x, j, j, fstar);
+}
+
+void orc_pull_site_abs(const orc_params *p, const double *f, int32_t x, int32_t j, int64_t y_abs,
+                       double fstar[9])
+{
+    if (p->lattice == ORC_LATTICE_D2Q7) {
+        pull_site7(p, f, x, j, y_abs, fstar);
+        return;
+    }
     for (int i = 0; i < 9; ++i) {
         int32_t xs = ((x - CX[i]) % p->L + p->L) % p->L;   /* periodic in x */
         int32_t js = j - CY[i];
@@ -272,6 +374,19 @@ static double sum9(const double v[9])
     double s = v[0];
     for (int i = 1; i < 9; ++i) s = s + v[i];
     return s;
+}
+
+static double sum7(const double v[7])
+{
+    double s = v[0];
+    for (int i = 1; i < 7; ++i) s = s + v[i];
+    return s;
+}
+
+/* density of a site's populations on either lattice, summed in index order */
+static double sumq(const orc_params *p, const double *v)
+{
+    return p->lattice == ORC_LATTICE_D2Q7 ? sum7(v) : sum9(v);
 }
 
 static int division_law(const orc_params *p)
@@ -321,6 +436,115 @@ static double division_lam(const orc_params *p, int64_t mfx, int64_t wsum)
 }
 
 /* ----------------------------------------------------------------------- */
+/* Steps 2-7 at one site of the D2Q7 lattice                                 */
+/* ----------------------------------------------------------------------- */
+static int update_site7(const orc_params *p, const double fstar_in[7], int64_t t, int32_t x,
+                        int64_t y_abs, int32_t h_prev_x, int64_t y_wall, int force, double lam,
+                        double out[7], double *S_out, double *dfix_out, int32_t *ndiv_out,
+                        int64_t *wfx_out)
+{
+    double fs[7];
+    for (int i = 0; i < 7; ++i) fs[i] = fstar_in[i];
+    *S_out = 0.0;
+    *dfix_out = 0.0;
+    *ndiv_out = 0;
+    *wfx_out = 0;
+
+    /* step 2: density and momentum (Eq. 1) with e_i = (cos, sin)((i-1) pi/3):
+     * j_x = (f1 - f4) + (f2 - f3 - f5 + f6)/2, j_y = sqrt(3)/2 (f2 + f3 - f5 - f6) */
+    double rho_star = sum7(fs);
+    double jx = (fs[1] - fs[4]) + 0.5 * (((fs[2] - fs[3]) + fs[6]) - fs[5]);
+    double jy = SQRT3_2 * (((fs[2] + fs[3]) - fs[5]) - fs[6]);
+
+    int tissue = (force < 0) ? (rho_star >= p->rho_c) : (force > 0);
+    if (!tissue) {
+        /* step 5, second case: reverse every direction (1-4, 2-5, 3-6) */
+        for (int i = 0; i < 7; ++i) out[i] = fs[OPP7[i]];
+        return 0;
+    }
+
+    /* step 3: the expected injection shared by the six moving directions */
+    double S = 0.0;
+    if (p->growth == ORC_GROWTH_BULK && in_region(p, y_abs, h_prev_x, y_wall))
+        S = p->growth_rate * rho_star;
+    double s6 = S / 6.0;
+    for (int i = 1; i < 7; ++i) fs[i] = fs[i] + s6;
+    /* step 3, division laws: as on D2Q9, with three axes; each division's
+     * axis is one base-3 digit of the 64 random bits */
+    double q;
+    if (division_eligible(p, rho_star, in_region(p, y_abs, h_prev_x, y_wall), &q)) {
+        *wfx_out = division_weight(p, q);
+        double l = lam * q;
+        if (l > 8.0) l = 8.0;
+        if (l > 0.0) {
+            double U;
+            uint64_t axes;
+            orc_division_draws(p->seed, p->replica, t, x, y_abs, &U, &axes);
+            int k = orc_poisson_k(U, l);
+            int count[3] = {0, 0, 0};
+            uint64_t digits = axes;
+            for (int d = 0; d < k; ++d) {
+                count[digits % 3u] += 1;
+                digits = digits / 3u;
+            }
+            double half = p->rho_cell * 0.5;
+            for (int a = 0; a < 3; ++a) {
+                /* axis a joins direction a + 1 and its reverse a + 4 */
+                double amount = (double)count[a] * half;
+                fs[a + 1] = fs[a + 1] + amount;
+                fs[OPP7[a + 1]] = fs[OPP7[a + 1]] + amount;
+            }
+            S = (double)k * p->rho_cell;
+            *ndiv_out = k;
+        }
+    }
+    double rho = rho_star + S;
+    *S_out = S;
+
+    /* step 4 and step 5, first case */
+    double kmu = 1.0 - p->mu;
+    double ux = (jx / rho) * kmu;
+    double uy = (jy / rho) * kmu;
+    double fss[7];
+    orc_fss7(rho, ux, uy, fss);
+    double omega = 1.0 / p->tau;
+    for (int i = 0; i < 7; ++i) out[i] = fs[i] - omega * (fs[i] - fss[i]);
+
+    /* step 6: Eq. 4 over seven directions (the first seven noise draws) */
+    if (rho > p->rho_c && p->sigma > 0.0) {
+        double u[9], eta[7];
+        orc_noise_uniforms(p->seed, p->replica, t, x, y_abs, u);
+        for (int i = 0; i < 7; ++i) eta[i] = p->sigma * (2.0 * u[i] - 1.0);
+        double m = sum7(eta) / 7.0;
+        for (int i = 0; i < 7; ++i) out[i] = out[i] + (eta[i] - m);
+    }
+
+    /* step 7, as on D2Q9 with the D2Q7 reverse directions */
+    int any_negative = 0;
+    for (int i = 0; i < 7; ++i) if (out[i] < 0.0) any_negative = 1;
+    if (any_negative) {
+        double before = sum7(out);
+        if (out[0] < 0.0) {
+            double rho_pre = sum7(out);
+            out[0] = 0.0;
+            double rest = sum7(out);
+            if (rest > 0.0) {
+                double r = rho_pre / rest;
+                for (int i = 0; i < 7; ++i) out[i] = out[i] * r;
+            }
+        }
+        for (int i = 1; i < 7; ++i) {
+            if (out[i] < 0.0) {
+                out[OPP7[i]] = out[OPP7[i]] + (-out[i]);
+                out[i] = 0.0;
+            }
+        }
+        *dfix_out = sum7(out) - before;
+    }
+    return 1;
+}
+
+/* ----------------------------------------------------------------------- */
 /* Steps 2-7 at one site                                                     */
 /* ----------------------------------------------------------------------- */
 int orc_update_site(const orc_params *p, const double fstar_in[9], int64_t t,
@@ -328,6 +552,9 @@ int orc_update_site(const orc_params *p, const double fstar_in[9], int64_t t,
                     int force, double lam, double out[9], double *S_out,
                     double *dfix_out, int32_t *ndiv_out, int64_t *wfx_out)
 {
+    if (p->lattice == ORC_LATTICE_D2Q7)
+        return update_site7(p, fstar_in, t, x, y_abs, h_prev_x, y_wall, force, lam, out, S_out,
+                            dfix_out, ndiv_out, wfx_out);
     double fs[9];
     for (int i = 0; i < 9; ++i) fs[i] = fstar_in[i];
     *S_out = 0.0;
@@ -468,8 +695,8 @@ static double window_mass(const orc_state *s)
     for (int32_t j = 0; j < p->H; ++j)
         for (int32_t x = 0; x < p->L; ++x) {
             double v[9];
-            for (int i = 0; i < 9; ++i) v[i] = s->f[idx(p, i, j, x)];
-            m += sum9(v);
+            for (int i = 0; i < orc_q(p); ++i) v[i] = s->f[idx(p, i, j, x)];
+            m += sumq(p, v);
         }
     return m;
 }
@@ -482,8 +709,8 @@ static int64_t window_mass_fx(const orc_state *s)
     for (int32_t j = 0; j < p->H; ++j)
         for (int32_t x = 0; x < p->L; ++x) {
             double v[9];
-            for (int i = 0; i < 9; ++i) v[i] = s->f[idx(p, i, j, x)];
-            m += mass_fx(sum9(v));
+            for (int i = 0; i < orc_q(p); ++i) v[i] = s->f[idx(p, i, j, x)];
+            m += mass_fx(sumq(p, v));
         }
     return m;
 }
@@ -498,8 +725,8 @@ static void division_rates_from_state(orc_state *s)
     for (int32_t j = 0; j < p->H; ++j)
         for (int32_t x = 0; x < p->L; ++x) {
             double v[9];
-            for (int i = 0; i < 9; ++i) v[i] = s->f[idx(p, i, j, x)];
-            double rho = sum9(v), q;
+            for (int i = 0; i < orc_q(p); ++i) v[i] = s->f[idx(p, i, j, x)];
+            double rho = sumq(p, v), q;
             int64_t y_abs = s->y_wall + j;
             if (rho >= p->rho_c &&
                 division_eligible(p, rho, in_region(p, y_abs, s->h[x], s->y_wall), &q))
@@ -524,7 +751,8 @@ static void check_front(orc_state *s)
 /* ----------------------------------------------------------------------- */
 size_t orc_state_bytes(const orc_params *p)
 {
-    return 2u * 9u * (size_t)p->L * (size_t)p->H * sizeof(double) + (size_t)p->L * sizeof(int32_t);
+    return 2u * (size_t)orc_q(p) * (size_t)p->L * (size_t)p->H * sizeof(double) +
+           (size_t)p->L * sizeof(int32_t);
 }
 
 orc_state *orc_create(const orc_params *p)
@@ -533,7 +761,7 @@ orc_state *orc_create(const orc_params *p)
     orc_state *s = (orc_state *)calloc(1, sizeof(orc_state));
     if (!s) return NULL;
     s->p = *p;
-    size_t n = 9u * (size_t)p->L * (size_t)p->H;
+    size_t n = (size_t)orc_q(p) * (size_t)p->L * (size_t)p->H;
     s->f = (double *)calloc(n, sizeof(double));
     s->fn = (double *)calloc(n, sizeof(double));
     s->h = (int32_t *)calloc((size_t)p->L, sizeof(int32_t));
@@ -546,8 +774,8 @@ orc_state *orc_create(const orc_params *p)
             double U = orc_init_uniform(p->seed, p->replica, x, j);
             double rho = p->rho_init * (1.0 + p->init_amp * (2.0 * U - 1.0));
             double fss[9];
-            orc_fss(rho, 0.0, 0.0, fss);
-            for (int i = 0; i < 9; ++i) s->f[idx(p, i, j, x)] = fss[i];
+            fss_rest(p, rho, fss);
+            for (int i = 0; i < orc_q(p); ++i) s->f[idx(p, i, j, x)] = fss[i];
         }
     s->t = 0;
     s->y_wall = 0;
@@ -556,8 +784,8 @@ orc_state *orc_create(const orc_params *p)
         int32_t hx = 0;
         for (int32_t j = 0; j < p->H; ++j) {
             double v[9];
-            for (int i = 0; i < 9; ++i) v[i] = s->f[idx(p, i, j, x)];
-            if (sum9(v) >= p->rho_c) hx = j + 1;
+            for (int i = 0; i < orc_q(p); ++i) v[i] = s->f[idx(p, i, j, x)];
+            if (sumq(p, v) >= p->rho_c) hx = j + 1;
         }
         s->h[x] = hx;
     }
@@ -594,10 +822,10 @@ static void advance_wall(orc_state *s)
     for (int32_t j = 0; j < (int32_t)k; ++j)
         for (int32_t x = 0; x < p->L; ++x) {
             double v[9];
-            for (int i = 0; i < 9; ++i) v[i] = s->f[idx(p, i, j, x)];
-            gone += sum9(v);
+            for (int i = 0; i < orc_q(p); ++i) v[i] = s->f[idx(p, i, j, x)];
+            gone += sumq(p, v);
         }
-    for (int i = 0; i < 9; ++i)
+    for (int i = 0; i < orc_q(p); ++i)
         for (int32_t j = 0; j < p->H; ++j)
             for (int32_t x = 0; x < p->L; ++x) {
                 int32_t src = j + (int32_t)k;
@@ -626,10 +854,10 @@ int orc_step(orc_state *s, int64_t nsteps)
                 double fstar[9], out[9], S, dfix;
                 int32_t ndiv;
                 int64_t wfx;
-                orc_pull_site(p, s->f, x, j, fstar);
+                orc_pull_site_abs(p, s->f, x, j, y_abs, fstar);
                 int tissue = orc_update_site(p, fstar, s->t, x, y_abs, s->h[x], s->y_wall, -1,
                                              s->lam, out, &S, &dfix, &ndiv, &wfx);
-                for (int i = 0; i < 9; ++i) s->fn[idx(p, i, j, x)] = out[i];
+                for (int i = 0; i < orc_q(p); ++i) s->fn[idx(p, i, j, x)] = out[i];
                 src += S;
                 fix += dfix;
                 s->divisions += ndiv;
@@ -681,12 +909,12 @@ void orc_front_heights(const orc_state *s, int32_t *h_out)
 
 void orc_get_populations(const orc_state *s, double *f_out)
 {
-    memcpy(f_out, s->f, 9u * (size_t)s->p.L * (size_t)s->p.H * sizeof(double));
+    memcpy(f_out, s->f, (size_t)orc_q(&s->p) * (size_t)s->p.L * (size_t)s->p.H * sizeof(double));
 }
 
 void orc_set_populations(orc_state *s, const double *f_in)
 {
-    memcpy(s->f, f_in, 9u * (size_t)s->p.L * (size_t)s->p.H * sizeof(double));
+    memcpy(s->f, f_in, (size_t)orc_q(&s->p) * (size_t)s->p.L * (size_t)s->p.H * sizeof(double));
     s->mass = window_mass(s);
     division_rates_from_state(s);
 }

@@ -1,7 +1,8 @@
 /*
- * lbm_oracle.h -- plain FP64 CPU oracle for the growing-tissue D2Q9 lattice
+ * lbm_oracle.h -- plain FP64 CPU oracle for the growing-tissue lattice
  * Boltzmann method (Killeen, Partridge, Bertrand, Lee, "Modeling growing
- * confluent tissues using a lattice Boltzmann method", arXiv 2303.02210).
+ * confluent tissues using a lattice Boltzmann method", arXiv 2303.02210), on
+ * the square D2Q9 lattice or on the paper's own triangular D2Q7 lattice.
  *
  * TEST INFRASTRUCTURE ONLY.  This code is the slow, obviously correct
  * reference the GPU library is checked against.  Only the test suite, the
@@ -38,6 +39,13 @@ enum { ORC_REGION_ALL = 0, ORC_REGION_FRONT_BAND = 1, ORC_REGION_REAR_BAND = 2 }
 enum { ORC_Y_WALL_FIXED = 0, ORC_Y_WALL_FOLLOW = 1, ORC_Y_PERIODIC = 2 };
 /* status bits */
 enum { ORC_ST_DOMAIN_FULL = 1u, ORC_ST_NONFINITE = 2u };
+/* lattice: square D2Q9 (populations [9][H][L]) or the paper's triangular D2Q7
+ * (Sec. II; populations [7][H][L]).  D2Q7 rows are horizontal lines sqrt(3)/2
+ * apart and odd rows are shifted half a lattice unit along +x, so site (x, y)
+ * sits at (x + (y mod 2)/2, y sqrt(3)/2); directions e_i = (cos, sin) of
+ * (i - 1) pi/3: 0 rest, 1 E, 2 NE, 3 NW, 4 W, 5 SW, 6 SE; reverse pairs 1-4,
+ * 2-5, 3-6.  Parity is that of the absolute row. */
+enum { ORC_LATTICE_D2Q9 = 0, ORC_LATTICE_D2Q7 = 1 };
 
 typedef struct {
     int32_t  L, H;           /* columns (periodic x), rows (growth axis y)   */
@@ -59,6 +67,7 @@ typedef struct {
     uint32_t replica;        /* Philox key word 1                             */
     double   rho_cell;       /* mass of one cell (division laws), Sec. II     */
     double   rho0;           /* density above which division stops, Eq. 5     */
+    int32_t  lattice;        /* ORC_LATTICE_*                                 */
 } orc_params;
 
 typedef struct {
@@ -113,6 +122,14 @@ void orc_fss(double rho, double ux_star, double uy_star, double out[9]);
  * f[9][H][L] (j = row inside the window). */
 void orc_pull_site(const orc_params *p, const double *f, int32_t x, int32_t j,
                    double fstar[9]);
+/* The same for window row j holding absolute row y_abs (D2Q7 pulls depend on
+ * the absolute row's parity; orc_pull_site takes y_abs = j). */
+void orc_pull_site_abs(const orc_params *p, const double *f, int32_t x, int32_t j,
+                       int64_t y_abs, double fstar[9]);
+/* Eq. 3 on D2Q7: w_i rho (1 + 4 e.u* + 8 (e.u*)^2 - 2 |u*|^2), w = 1/2, 1/12. */
+void orc_fss7(double rho, double ux_star, double uy_star, double out[7]);
+/* Populations per site of the lattice p names (9 or 7). */
+int orc_q(const orc_params *p);
 
 /* Steps 2-7 of Appendix A at one site, given its streamed populations.
  * force: -1 classify by density, 0 force the void branch, 1 force tissue.

@@ -5,8 +5,9 @@ checked against.  Only the test suite, the smoke check and the CPU-baseline
 leg of the benchmark may import this module; the product package never does.
 
 The oracle follows Appendix A of arXiv 2303.02210 (steps 1-7 per site, then
-the front heights, the width of Sec. III and the rear-wall rule), mapped to the
-D2Q9 lattice; see ``lbm_oracle.c`` for the per-step citations.
+the front heights, the width of Sec. III and the rear-wall rule), on the
+square D2Q9 lattice or on the paper's triangular D2Q7 lattice; see
+``lbm_oracle.c`` for the per-step citations.
 """
 from __future__ import annotations
 
@@ -23,6 +24,8 @@ _LIB = os.environ.get("LBM_ORACLE_LIB") or os.path.join(_HERE, "liblbm_oracle.so
 GROWTH = {"none": 0, "bulk": 1, "division": 2, "division_density": 3}
 REGION = {"all": 0, "front_band": 1, "rear_band": 2}
 YBC = {"fixed": 0, "follow": 1, "periodic": 2}
+LATTICE = {"d2q9": 0, "d2q7": 1}
+Q = {"d2q9": 9, "d2q7": 7}
 ST_DOMAIN_FULL = 1
 ST_NONFINITE = 2
 
@@ -52,6 +55,7 @@ class _Params(ctypes.Structure):
         ("wall_w_factor", ctypes.c_double),
         ("seed", ctypes.c_uint32), ("replica", ctypes.c_uint32),
         ("rho_cell", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("lattice", ctypes.c_int32),
     ]
 
 
@@ -89,6 +93,11 @@ def lib():
         L.orc_fss.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.orc_pull_site.argtypes = [ctypes.POINTER(_Params), dp, ctypes.c_int32,
                                     ctypes.c_int32, dp]
+        L.orc_pull_site_abs.argtypes = [ctypes.POINTER(_Params), dp, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int64, dp]
+        L.orc_fss7.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_q.argtypes = [ctypes.POINTER(_Params)]
+        L.orc_q.restype = ctypes.c_int
         L.orc_update_site.argtypes = [ctypes.POINTER(_Params), dp, ctypes.c_int64,
                                       ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                       ctypes.c_int64, ctypes.c_int, ctypes.c_double, dp, dp, dp,
@@ -143,7 +152,13 @@ def make_params(cfg: dict) -> _Params:
     p.replica = int(cfg.get("replica", 0)) & 0xFFFFFFFF
     p.rho_cell = float(cfg.get("rho_cell", 0.1))
     p.rho0 = float(cfg.get("rho0", 1.5))
+    p.lattice = LATTICE[cfg.get("lattice", "d2q9")]
     return p
+
+
+def q_of(p: _Params) -> int:
+    """Populations per site of the lattice p names."""
+    return 7 if p.lattice == LATTICE["d2q7"] else 9
 
 
 def philox4x32_10(ctr, key) -> np.ndarray:
@@ -203,20 +218,30 @@ def fss(rho, ux, uy) -> np.ndarray:
     return out
 
 
-def pull_site(cfg_or_params, f: np.ndarray, x: int, j: int) -> np.ndarray:
-    p = cfg_or_params if isinstance(cfg_or_params, _Params) else make_params(cfg_or_params)
-    f = np.ascontiguousarray(f, dtype=np.float64)
-    assert f.shape == (9, p.H, p.L)
-    out = np.zeros(9, np.float64)
-    lib().orc_pull_site(ctypes.byref(p), _ptr(f, ctypes.c_double), x, j,
-                        _ptr(out, ctypes.c_double))
+def fss7(rho, ux, uy) -> np.ndarray:
+    out = np.zeros(7, np.float64)
+    lib().orc_fss7(float(rho), float(ux), float(uy), _ptr(out, ctypes.c_double))
     return out
 
 
-def update_site_ex(cfg_or_params, fstar, t, x, y_abs, h_prev_x, y_wall=0, force=-1, lam=0.0):
-    """Steps 2-7 at one site.  Returns (f_out[9], tissue, S, dfix, ndiv, wfx)."""
+def pull_site(cfg_or_params, f: np.ndarray, x: int, j: int, y_abs: int | None = None) -> np.ndarray:
+    """Step 1 at window row j (absolute row y_abs, default j)."""
     p = cfg_or_params if isinstance(cfg_or_params, _Params) else make_params(cfg_or_params)
-    fs = np.ascontiguousarray(fstar, dtype=np.float64)
+    q = q_of(p)
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    assert f.shape == (q, p.H, p.L)
+    out = np.zeros(9, np.float64)
+    lib().orc_pull_site_abs(ctypes.byref(p), _ptr(f, ctypes.c_double), x, j,
+                            j if y_abs is None else int(y_abs), _ptr(out, ctypes.c_double))
+    return out[:q]
+
+
+def update_site_ex(cfg_or_params, fstar, t, x, y_abs, h_prev_x, y_wall=0, force=-1, lam=0.0):
+    """Steps 2-7 at one site.  Returns (f_out[Q], tissue, S, dfix, ndiv, wfx)."""
+    p = cfg_or_params if isinstance(cfg_or_params, _Params) else make_params(cfg_or_params)
+    q = q_of(p)
+    fs = np.zeros(9, np.float64)
+    fs[:q] = np.asarray(fstar, dtype=np.float64)[:q]
     out = np.zeros(9, np.float64)
     S = ctypes.c_double()
     dfix = ctypes.c_double()
@@ -226,11 +251,11 @@ def update_site_ex(cfg_or_params, fstar, t, x, y_abs, h_prev_x, y_wall=0, force=
                                    int(x), int(y_abs), int(h_prev_x), int(y_wall), int(force),
                                    float(lam), _ptr(out, ctypes.c_double), ctypes.byref(S),
                                    ctypes.byref(dfix), ctypes.byref(nd), ctypes.byref(wfx))
-    return out, bool(tissue), S.value, dfix.value, nd.value, wfx.value
+    return out[:q], bool(tissue), S.value, dfix.value, nd.value, wfx.value
 
 
 def update_site(cfg_or_params, fstar, t, x, y_abs, h_prev_x, y_wall=0, force=-1, lam=0.0):
-    """Steps 2-7 at one site.  Returns (f_out[9], tissue, S, dfix)."""
+    """Steps 2-7 at one site.  Returns (f_out[Q], tissue, S, dfix)."""
     return update_site_ex(cfg_or_params, fstar, t, x, y_abs, h_prev_x, y_wall, force, lam)[:4]
 
 
@@ -245,6 +270,7 @@ class Oracle:
             raise ValueError("invalid oracle parameters")
         self.L = self.p.L
         self.H = self.p.H
+        self.Q = q_of(self.p)
 
     def close(self):
         if self._h:
@@ -276,13 +302,13 @@ class Oracle:
         lib().orc_set_front_heights(self._h, _ptr(a, ctypes.c_int32))
 
     def populations(self) -> np.ndarray:
-        out = np.zeros((9, self.H, self.L), np.float64)
+        out = np.zeros((self.Q, self.H, self.L), np.float64)
         lib().orc_get_populations(self._h, _ptr(out, ctypes.c_double))
         return out
 
     def set_populations(self, f) -> None:
         a = np.ascontiguousarray(f, dtype=np.float64)
-        assert a.shape == (9, self.H, self.L)
+        assert a.shape == (self.Q, self.H, self.L)
         lib().orc_set_populations(self._h, _ptr(a, ctypes.c_double))
 
     def set_step(self, t: int) -> None:
