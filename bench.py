@@ -34,7 +34,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("lbm_step.hpp", "lbm_device.hpp", "lbm_internal.hpp"):
+    for f in ("lbm_step.hpp", "lbm_d2q7.hpp", "lbm_device.hpp", "lbm_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2303_02210_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -112,6 +112,9 @@ def main():
                     help="bulk / edge: the growth law (default: the workload's own, a "
                          "continuous source); division draws discrete cell divisions per site, "
                          "division_density accepts them with Eq. 5's density weight")
+    ap.add_argument("--lattice", default="d2q9", choices=["d2q9", "d2q7"],
+                    help="bulk / edge: the square D2Q9 lattice (default) or the paper's "
+                         "triangular D2Q7 lattice")
     ap.add_argument("--tuned", action="store_true", help="launch shapes from the autotuner cache")
     ap.add_argument("--shape", default=None, help="force a launch shape: kernel_vb,kernel_ty")
     args = ap.parse_args()
@@ -138,6 +141,8 @@ def main():
     cfg = dict(base, precision=args.precision)
     if args.growth and args.growth != cfg["growth"]:
         cfg.update(growth=args.growth, name=f"{cfg['name']}_{args.growth}")
+    if args.lattice != "d2q9":
+        cfg.update(lattice=args.lattice, name=f"{cfg['name']}_{args.lattice}")
     if args.tuned:
         from paper_2303_02210_amd import autotune
         cfg = autotune.apply(cfg)
@@ -145,7 +150,8 @@ def main():
         v = [int(x) for x in args.shape.split(",")]
         cfg.update(kernel_vb=v[0], kernel_ty=v[1])
     L, H = cfg["L"], cfg["H"]
-    bpu = 2 * 9 * STORE_BYTES[args.precision]          # read 9 + write 9 populations
+    nq = 7 if args.lattice == "d2q7" else 9
+    bpu = 2 * nq * STORE_BYTES[args.precision]         # read Q + write Q populations
 
     # warm-up on a scratch run
     sim = Sim(cfg)
@@ -196,7 +202,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPE[args.precision], "data": "synthetic",
         "config": {"workload": cfg["name"], "L": L, "H": H, "precision": args.precision,
-                   "growth": cfg["growth"], "region": cfg["region"],
+                   "lattice": args.lattice, "growth": cfg["growth"], "region": cfg["region"],
                    "growth_rate": cfg["growth_rate"], "tau": cfg["tau"], "sigma": cfg["sigma"],
                    "init_rows": cfg["init_rows"], "h_every": every, "sweep": "full",
                    "bytes_per_update": bpu,

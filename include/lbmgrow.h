@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 2u
+#define LBM_ABI_VERSION 3u
 
 typedef struct lbm_handle lbm_handle;
 typedef struct lbm_batch lbm_batch;
@@ -92,6 +92,17 @@ typedef enum {
     LBM_Y_PERIODIC = 2       /* periodic rows (test mode)                     */
 } lbm_ybc;
 
+/* Lattice (Sec. II).  D2Q9: the square lattice, directions 0 rest, 1 E, 2 N,
+ * 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE.  D2Q7: the paper's own triangular
+ * lattice, weights 1/2 and 1/12, c_s^2 = 1/4, directions 0 rest, 1 E, 2 NE,
+ * 3 NW, 4 W, 5 SW, 6 SE; its rows are horizontal lines sqrt(3)/2 apart with
+ * odd (absolute) rows shifted half a unit along +x.  Population arrays are
+ * [Q][H][L] with Q = 9 or 7. */
+typedef enum {
+    LBM_LATTICE_D2Q9 = 0,
+    LBM_LATTICE_D2Q7 = 1
+} lbm_lattice;
+
 /* lbm_params.flags */
 #define LBM_FLAG_WINDOW 1u   /* sweep only rows that can hold mass: rows at or
                                 below the highest front seen plus one (the rest
@@ -101,7 +112,10 @@ typedef enum {
  * Model and run parameters.  Set abi_version = LBM_ABI_VERSION and
  * struct_size = sizeof(lbm_params).
  *   L, H          columns (periodic) and rows of the live window; L >= 2,
- *                 H >= 4, L * H * 9 populations must fit the workspace.
+ *                 H >= 4, L * H * Q populations must fit the workspace.
+ *   lattice       lbm_lattice.  D2Q7 runs the one-column-per-lane form
+ *                 (kernel_vb 0 or 1), needs an even H when periodic, and is
+ *                 not accepted by batches (LBM_E_UNSUPPORTED).
  *   precision     lbm_precision.
  *   tau           relaxation time of Eq. 2, tau > 1/2.
  *   mu            friction: the steady state uses u* = (1 - mu) u (below
@@ -168,6 +182,8 @@ typedef struct {
     int32_t  kernel_ty;
     double   rho_cell;
     double   rho0;
+    int32_t  lattice;
+    int32_t  reserved0;
 } lbm_params;
 
 /* Diagnostics after the last enqueued step (all reductions in float64). */
@@ -222,7 +238,7 @@ int lbm_front_heights_async(lbm_handle *h, int32_t *dst);
 /* Fill *out.  Synchronizes. */
 int lbm_diagnostics(lbm_handle *h, lbm_diag *out);
 
-/* Populations of the live window decoded to float64 [9][H][L].
+/* Populations of the live window decoded to float64 [Q][H][L].
  * Synchronizes. */
 int lbm_get_populations(lbm_handle *h, double *host_f);
 
@@ -265,7 +281,8 @@ int lbm_destroy(lbm_handle *h);
  *                        members must use the same stream.
  *   lbm_batch_add/remove membership changes (take effect at the next step);
  *                        a handle belongs to at most one batch, and
- *                        lbm_destroy removes it from its batch.
+ *                        lbm_destroy removes it from its batch; D2Q7 handles
+ *                        are refused with LBM_E_UNSUPPORTED.
  *   lbm_batch_step       nsteps >= 0 steps of every member; does not
  *                        synchronize; LBM_E_STATE if a member is in an error
  *                        state (remove it and step again).

@@ -12,7 +12,7 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblbmgrow.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 OK = 0
 E_INVALID, E_NOMEM, E_DEVICE, E_DOMAIN_FULL, E_NONFINITE, E_UNSUPPORTED, E_STATE = (
@@ -23,6 +23,8 @@ ERROR_NAMES = {0: "OK", -1: "LBM_E_INVALID", -2: "LBM_E_NOMEM", -3: "LBM_E_DEVIC
 
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3}
 STORAGE_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2}
+LATTICE = {"d2q9": 0, "d2q7": 1}
+Q = {"d2q9": 9, "d2q7": 7}
 GROWTH = {"none": 0, "bulk": 1, "division": 2, "division_density": 3}
 REGION = {"all": 0, "front_band": 1, "rear_band": 2}
 YBC = {"fixed": 0, "follow": 1, "periodic": 2}
@@ -47,6 +49,7 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint32), ("replica", ctypes.c_uint32),
         ("kernel_vb", ctypes.c_int32), ("kernel_ty", ctypes.c_int32),
         ("rho_cell", ctypes.c_double), ("rho0", ctypes.c_double),
+        ("lattice", ctypes.c_int32), ("reserved0", ctypes.c_int32),
     ]
 
 
@@ -141,6 +144,7 @@ def make_params(cfg: dict) -> Params:
     p.kernel_ty = int(cfg.get("kernel_ty", 0))
     p.rho_cell = float(cfg.get("rho_cell", 0.1))
     p.rho0 = float(cfg.get("rho0", 1.5))
+    p.lattice = LATTICE[cfg.get("lattice", "d2q9")]
     return p
 
 

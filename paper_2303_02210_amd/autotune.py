@@ -34,11 +34,16 @@ def key(cfg: dict) -> str:
     """Storage, width and height rounded up to powers of two, and whether a
     division law runs (its kernels hold more registers)."""
     div = "/div" if str(cfg.get("growth", "bulk")).startswith("division") else ""
-    return f"{cfg.get('precision', 'fp64')}/L{_pow2(int(cfg['L']))}/H{_pow2(int(cfg['H']))}{div}"
+    lat = "/d2q7" if cfg.get("lattice", "d2q9") == "d2q7" else ""
+    return f"{cfg.get('precision', 'fp64')}/L{_pow2(int(cfg['L']))}/H{_pow2(int(cfg['H']))}{div}{lat}"
 
 
 def candidates(cfg: dict):
     esize = _BYTES[cfg.get("precision", "fp64")]
+    if cfg.get("lattice", "d2q9") == "d2q7":      # one form: a column per lane
+        for ty in (1, 2, 4, 8):
+            yield {"kernel_vb": 1, "kernel_ty": ty}
+        return
     vbs = [1] + [vb for vb in (4, 8, 16) if vb >= esize and int(cfg["L"]) % (vb // esize) == 0]
     for vb in vbs:
         for ty in (1, 2, 4, 8):
@@ -121,6 +126,8 @@ def main(argv=None):
     work = [dict(si.BULK_4096_FP32, precision=p) for p in ("fp64", "fp32", "fp16", "bf16")]
     work += [dict(si.EDGE_2048x8192, precision=p) for p in ("fp32", "fp16", "bf16")]
     work += [dict(si.BULK_4096_FP32, precision=p, growth="division")
+             for p in ("fp64", "fp32", "fp16", "bf16")]
+    work += [dict(si.BULK_4096_FP32, precision=p, lattice="d2q7")
              for p in ("fp64", "fp32", "fp16", "bf16")]
     seen = set()
     for c in si.ensemble():

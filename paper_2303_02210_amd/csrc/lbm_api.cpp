@@ -22,6 +22,12 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // D2Q9 weights (rest, axes, diagonals).
 const double kW[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
                       1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+// D2Q7 weights (Sec. II): 1/2 at rest, 1/12 on each of the six directions.
+const double kW7[9] = {1.0 / 2.0, 1.0 / 12.0, 1.0 / 12.0, 1.0 / 12.0, 1.0 / 12.0,
+                       1.0 / 12.0, 1.0 / 12.0, 0.0, 0.0};
+
+int lattice_q(const lbm_params *p) { return p->lattice == LBM_LATTICE_D2Q7 ? 7 : 9; }
+const double *lattice_w(const lbm_params *p) { return p->lattice == LBM_LATTICE_D2Q7 ? kW7 : kW; }
 
 // ---- host float16 / bfloat16 conversions, round to nearest even --------------
 uint16_t f32_to_f16(float f)
@@ -94,9 +100,9 @@ size_t elem_bytes(int prec)
 
 // Storage offset W_i = w_i rho_ref rounded to the storage type (0 when the
 // storage holds f_i itself).
-double offset_base(int prec, int i, double rho_ref)
+double offset_base(int prec, double w, double rho_ref)
 {
-    const float v = (float)(kW[i] * rho_ref);
+    const float v = (float)(w * rho_ref);
     if (prec == LBM_FP16_OFFSET) return (double)f16_to_f32(f32_to_f16(v));
     if (prec == LBM_BF16_OFFSET) return (double)bf16_to_f32(f32_to_bf16(v));
     return 0.0;
@@ -128,7 +134,8 @@ bool params_ok(const lbm_params *p, std::string *why)
     if (p->abi_version != LBM_ABI_VERSION) return bad("abi_version mismatch");
     if (p->struct_size != sizeof(lbm_params)) return bad("struct_size mismatch");
     if (p->L < 2 || p->H < 4) return bad("L must be >= 2 and H >= 4");
-    if ((int64_t)p->L * (int64_t)p->H * 9 > (int64_t)1 << 31) return bad("lattice too large");
+    if (p->lattice != LBM_LATTICE_D2Q9 && p->lattice != LBM_LATTICE_D2Q7) return bad("bad lattice");
+    if ((int64_t)p->L * (int64_t)p->H * lattice_q(p) > (int64_t)1 << 31) return bad("lattice too large");
     if (p->precision < LBM_FP64 || p->precision > LBM_BF16_OFFSET) return bad("bad precision");
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return bad("tau must be > 1/2");
     if (!(p->mu >= 0.0 && p->mu <= 1.0)) return bad("mu must be in [0, 1]");
@@ -155,6 +162,10 @@ bool params_ok(const lbm_params *p, std::string *why)
     if (p->kernel_ty < 0 || p->kernel_ty > 64) return bad("kernel_ty must be in [0, 64]");
     if ((p->flags & LBM_FLAG_WINDOW) && p->ybc == LBM_Y_PERIODIC)
         return bad("the sweep window needs a rear wall");
+    if (p->lattice == LBM_LATTICE_D2Q7 && p->kernel_vb > 1)
+        return bad("the D2Q7 step has the one-column-per-lane form only (kernel_vb 0 or 1)");
+    if (p->lattice == LBM_LATTICE_D2Q7 && p->ybc == LBM_Y_PERIODIC && p->H % 2 != 0)
+        return bad("a periodic D2Q7 lattice needs an even number of rows");
     if ((p->precision == LBM_FP16_OFFSET || p->precision == LBM_BF16_OFFSET) &&
         (!(p->rho_ref >= 0.0) || !std::isfinite(p->rho_ref)))
         return bad("rho_ref must be >= 0");
@@ -181,7 +192,8 @@ Layout make_layout(const lbm_params *p)
     int tws = (l64 % 256 == 0) ? 8 : ((l64 % 128 == 0) ? 7 : 6);
     l.lp = (int64_t)align_up((size_t)p->L, (size_t)1 << tws);
     l.tl.tws = tws;
-    l.tl.rs = 9 * l.lp;
+    l.tl.nq = lattice_q(p);
+    l.tl.rs = (int64_t)l.tl.nq * l.lp;
     l.nelem = (size_t)l.tl.rs * (size_t)p->H;
     l.fbytes = align_up(l.nelem * l.esize, kAlign);
     // vector kernel when the columns split evenly into lanes; bytes per lane
@@ -192,6 +204,7 @@ Layout make_layout(const lbm_params *p)
     int ty_pref = l.esize == 2 ? (p->growth >= LBM_GROWTH_DIVISION ? 4 : 2) : 1;
     bool scalar = false;
     if (p->kernel_vb == 1) scalar = true;                 // one column per lane
+    if (p->lattice == LBM_LATTICE_D2Q7) scalar = true;    // (D2Q7's only form)
     else if (p->kernel_vb == 2) l.staged = true;          // rows staged through LDS
     else if (p->kernel_vb > 1) l.vb = p->kernel_vb;       // 4, 8 or 16 bytes per lane
     // the staged form moves 16-bit populations in pairs of columns
@@ -211,7 +224,11 @@ Layout make_layout(const lbm_params *p)
     l.nt = lanes <= 64 ? 64 : (lanes <= 128 ? 128 : 256);
     if (l.staged) l.nt = 64 * StagedGeom((int)l.esize).waves();
     l.gx = (lanes + l.nt - 1) / l.nt;
-    l.ty = pick_ty(l.gx, p->H, l.vec || p->kernel_ty > 0 ? ty_pref : 2, p->kernel_ty > 0);
+    // D2Q7 (one column per lane), measured best at 4096 x 4096: float64 1 row,
+    // float32 2 rows, 16-bit 4 rows per thread
+    if (p->lattice == LBM_LATTICE_D2Q7 && p->kernel_ty <= 0) ty_pref = l.esize == 8 ? 1 : (l.esize == 4 ? 2 : 4);
+    const bool pref_rows = l.vec || p->kernel_ty > 0 || p->lattice == LBM_LATTICE_D2Q7;
+    l.ty = pick_ty(l.gx, p->H, pref_rows ? ty_pref : 2, p->kernel_ty > 0);
     l.gy = (p->H + l.ty - 1) / l.ty;
     l.rb = 2;
     l.nblocks = l.gx * l.gy;
@@ -316,6 +333,7 @@ int do_init(lbm_handle *h)
         a.w[i] = kW[i];
         a.Wd[i] = (R)h->Wd[i];
     }
+    for (int i = 0; i < 9; ++i) a.w[i] = lattice_w(&p)[i];
     if ((rc = h->hip(launch_init<S>(a, dim3(l.gx, l.gy), l.nt, s), "init kernel"))) return rc;
     h->cur = 0;
     h->t = 0;
@@ -354,7 +372,7 @@ void fill_step_args(const lbm_handle *h, StepArgs<S> &a)
     a.rho_cell = p.rho_cell;
     a.rho0 = p.rho0;
     for (int i = 0; i < 9; ++i) {
-        a.w[i] = (R)kW[i];
+        a.w[i] = (R)lattice_w(&p)[i];
         a.Wd[i] = (R)h->Wd[i];
     }
 }
@@ -397,9 +415,10 @@ int do_step(lbm_handle *h, int64_t n)
         a.h_next = h->hslot(h->t + 1);
         a.h_clear = h->device_driven ? nullptr : h->hslot(h->t + 2);
         a.t = (uint32_t)h->t;
-        int rc = h->hip(l.staged ? launch_step_staged<S>(a, grid, h->stream)
-                        : l.vec  ? launch_step_vec<S>(a, grid, l.nt, l.vb, h->stream)
-                                 : launch_step<S>(a, grid, l.nt, l.rb, h->stream),
+        int rc = h->hip(l.tl.nq == 7 ? launch_step7<S>(a, grid, l.nt, l.rb, h->stream)
+                        : l.staged ? launch_step_staged<S>(a, grid, h->stream)
+                        : l.vec    ? launch_step_vec<S>(a, grid, l.nt, l.vb, h->stream)
+                                   : launch_step<S>(a, grid, l.nt, l.rb, h->stream),
                         "step kernel");
         if (rc) return rc;
         if (h->device_driven) {
@@ -574,7 +593,7 @@ int lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *hip_str
     h->device_driven = p->ybc == LBM_Y_WALL_FOLLOW || (p->flags & LBM_FLAG_WINDOW) ||
                        p->growth >= LBM_GROWTH_DIVISION;
     h->mode = p->ybc == LBM_Y_PERIODIC ? kModePeriodic : (h->device_driven ? kModeDevice : kModeFixed);
-    for (int i = 0; i < 9; ++i) h->Wd[i] = offset_base(p->precision, i, p->rho_ref);
+    for (int i = 0; i < 9; ++i) h->Wd[i] = offset_base(p->precision, lattice_w(p)[i], p->rho_ref);
     int rc = LBM_DISPATCH(p->precision, do_init, h);
     if (rc == LBM_OK && h->device_driven) {
         // rows the first step must sweep: the initial front (at most
@@ -675,7 +694,7 @@ int lbm_get_populations(lbm_handle *h, double *host_f)
     DevState st{};
     if ((rc = read_state(h, &st))) return rc;
     const bool ring = h->mode == kModeDevice;
-    for (int q = 0; q < 9; ++q)
+    for (int q = 0; q < l.tl.nq; ++q)
         for (int j = 0; j < p.H; ++j) {
             const int64_t y = st.y_wall + j;
             const bool valid = h->mode == kModePeriodic || y < st.y_valid_top;
@@ -701,7 +720,7 @@ int lbm_set_populations(lbm_handle *h, const double *host_f)
     if ((rc = read_state(h, &st))) return rc;
     std::vector<char> raw(l.nelem * l.esize, 0);
     const bool ring = h->mode == kModeDevice;
-    for (int q = 0; q < 9; ++q)
+    for (int q = 0; q < l.tl.nq; ++q)
         for (int j = 0; j < p.H; ++j) {
             const int64_t y = st.y_wall + j;
             const int64_t r = ring ? (y % p.H) : j;
@@ -1079,6 +1098,7 @@ int lbm_batch_add(lbm_batch *b, lbm_handle *h)
 {
     if (!b || !h || h->batch || h->stream != b->stream) return LBM_E_INVALID;
     if ((int)b->members.size() >= b->max_members) return LBM_E_INVALID;
+    if (h->p.lattice != LBM_LATTICE_D2Q9) return LBM_E_UNSUPPORTED;   // batches run D2Q9
     b->members.push_back(h);
     h->batch = b;
     h->rep_ok = false;

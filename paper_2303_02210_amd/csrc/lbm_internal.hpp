@@ -39,16 +39,18 @@ enum : int { kRegionAll = 0, kRegionFrontBand = 1, kRegionRearBand = 2 };
 enum : uint32_t { kStDomainFull = 1u, kStNonFinite = 2u };
 
 // Population layout.  Each row holds the padded width Lp = n_tiles * TW
-// columns as n_tiles consecutive tiles; a tile stores the 9 directions of TW
-// consecutive columns one after the other ([tile][direction][column in tile]).
-// A wavefront's reads of one row are then a few contiguous runs instead of
-// nine streams far apart.  TW is a power of two (64, 128 or 256 columns).
+// columns as n_tiles consecutive tiles; a tile stores the nq directions (9 on
+// D2Q9, 7 on D2Q7) of TW consecutive columns one after the other
+// ([tile][direction][column in tile]).  A wavefront's reads of one row are
+// then a few contiguous runs instead of nq streams far apart.  TW is a power
+// of two (64, 128 or 256 columns).
 struct Tiles {
-    int64_t rs;    // elements per row: 9 * Lp
+    int64_t rs;    // elements per row: nq * Lp
     int32_t tws;   // log2(TW)
+    int32_t nq;    // populations per site
     __host__ __device__ int64_t col(int x) const
     {
-        return ((int64_t)(x >> tws) * 9 << tws) + (x & ((1 << tws) - 1));
+        return ((int64_t)(x >> tws) * nq << tws) + (x & ((1 << tws) - 1));
     }
     __host__ __device__ int64_t at(int q, int64_t r, int x) const
     {
@@ -232,6 +234,9 @@ __host__ __device__ inline TileRef run_ref(int rep, int64_t l, int64_t strips, i
 
 template <class S>
 hipError_t launch_step(const StepArgs<S> &a, dim3 grid, int nt, int rb, hipStream_t s);
+// The step on the D2Q7 lattice (one column per lane, rb rows' loads at once).
+template <class S>
+hipError_t launch_step7(const StepArgs<S> &a, dim3 grid, int nt, int rb, hipStream_t s);
 // A batch group: n members with the same storage type and kernel form (div:
 // the members grow by the division laws).
 // reps: device array of member descriptors; table: the group's tiles;

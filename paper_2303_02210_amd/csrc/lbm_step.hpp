@@ -80,6 +80,17 @@ __device__ __forceinline__ R sum9(const R v[9])
     return s;
 }
 
+// The first q of nine values summed in index order (q = 9 on D2Q9, 7 on D2Q7).
+template <class R>
+__device__ __forceinline__ R sumq(const R v[9], int q)
+{
+    R s = v[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+        if (i < q) s = s + v[i];
+    return s;
+}
+
 // Barrier for LDS traffic only: waits for this wave's LDS operations, not
 // for its global stores (__syncthreads would also wait for every store in
 // flight, which a tile that goes on to other work must not do).
@@ -1499,12 +1510,13 @@ __global__ __launch_bounds__(NT) void init_kernel(InitArgs<S> a)
             R kept[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
+                if (i >= a.tl.nq) break;
                 const R f = (R)(a.w[i] * rho);
                 const S s = Codec<S>::enc(f, a.Wd[i]);
                 a.f[a.tl.at(i, j, x)] = s;
                 kept[i] = Codec<S>::dec(s, a.Wd[i]);
             }
-            const R r = sum9(kept);
+            const R r = sumq(kept, a.tl.nq);
             m_acc += (double)r;
             if (r >= (R)a.rho_c) ymax = j;
         }
@@ -1545,8 +1557,8 @@ __global__ __launch_bounds__(NT) void mass_kernel(MassArgs<S> a)
             R v[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                v[i] = Codec<S>::dec(a.f[a.tl.at(i, r, x)], a.Wd[i]);
-            const R rho = sum9(v);
+                if (i < a.tl.nq) v[i] = Codec<S>::dec(a.f[a.tl.at(i, r, x)], a.Wd[i]);
+            const R rho = sumq(v, a.tl.nq);
             m_acc += (double)rho;
             if (a.growth >= kGrowthDivision) {
                 // the division laws' tallies of a state given as populations:
@@ -1705,8 +1717,8 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs<S> &a)
             R v[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i)
-                v[i] = Codec<S>::dec(a.f[a.tl.at(i, r, x)], a.Wd[i]);
-            const R m = sum9(v);
+                if (i < a.tl.nq) v[i] = Codec<S>::dec(a.f[a.tl.at(i, r, x)], a.Wd[i]);
+            const R m = sumq(v, a.tl.nq);
             gone[0] += (double)m;
             gone_fx[0] += mass_fx((double)m);
         }
@@ -1894,6 +1906,12 @@ __global__ void batch_advance(BatchRep<S> *const *reps, int n, int K)
         R->cur0 = (R->cur0 + K) & 1;
     }
 }
+
+}  // namespace lbm
+
+#include "lbm_d2q7.hpp"
+
+namespace lbm {
 
 // ---------------------------------------------------------------------------
 // Launchers (host side)

@@ -18,7 +18,8 @@ def _torch():
 
 
 class Sim:
-    """A growing-tissue D2Q9 simulation resident on one GPU.
+    """A growing-tissue simulation (D2Q9, or the paper's D2Q7 lattice)
+    resident on one GPU.
 
     ``cfg`` is a workload dict (keys of ``lbm_params``; see ``synth_inputs``).
     """
@@ -30,6 +31,7 @@ class Sim:
         self.cfg = dict(cfg)
         self.L = int(cfg["L"])
         self.H = int(cfg["H"])
+        self.Q = _ffi.Q[cfg.get("lattice", "d2q9")]
         self.device = torch.device(device)
         self._lib = _ffi.lib()
         self._p = _ffi.make_params(cfg)
@@ -95,14 +97,14 @@ class Sim:
 
     # -- state access ----------------------------------------------------
     def populations(self) -> np.ndarray:
-        out = np.zeros((9, self.H, self.L), np.float64)
+        out = np.zeros((self.Q, self.H, self.L), np.float64)
         self._check(self._lib.lbm_get_populations(self._h, out.ctypes.data_as(ctypes.c_void_p)),
                     "lbm_get_populations")
         return out
 
     def set_populations(self, f) -> None:
         a = np.ascontiguousarray(f, dtype=np.float64)
-        assert a.shape == (9, self.H, self.L)
+        assert a.shape == (self.Q, self.H, self.L)
         self._check(self._lib.lbm_set_populations(self._h, a.ctypes.data_as(ctypes.c_void_p)),
                     "lbm_set_populations")
 

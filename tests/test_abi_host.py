@@ -84,6 +84,8 @@ def test_workspace_bytes_scales_with_precision():
     dict(init_amp=1.0), dict(region_width=-1), dict(precision="fp64", window=True, ybc="periodic"),
     dict(growth="division", rho_cell=0.0), dict(growth="division_density", rho_cell=float("inf")),
     dict(growth="division_density", rho0=0.5), dict(growth="division_density", rho0=0.4),
+    dict(lattice="d2q7", kernel_vb=4), dict(lattice="d2q7", kernel_vb=2),
+    dict(lattice="d2q7", ybc="periodic", H=63, init_rows=10),
 ])
 def test_invalid_parameters_rejected_on_host(bad):
     c = dict(si.SMALL_FP64)
@@ -93,6 +95,14 @@ def test_invalid_parameters_rejected_on_host(bad):
     h = ctypes.c_void_p()
     rc = _ffi.lib().lbm_create(ctypes.byref(p), ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(h))
     assert rc == _ffi.E_INVALID and not h.value
+
+
+def test_d2q7_workspace_holds_seven_populations():
+    base = dict(si.BULK_4096_FP32)
+    n9 = _ws(base)
+    n7 = _ws(dict(base, lattice="d2q7"))
+    pops = 2 * 4096 * 4096 * 4
+    assert n9 - n7 >= 2 * pops and n7 >= 7 * pops
 
 
 def test_abi_version_and_size_checked():
