@@ -104,7 +104,8 @@ def main():
                     help="ensemble/served: skip the one-run-at-a-time comparison")
     ap.add_argument("--out", default=None, help="precision: write the curves to this JSON file")
     ap.add_argument("--workload", default="bulk",
-                    choices=["bulk", "edge", "ensemble", "served", "precision", "appb"],
+                    choices=["bulk", "edge", "ensemble", "served", "precision", "appb", "scaling",
+                             "extremes", "dispersion"],
                     help="bulk: 4096 x 4096 bulk growth (default); edge: 2048 x 8192 growth "
                          "within 8 rows of the front; ensemble: 256 replicas of uneven size, "
                          "batched, against the same runs stepped one after another")
@@ -112,9 +113,12 @@ def main():
                     help="bulk / edge: the growth law (default: the workload's own, a "
                          "continuous source); division draws discrete cell divisions per site, "
                          "division_density accepts them with Eq. 5's density weight")
-    ap.add_argument("--lattice", default="d2q9", choices=["d2q9", "d2q7"],
-                    help="bulk / edge: the square D2Q9 lattice (default) or the paper's "
-                         "triangular D2Q7 lattice")
+    ap.add_argument("--lattice", default=None, choices=["d2q9", "d2q7"],
+                    help="the square D2Q9 lattice or the paper's triangular D2Q7 lattice "
+                         "(default: D2Q9 for bulk / edge, D2Q7 for the paper's experiments)")
+    ap.add_argument("--sigma", type=float, default=None,
+                    help="appb / scaling / extremes / dispersion: noise amplitude in units of "
+                         "rho_init (default: the paper's 0.01 on 0.1, i.e. 0.1)")
     ap.add_argument("--tuned", action="store_true", help="launch shapes from the autotuner cache")
     ap.add_argument("--shape", default=None, help="force a launch shape: kernel_vb,kernel_ty")
     args = ap.parse_args()
@@ -137,6 +141,10 @@ def main():
         return bench_precision(args)
     if args.workload == "appb":
         return bench_appb(args)
+    if args.workload in ("scaling", "extremes", "dispersion"):
+        return {"scaling": bench_scaling, "extremes": bench_extremes,
+                "dispersion": bench_dispersion}[args.workload](args)
+    args.lattice = args.lattice or "d2q9"
     base = si.BULK_4096_FP32 if args.workload == "bulk" else si.EDGE_2048x8192
     cfg = dict(base, precision=args.precision)
     if args.growth and args.growth != cfg["growth"]:
@@ -346,16 +354,19 @@ def bench_served(args):
     print(json.dumps(out), flush=True)
 
 
-def _curves(sims, steps, every, stream_sync):
+def _curves(sims, steps, every, stream_sync, times=None):
     """Advance sims together and record hbar(t), W(t) and mass every `every`
-    steps (sims: an Ensemble)."""
+    steps, or at the given increasing times (sims: an Ensemble)."""
     import numpy as np
     rec = {"t": [], "hbar": [], "W": [], "mass": [], "wmass": []}
+    marks = list(times) if times is not None else list(range(every, steps + every, every))
     done = 0
-    while done < steps:
-        n = min(every, steps - done)
-        sims.step(n)
-        done += n
+    for mark in marks:
+        mark = min(int(mark), steps)
+        if mark <= done:
+            continue
+        sims.step(mark - done)
+        done = mark
         stream_sync()
         ds = [m.diagnostics() for m in sims.members]
         rec["t"].append(done)
@@ -378,7 +389,9 @@ def bench_appb(args):
     from paper_2303_02210_amd import Ensemble
 
     nseed = 4
-    cfgs = si.appendix_b(nseed)
+    cfgs = si.appendix_b(nseed, lattice=args.lattice or "d2q7")
+    if args.sigma is not None:
+        cfgs = [dict(c, sigma=args.sigma) for c in cfgs]
     steps = args.steps
     every = max(100, steps // 200)
     log(f"appendix B: {len(cfgs)} runs of {cfgs[0]['L']}x{cfgs[0]['H']}, {steps} steps")
@@ -420,7 +433,8 @@ def bench_appb(args):
                        max(res["rear_band_30"]["W_final_mean"], 1e-12), 3),
         "unit": "ratio", "n_gpus": 1, "steps": steps, "warmup": 0,
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "appendix_b_640", "L": cfgs[0]["L"], "H": cfgs[0]["H"],
+        "config": {"workload": "appendix_b_640", "lattice": cfgs[0]["lattice"],
+                   "L": cfgs[0]["L"], "H": cfgs[0]["H"],
                    "seeds": nseed, "every": every,
                    "params": {k: cfgs[0][k] for k in ("tau", "mu", "rho_c", "rho_init", "init_amp",
                                                       "sigma", "growth_rate", "rho_cell", "rho0",
@@ -436,6 +450,192 @@ def bench_appb(args):
     out.pop("t")
     for r in out["regimes"].values():
         r.pop("W_mean"), r.pop("W_ci95"), r.pop("profile_seed0")
+    print(json.dumps(out), flush=True)
+
+
+def _paper_params(c):
+    return {k: c[k] for k in ("lattice", "tau", "mu", "rho_c", "rho_init", "init_amp", "sigma",
+                              "growth", "growth_rate", "rho_cell", "rho0", "wall_min_gap",
+                              "wall_w_factor", "H", "precision")}
+
+
+def bench_scaling(args):
+    """Fig. 2: w(L, t) of uniform divisions at L = 40, 80, 160, 320 (8 seeds
+    each, batched), the exponents beta, alpha and z fitted from the seed-mean
+    curves, and the spread of the collapse with the fitted and with the KPZ
+    exponents (1/2, 3/2)."""
+    import numpy as np
+    import synth_inputs as si
+    from paper_2303_02210_amd import Ensemble
+    from paper_2303_02210_amd import scaling as sc
+
+    nseed = 8
+    cfgs = si.scaling_runs(nseed=nseed, lattice=args.lattice or "d2q7")
+    if args.sigma is not None:
+        cfgs = [dict(c, sigma=args.sigma) for c in cfgs]
+    steps = args.steps
+    every = 0
+    # log-spaced samples, so that the early power law is resolved
+    times = np.unique(np.round(np.logspace(0, np.log10(steps), 300)).astype(int))
+    log(f"scaling: {len(cfgs)} runs, widths {si.SCALING_WIDTHS}, {steps} steps")
+    ens = Ensemble(cfgs)
+    t0 = time.perf_counter()
+    c = _curves(ens, steps, 0, ens.synchronize, times=times)
+    wall = time.perf_counter() - t0
+    dg = [m.diagnostics() for m in ens.members]
+    ens.close()
+    for m in ens.members:
+        m.close()
+    curves, per_L = {}, {}
+    for i, L in enumerate(si.SCALING_WIDTHS):
+        sl = slice(i * nseed, (i + 1) * nseed)
+        w = c["W"][:, sl]
+        curves[L] = (c["t"], w.mean(1))
+        per_L[L] = {"W_final_mean": float(w[-1].mean()),
+                    "fix_over_src": float(np.mean([d["fix_total"] / max(d["src_total"], 1e-30)
+                                                   for d in dg[sl]])),
+                    "window_mass_growth_max": float(np.max(c["wmass"][-1, sl] / c["wmass"][0, sl]))}
+    fit = sc.fit_exponents(curves)
+    _, spread_fit = sc.collapse(curves, fit["alpha"], fit["z"])
+    _, spread_kpz = sc.collapse(curves, 0.5, 1.5)
+    for L in si.SCALING_WIDTHS:
+        per_L[L].update({k: fit["sizes"][L][k] for k in ("w_inf", "w_inf_se", "beta", "t_inf")})
+    out = {"metric": "scaling_exponents", "value": round(fit["alpha"], 4), "unit": "alpha",
+           "n_gpus": 1, "steps": steps, "data": "synthetic",
+           "config": {"workload": "scaling_fig2", "widths": list(si.SCALING_WIDTHS),
+                      "seeds": nseed, "every": every, "params": _paper_params(cfgs[0])},
+           "alpha": fit["alpha"], "beta": fit["beta"], "z": fit["z"],
+           "alpha_over_beta": fit["alpha_over_beta"],
+           "collapse_spread_fitted": spread_fit, "collapse_spread_kpz": spread_kpz,
+           "sizes": {str(L): v for L, v in per_L.items()}, "wall_s": round(wall, 2)}
+    log(f"alpha {fit['alpha']:.3f} beta {fit['beta']:.3f} z {fit['z']:.3f}; collapse spread "
+        f"fitted {spread_fit:.3f}, KPZ {spread_kpz:.3f}")
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump(dict(out, t=c["t"].tolist(),
+                           W={str(L): np.asarray(curves[L][1]).tolist() for L in curves}), fh)
+    print(json.dumps(out), flush=True)
+
+
+def bench_extremes(args):
+    """Fig. 3c: under Eq. 5, the divisions in the 21 x 20 rectangles below
+    h_max and below h_min, their difference sampled every interval (the map
+    cleared each time) after a warm-up, at L = 40 (16 seeds) and L = 640
+    (4 seeds)."""
+    import numpy as np
+    import synth_inputs as si
+    from paper_2303_02210_amd import Ensemble
+    from paper_2303_02210_amd import scaling as sc
+
+    cfgs = si.extremes_runs(lattice=args.lattice or "d2q7")
+    if args.sigma is not None:
+        cfgs = [dict(c, sigma=args.sigma) for c in cfgs]
+    steps = args.steps
+    warm = steps // 5
+    every = max(100, steps // 200)
+    log(f"extremes: {len(cfgs)} runs, {steps} steps (warm-up {warm}, every {every})")
+    ens = Ensemble(cfgs)
+    ens.step(warm)
+    ens.synchronize()
+    for m in ens.members:
+        m.division_map(clear=True)
+    diffs = {40: [], 640: []}
+    done = warm
+    t0 = time.perf_counter()
+    while done < steps:
+        ens.step(every)
+        done += every
+        ens.synchronize()
+        for c, m in zip(cfgs, ens.members):
+            dmap = m.division_map(clear=True)
+            h = m.front_heights()
+            diffs[c["L"]].append(sc.division_difference(dmap, h, m.diagnostics()["y_wall"]))
+    wall = time.perf_counter() - t0
+    W = {L: float(np.mean([m.diagnostics()["W"] for c, m in zip(cfgs, ens.members)
+                           if c["L"] == L])) for L in diffs}
+    ens.close()
+    for m in ens.members:
+        m.close()
+    res = {}
+    for L, d in diffs.items():
+        d = np.asarray(d, float)
+        hist, edges = np.histogram(d, bins=21)
+        res[str(L)] = {"samples": int(d.size), "mean": float(d.mean()), "std": float(d.std()),
+                       "se": float(d.std() / np.sqrt(d.size)),
+                       "frac_positive": float((d > 0).mean()), "W_final_mean": W[L],
+                       "hist": hist.tolist(), "edges": np.round(edges, 2).tolist()}
+        log(f"L={L}: mean difference {d.mean():.2f} +- {d.std() / np.sqrt(d.size):.2f} "
+            f"(positive {100 * (d > 0).mean():.0f}%), W {W[L]:.2f}")
+    out = {"metric": "extremes_division_difference", "value": res["640"]["mean"],
+           "unit": "divisions", "n_gpus": 1, "steps": steps, "data": "synthetic",
+           "config": {"workload": "extremes_fig3c", "widths": [40, 640], "warmup": warm,
+                      "every": every, "params": _paper_params(cfgs[0])},
+           "sizes": res, "wall_s": round(wall, 2)}
+    print(json.dumps(out), flush=True)
+
+
+def bench_dispersion(args):
+    """Eq. 7: flat fronts perturbed by one cosine mode (amplitude 8 rows, modes
+    n = 1..8 of L = 640, 6 seeds each) under Eq. 5; the growth rate omega(q)
+    of each mode's amplitude over the run and the fit omega = k - gamma q^2."""
+    import numpy as np
+    import synth_inputs as si
+    from paper_2303_02210_amd import Ensemble
+    from paper_2303_02210_amd import scaling as sc
+
+    cfgs = si.dispersion_runs(lattice=args.lattice or "d2q7")
+    if args.sigma is not None:
+        cfgs = [dict(c, sigma=args.sigma) for c in cfgs]
+    steps = args.steps
+    every = max(20, steps // 100)
+    h0 = 150.0
+    log(f"dispersion: {len(cfgs)} runs, modes {si.DISPERSION_MODES}, {steps} steps")
+    ens = Ensemble(cfgs)
+    for c, m in zip(cfgs, ens.members):
+        L, H = c["L"], c["H"]
+        x = np.arange(L)
+        h = np.floor(h0 + c["amplitude"] * np.cos(2 * np.pi * c["mode"] * x / L) + 0.5).astype(np.int32)
+        Q = m.Q
+        w = np.array([0.5] + [1 / 12] * 6) if Q == 7 else \
+            np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+        f = np.zeros((Q, H, L))
+        rows = np.arange(H)[:, None]
+        f[:, :, :] = w[:, None, None] * (rows < h[None, :]) * c["rho_init"]
+        m.set_populations(f)
+        m.set_front_heights(h)
+    amps = {c["name"]: [] for c in cfgs}
+    ts = []
+    done = 0
+    t0 = time.perf_counter()
+    while done < steps:
+        ens.step(every)
+        done += every
+        ens.synchronize()
+        ts.append(done)
+        for c, m in zip(cfgs, ens.members):
+            amps[c["name"]].append(sc.mode_amplitude(m.front_heights(), c["mode"]))
+    wall = time.perf_counter() - t0
+    ens.close()
+    for m in ens.members:
+        m.close()
+    L = cfgs[0]["L"]
+    q, om, om_se = [], [], []
+    per = {}
+    for n in si.DISPERSION_MODES:
+        rates = [sc.growth_rate(ts, amps[c["name"]]) for c in cfgs if c["mode"] == n]
+        q.append(2 * np.pi * n / L)
+        om.append(float(np.mean(rates)))
+        om_se.append(float(np.std(rates, ddof=1) / np.sqrt(len(rates))))
+        per[str(n)] = {"q": q[-1], "omega": om[-1], "omega_se": om_se[-1]}
+    fit = sc.fit_dispersion(q, om)
+    log(f"omega(q): {np.round(om, 6).tolist()}; k {fit['k']:.3g} gamma {fit['gamma']:.3g}")
+    out = {"metric": "dispersion_fit", "value": fit["k"], "unit": "per step", "n_gpus": 1,
+           "steps": steps, "data": "synthetic",
+           "config": {"workload": "dispersion_eq7", "L": L, "modes": list(si.DISPERSION_MODES),
+                      "amplitude": cfgs[0]["amplitude"], "h0": h0, "every": every,
+                      "params": _paper_params(cfgs[0])},
+           "modes": per, "k": fit["k"], "gamma": fit["gamma"], "q_c": fit["q_c"],
+           "L_c": fit["L_c"], "wall_s": round(wall, 2)}
     print(json.dumps(out), flush=True)
 
 

@@ -104,6 +104,8 @@ typedef enum {
 } lbm_lattice;
 
 /* lbm_params.flags */
+#define LBM_FLAG_DIVISION_MAP 2u   /* keep a per-site count of the divisions
+                                      (read with lbm_division_map)            */
 #define LBM_FLAG_WINDOW 1u   /* sweep only rows that can hold mass: rows at or
                                 below the highest front seen plus one (the rest
                                 are exactly zero); results are unchanged      */
@@ -114,8 +116,7 @@ typedef enum {
  *   L, H          columns (periodic) and rows of the live window; L >= 2,
  *                 H >= 4, L * H * Q populations must fit the workspace.
  *   lattice       lbm_lattice.  D2Q7 runs the one-column-per-lane form
- *                 (kernel_vb 0 or 1), needs an even H when periodic, and is
- *                 not accepted by batches (LBM_E_UNSUPPORTED).
+ *                 (kernel_vb 0 or 1) and needs an even H when periodic.
  *   precision     lbm_precision.
  *   tau           relaxation time of Eq. 2, tau > 1/2.
  *   mu            friction: the steady state uses u* = (1 - mu) u (below
@@ -250,6 +251,13 @@ int lbm_set_populations(lbm_handle *h, const double *host_f);
  * Synchronizes. */
 int lbm_set_front_heights(lbm_handle *h, const int32_t *host_h);
 
+/* Divisions per site of the live window since creation or the last clear
+ * (Sec. IV: the proliferation counts near h_max and h_min), [H][L] int32,
+ * row j = absolute row y_wall + j; rows the rear wall retires leave the
+ * map.  clear != 0 zeroes it afterwards.  Needs LBM_FLAG_DIVISION_MAP
+ * (LBM_E_INVALID otherwise).  Not part of checkpoints.  Synchronizes. */
+int lbm_division_map(lbm_handle *h, int32_t *host_counts, int clear);
+
 /* Checkpoint: size of the host blob, save, and restore into a handle created
  * with the same parameters.  A restored run continues bit for bit like the
  * uninterrupted one (all draws are keyed by step and site).  Synchronize. */
@@ -281,8 +289,7 @@ int lbm_destroy(lbm_handle *h);
  *                        members must use the same stream.
  *   lbm_batch_add/remove membership changes (take effect at the next step);
  *                        a handle belongs to at most one batch, and
- *                        lbm_destroy removes it from its batch; D2Q7 handles
- *                        are refused with LBM_E_UNSUPPORTED.
+ *                        lbm_destroy removes it from its batch.
  *   lbm_batch_step       nsteps >= 0 steps of every member; does not
  *                        synchronize; LBM_E_STATE if a member is in an error
  *                        state (remove it and step again).

@@ -254,6 +254,7 @@ struct orc_state {
     uint32_t   status;
     double     lam;        /* division laws: lam of the next step              */
     int64_t    divisions;  /* cumulative divisions                             */
+    int32_t   *divmap;     /* [H][L] divisions per window site since cleared   */
 };
 
 static size_t idx(const orc_params *p, int i, int32_t j, int32_t x)
@@ -765,7 +766,8 @@ orc_state *orc_create(const orc_params *p)
     s->f = (double *)calloc(n, sizeof(double));
     s->fn = (double *)calloc(n, sizeof(double));
     s->h = (int32_t *)calloc((size_t)p->L, sizeof(int32_t));
-    if (!s->f || !s->fn || !s->h) { orc_destroy(s); return NULL; }
+    s->divmap = (int32_t *)calloc((size_t)p->L * (size_t)p->H, sizeof(int32_t));
+    if (!s->f || !s->fn || !s->h || !s->divmap) { orc_destroy(s); return NULL; }
 
     /* Appendix A initialisation: u = 0, rho uniform around rho_init in the
      * first init_rows rows, f_i = f_i^SS(rho, 0); empty above */
@@ -803,6 +805,7 @@ void orc_destroy(orc_state *s)
     free(s->f);
     free(s->fn);
     free(s->h);
+    free(s->divmap);
     free(s);
 }
 
@@ -831,6 +834,12 @@ static void advance_wall(orc_state *s)
                 int32_t src = j + (int32_t)k;
                 s->f[idx(p, i, j, x)] = (src < p->H) ? s->f[idx(p, i, src, x)] : 0.0;
             }
+    /* the division map moves with the window */
+    for (int32_t j = 0; j < p->H; ++j)
+        for (int32_t x = 0; x < p->L; ++x) {
+            int32_t src = j + (int32_t)k;
+            s->divmap[(size_t)j * p->L + x] = (src < p->H) ? s->divmap[(size_t)src * p->L + x] : 0;
+        }
     s->y_wall += k;
     s->retired += gone;
     s->mass = s->mass - gone;
@@ -861,6 +870,7 @@ int orc_step(orc_state *s, int64_t nsteps)
                 src += S;
                 fix += dfix;
                 s->divisions += ndiv;
+                s->divmap[(size_t)j * p->L + x] += ndiv;
                 wsum += wfx;
                 if (tissue && y_abs + 1 > h_new[x]) h_new[x] = (int32_t)(y_abs + 1);
             }
@@ -934,4 +944,14 @@ void orc_set_step(orc_state *s, int64_t t)
 void orc_set_lam(orc_state *s, double lam)
 {
     s->lam = lam;
+}
+
+void orc_division_map(const orc_state *s, int32_t *out)
+{
+    memcpy(out, s->divmap, (size_t)s->p.L * (size_t)s->p.H * sizeof(int32_t));
+}
+
+void orc_clear_division_map(orc_state *s)
+{
+    memset(s->divmap, 0, (size_t)s->p.L * (size_t)s->p.H * sizeof(int32_t));
 }

@@ -160,6 +160,10 @@ void       orc_set_step(orc_state *s, int64_t t);
 /* division laws: set lam of the next step (it otherwise comes from the
  * previous step, or from the state's own densities after a set) */
 void       orc_set_lam(orc_state *s, double lam);
+/* Divisions per site of the window ([H][L], row j = absolute row y_wall + j)
+ * since creation or the last clear; rows the wall retires leave the map. */
+void       orc_division_map(const orc_state *s, int32_t *out);
+void       orc_clear_division_map(orc_state *s);
 
 #ifdef __cplusplus
 }

@@ -122,6 +122,8 @@ def lib():
         L.orc_set_front_heights.argtypes = [ctypes.c_void_p, i32p]
         L.orc_set_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
         L.orc_set_lam.argtypes = [ctypes.c_void_p, ctypes.c_double]
+        L.orc_division_map.argtypes = [ctypes.c_void_p, i32p]
+        L.orc_clear_division_map.argtypes = [ctypes.c_void_p]
     return _lib
 
 
@@ -316,3 +318,10 @@ class Oracle:
 
     def set_lam(self, lam: float) -> None:
         lib().orc_set_lam(self._h, float(lam))
+
+    def division_map(self, clear: bool = False) -> np.ndarray:
+        out = np.zeros((self.H, self.L), np.int32)
+        lib().orc_division_map(self._h, _ptr(out, ctypes.c_int32))
+        if clear:
+            lib().orc_clear_division_map(self._h)
+        return out

@@ -29,6 +29,7 @@ GROWTH = {"none": 0, "bulk": 1, "division": 2, "division_density": 3}
 REGION = {"all": 0, "front_band": 1, "rear_band": 2}
 YBC = {"fixed": 0, "follow": 1, "periodic": 2}
 FLAG_WINDOW = 1
+FLAG_DIVISION_MAP = 2
 ST_DOMAIN_FULL = 1
 ST_NONFINITE = 2
 
@@ -78,6 +79,7 @@ _SIGS = [
     ("lbm_get_populations", ctypes.c_int, [_VP, _VP]),
     ("lbm_set_populations", ctypes.c_int, [_VP, _VP]),
     ("lbm_set_front_heights", ctypes.c_int, [_VP, _VP]),
+    ("lbm_division_map", ctypes.c_int, [_VP, _VP, ctypes.c_int]),
     ("lbm_state_bytes", ctypes.c_size_t, [_VP]),
     ("lbm_get_state", ctypes.c_int, [_VP, _VP, ctypes.c_size_t]),
     ("lbm_set_state", ctypes.c_int, [_VP, _VP, ctypes.c_size_t]),
@@ -139,7 +141,8 @@ def make_params(cfg: dict) -> Params:
     p.rho_ref = float(cfg.get("rho_ref", cfg.get("rho_init", 1.0)))
     p.seed = int(cfg.get("seed", 0)) & 0xFFFFFFFF
     p.replica = int(cfg.get("replica", 0)) & 0xFFFFFFFF
-    p.flags = FLAG_WINDOW if cfg.get("window", False) else 0
+    p.flags = (FLAG_WINDOW if cfg.get("window", False) else 0) | \
+        (FLAG_DIVISION_MAP if cfg.get("division_map", False) else 0)
     p.kernel_vb = int(cfg.get("kernel_vb", 0))
     p.kernel_ty = int(cfg.get("kernel_ty", 0))
     p.rho_cell = float(cfg.get("rho_cell", 0.1))

@@ -117,6 +117,7 @@ struct Layout {
     size_t off_f[2] = {0, 0};
     size_t off_h[3] = {0, 0, 0};
     size_t off_colmax = 0, off_partials = 0, off_state = 0, off_diag = 0, off_rep = 0;
+    size_t off_divmap = 0;   // [H][L] int32 per-site divisions (0: not kept)
     size_t total = 0;
     int nt = 256, ty = 16, gx = 1, gy = 1, nblocks = 1, rb = 2;
     bool vec = false;   // vector kernel: vb bytes (cpt columns) per thread
@@ -155,7 +156,7 @@ bool params_ok(const lbm_params *p, std::string *why)
     if (p->ybc < LBM_Y_WALL_FIXED || p->ybc > LBM_Y_PERIODIC) return bad("bad ybc");
     if (p->ybc == LBM_Y_WALL_FOLLOW && (p->wall_min_gap < 0 || !(p->wall_w_factor >= 0.0)))
         return bad("bad wall follow parameters");
-    if ((p->flags & ~LBM_FLAG_WINDOW) != 0) return bad("unknown flags");
+    if ((p->flags & ~(LBM_FLAG_WINDOW | LBM_FLAG_DIVISION_MAP)) != 0) return bad("unknown flags");
     if (!(p->kernel_vb == 0 || p->kernel_vb == 1 || p->kernel_vb == 2 || p->kernel_vb == 4 ||
           p->kernel_vb == 8 || p->kernel_vb == 16))
         return bad("kernel_vb must be 0, 1, 2, 4, 8 or 16");
@@ -242,6 +243,10 @@ Layout make_layout(const lbm_params *p)
     l.off_state = o; o += align_up(sizeof(DevState), kAlign);
     l.off_diag = o; o += align_up(sizeof(DiagOut), kAlign);
     l.off_rep = o; o += align_up(sizeof(BatchRep<double>), kAlign);
+    if (p->flags & LBM_FLAG_DIVISION_MAP) {
+        l.off_divmap = o;
+        o += align_up((size_t)p->L * (size_t)p->H * 4, kAlign);
+    }
     l.total = o;
     return l;
 }
@@ -274,6 +279,7 @@ struct lbm_handle {
     double *partials() const { return at<double>(lay.off_partials); }
     DevState *st() const { return at<DevState>(lay.off_state); }
     DiagOut *diag() const { return at<DiagOut>(lay.off_diag); }
+    int32_t *divmap() const { return lay.off_divmap ? at<int32_t>(lay.off_divmap) : nullptr; }
 
     int fail(int code, const std::string &m)
     {
@@ -305,6 +311,9 @@ int do_init(lbm_handle *h)
                      "fill")))
         return rc;
     if ((rc = h->hip(launch_fill_f64(h->partials(), (int64_t)l.nblocks * kPartialSlots, 0.0, s), "fill")))
+        return rc;
+    if (h->divmap() &&
+        (rc = h->hip(launch_fill_i32(h->divmap(), (int64_t)p.L * p.H, 0, s), "fill")))
         return rc;
     // the device state, division tallies and counts included
     if ((rc = h->hip(launch_fill_i32(reinterpret_cast<int32_t *>(h->st()),
@@ -350,6 +359,7 @@ void fill_step_args(const lbm_handle *h, StepArgs<S> &a)
     const Layout &l = h->lay;
     a = StepArgs<S>{};
     a.partials = h->partials();
+    a.divmap = h->divmap();
     a.colmax = h->colmax();
     a.st = h->st();
     a.L = p.L;
@@ -384,6 +394,7 @@ void fill_finalize_args(const lbm_handle *h, FinalizeArgs<S> &fa)
     const lbm_params &p = h->p;
     fa = FinalizeArgs<S>{};
     fa.st = h->st();
+    fa.divmap = h->divmap();
     fa.colmax = h->colmax();
     fa.L = p.L;
     fa.H = p.H;
@@ -757,6 +768,31 @@ int lbm_set_front_heights(lbm_handle *h, const int32_t *host_h)
     return h->hip(hipStreamSynchronize(h->stream), "synchronize");
 }
 
+int lbm_division_map(lbm_handle *h, int32_t *host_counts, int clear)
+{
+    int rc = usable(h);
+    if (rc) return rc;
+    if (!host_counts || !h->divmap()) return LBM_E_INVALID;
+    const lbm_params &p = h->p;
+    std::vector<int32_t> raw((size_t)p.L * p.H);
+    rc = h->hip(hipMemcpyAsync(raw.data(), h->divmap(), raw.size() * 4, hipMemcpyDeviceToHost,
+                               h->stream),
+                "division map copy");
+    if (rc) return rc;
+    if (clear && (rc = h->hip(launch_fill_i32(h->divmap(), (int64_t)p.L * p.H, 0, h->stream),
+                              "fill")))
+        return rc;
+    DevState st{};
+    if ((rc = read_state(h, &st))) return rc;   // (synchronizes the stream)
+    // window row j holds absolute row y_wall + j at physical row (y_wall + j) mod H
+    const bool ring = h->mode == kModeDevice;
+    for (int j = 0; j < p.H; ++j) {
+        const int64_t r = ring ? (st.y_wall + j) % p.H : j;
+        std::memcpy(host_counts + (size_t)j * p.L, raw.data() + (size_t)r * p.L, (size_t)p.L * 4);
+    }
+    return LBM_OK;
+}
+
 size_t lbm_state_bytes(const lbm_handle *h)
 {
     if (!h) return 0;
@@ -864,7 +900,8 @@ constexpr int kMaxGroups = 16;
 constexpr int kWindowGrid = 8192;   // blocks of a windowed group's launch
 
 struct BatchGroup {
-    int prec = 0, vec = 0, nt = 0, vbrb = 0, ty = 0, windowed = 0, div = 0;   // kernel form
+    // kernel form; form: 0 one column per lane, 1 vector, 2 the D2Q7 step
+    int prec = 0, form = 0, nt = 0, vbrb = 0, ty = 0, windowed = 0, div = 0;
     std::vector<lbm_handle *> m;
     int64_t tiles = 0;                           // tiles over all members
     int grid = 0;                                // blocks per step launch
@@ -918,7 +955,7 @@ hipError_t enqueue_group_step(const BatchGroup &g, int k, hipStream_t s)
                                  g.table, g.count, s);
     if (e != hipSuccess) return e;
     return launch_step_batch<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps), g.table, g.count,
-                                g.grid, g.vec, g.nt, g.vbrb, g.div, k, s);
+                                g.grid, g.form, g.nt, g.vbrb, g.div, k, s);
 }
 template <class S>
 hipError_t enqueue_group_finalize(const BatchGroup &g, int k, hipStream_t s)
@@ -971,9 +1008,10 @@ struct lbm_batch {
             const int vbrb = h->lay.vec ? h->lay.vb : h->lay.rb;
             const int win = (h->p.flags & LBM_FLAG_WINDOW) ? 1 : 0;
             const int div = h->p.growth >= LBM_GROWTH_DIVISION ? 1 : 0;
+            const int form = h->lay.tl.nq == 7 ? 2 : (h->lay.vec ? 1 : 0);
             BatchGroup *g = nullptr;
             for (BatchGroup &c : groups)
-                if (c.prec == h->p.precision && c.vec == (int)h->lay.vec && c.nt == h->lay.nt &&
+                if (c.prec == h->p.precision && c.form == form && c.nt == h->lay.nt &&
                     c.vbrb == vbrb && c.ty == h->lay.ty && c.windowed == win && c.div == div)
                     g = &c;
             if (!g) {
@@ -981,7 +1019,7 @@ struct lbm_batch {
                 groups.emplace_back();
                 g = &groups.back();
                 g->prec = h->p.precision;
-                g->vec = h->lay.vec;
+                g->form = form;
                 g->nt = h->lay.nt;
                 g->vbrb = vbrb;
                 g->ty = h->lay.ty;
@@ -1098,7 +1136,6 @@ int lbm_batch_add(lbm_batch *b, lbm_handle *h)
 {
     if (!b || !h || h->batch || h->stream != b->stream) return LBM_E_INVALID;
     if ((int)b->members.size() >= b->max_members) return LBM_E_INVALID;
-    if (h->p.lattice != LBM_LATTICE_D2Q9) return LBM_E_UNSUPPORTED;   // batches run D2Q9
     b->members.push_back(h);
     h->batch = b;
     h->rep_ok = false;

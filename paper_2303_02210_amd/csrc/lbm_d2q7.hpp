@@ -306,6 +306,7 @@ __device__ __forceinline__ void step_tile7(const StepArgs<S> &a, const StepIO<S>
                 mfx_acc += mfx_site;
                 dv.w += dv_site.w;
                 dv.n += dv_site.n;
+                if constexpr (DIV) count_divisions(a, y, x, dv_site.n);
                 if (tissue) {
                     ymax = y;
                     if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
@@ -342,6 +343,24 @@ __global__ __launch_bounds__(NT) void step_kernel7(StepArgs<S> a)
     const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
     const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
     step_tile7<S, NT, RB, DIV>(a, io, lin % nbx, lin / nbx, nbx);
+}
+
+// Batches: as step_batch, with the D2Q7 tile body.
+template <class S, int NT, int RB, bool DIV>
+__global__ __launch_bounds__(NT) void step_batch7(BatchRep<S> *const *reps, const TileRef *table,
+                                                  const int32_t *count, int k)
+{
+    static_assert(sizeof(BatchRep<S>) % 4 == 0, "descriptor is staged as dwords");
+    __shared__ uint32_t stage[sizeof(BatchRep<S>) / 4];
+    const BatchRep<S> &R = *reinterpret_cast<const BatchRep<S> *>(stage);
+    const int total = *count;
+    for (int c = blockIdx.x; c < total; c += gridDim.x) {
+        const TileRef e = table[xcd_order(c, total, 2)];
+        stage_dwords<NT>(reps[e.rep], stage, (int)(sizeof(BatchRep<S>) / 4));
+        const StepIO<S> io = batch_io(&R, k);
+        const int bx = e.local0 % R.gx, by = e.local0 / R.gx;
+        step_tile7<S, NT, RB, DIV>(R.a, io, bx, by, R.gx, e.n);
+    }
 }
 
 template <class S, int RB, bool DIV>

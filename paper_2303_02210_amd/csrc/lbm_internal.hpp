@@ -111,6 +111,7 @@ struct StepArgs {
     int32_t *h_clear;       // slot to reset to the wall row (fixed modes), or null
     int32_t *colmax;        // per-column highest front
     double *partials;       // [nblocks][kPartialSlots]: mass, injected, fix, spare
+    int32_t *divmap;        // [H][L] divisions per site (physical rows), or null
     DevState *st;
     int32_t L, H, ty;
     Tiles tl;
@@ -169,6 +170,7 @@ struct FinalizeArgs {
     int32_t follow, window, min_gap;
     double w_factor;
     R Wd[9];
+    int32_t *divmap;        // per-site divisions: rows the wall retires are cleared
     // division laws: the rate of the next step from the step's tallies
     int32_t growth;
     double g, rho_cell;

@@ -185,6 +185,15 @@ __device__ __forceinline__ DivTally div_site(const DivTally &d)
     return s;
 }
 
+// The per-site division map (if kept): a site's divisions at its physical
+// row y mod H.  Each site is updated by one lane per step, so no atomics.
+template <class S>
+__device__ __forceinline__ void count_divisions(const StepArgs<S> &a, int64_t y, uint32_t x,
+                                                long long n)
+{
+    if (n > 0 && a.divmap) a.divmap[(y % a.H) * a.L + x] += (int32_t)n;
+}
+
 // Deterministic block sums of a tile's tallies (fixed tree), one LDS round:
 // the three masses end in thread 0; with the division laws, thread 0 also
 // adds the block's fixed-point mass, weight and divisions to one of the
@@ -609,6 +618,7 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
                 mfx_acc += mfx_site;
                 dv.w += dv_site.w;
                 dv.n += dv_site.n;
+                if constexpr (DIV) count_divisions(a, y, x, dv_site.n);
                 if (tissue) {
                     ymax = y;
                     if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
@@ -1047,6 +1057,7 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
                 mfx_acc += mfx_site;
                 dv.w += dv_site.w;
                 dv.n += dv_site.n;
+                if constexpr (DIV) count_divisions(a, y, x, dv_site.n);
                 if (tissue) {
                     tmask |= 1u << k;
                     if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
@@ -1418,6 +1429,7 @@ __device__ __forceinline__ void step_staged_tile(const StepArgs<S> &a, const Ste
                 mfx_acc += mfx_site;
                 dv.w += dv_site.w;
                 dv.n += dv_site.n;
+                if constexpr (DIV) count_divisions(a, y, (uint32_t)(c0 + i), dv_site.n);
                 if (tissue) {
                     jmax[v] = j;
                     if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
@@ -1724,6 +1736,10 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs<S> &a)
         }
         block_reduce(gone, shd);
         block_reduce(gone_fx, shi);
+        // the division map forgets the rows the wall leaves behind
+        if (a.divmap)
+            for (int64_t e = threadIdx.x; e < n; e += kRedThreads)
+                a.divmap[((y_wall + e / a.L) % a.H) * a.L + e % a.L] = 0;
     }
     // division laws: the next step's rate from this step's tallies, less the
     // rows the wall leaves behind
@@ -2008,7 +2024,12 @@ void launch_batch_div(BatchRep<S> *const *reps, const TileRef *table, const int3
                       int grid, int vec, int vb_or_rb, int k, hipStream_t s)
 {
     const dim3 g(grid), b(NT);
-    if (vec) {
+    if (vec == 2) {   // the D2Q7 step
+        if (vb_or_rb >= 2)
+            hipLaunchKernelGGL((step_batch7<S, NT, 2, DIV>), g, b, 0, s, reps, table, count, k);
+        else
+            hipLaunchKernelGGL((step_batch7<S, NT, 1, DIV>), g, b, 0, s, reps, table, count, k);
+    } else if (vec) {
         if (vb_or_rb == 4) {
             if constexpr (sizeof(S) <= 4)
                 hipLaunchKernelGGL((step_batch<S, NT, 1, true, DIV>), g, b, 0, s, reps, table, count, k);

@@ -108,6 +108,14 @@ class Sim:
         self._check(self._lib.lbm_set_populations(self._h, a.ctypes.data_as(ctypes.c_void_p)),
                     "lbm_set_populations")
 
+    def division_map(self, clear: bool = False) -> np.ndarray:
+        """Divisions per site of the window since creation or the last clear,
+        [H][L] (row j = absolute row y_wall + j); needs cfg["division_map"]."""
+        out = np.zeros((self.H, self.L), np.int32)
+        self._check(self._lib.lbm_division_map(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                               1 if clear else 0), "lbm_division_map")
+        return out
+
     def set_front_heights(self, h) -> None:
         a = np.ascontiguousarray(h, dtype=np.int32)
         assert a.shape == (self.L,)

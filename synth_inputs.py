@@ -117,26 +117,60 @@ def served_trace(n: int = 600, rate_hz: float = 20.0, seed: int = 0,
     return out
 
 
-# Appendix B: the density-dependent division law (Eq. 5) against divisions
-# held to a band of 30 rows above the rear wall, uniform within it, at
-# L = 640 with the paper's Appendix A parameters rescaled to rho_init = 1
-# (sigma 0.01 -> 0.1, rho_cell 0.01 -> 0.1, rho0 0.15 -> 1.5; initial density
-# uniform on [0.9, 1.1] rho_init), the rear wall kept max(50, 10 w) behind
-# the mean front, float32.  Height and initial tissue rows are this build's
-# choice: room for the wall gap and a front several w rough.
-APPB_BASE = dict(BASE, L=640, H=2048, init_rows=100, init_amp=0.1, sigma=0.1,
-                 growth_rate=1e-3, ybc="follow", wall_min_gap=50, wall_w_factor=10.0,
-                 window=True, precision="fp32")
+# The paper's runs (Sec. III, IV, Appendix A): its own D2Q7 lattice and the
+# Appendix A parameters rescaled to rho_init = 1 (sigma 0.01 -> 0.1,
+# rho_cell 0.01 -> 0.1, rho0 0.15 -> 1.5; initial density uniform on
+# [0.9, 1.1] rho_init), the rear wall kept max(50, 10 w) behind the mean
+# front, the sweep window on, float32.  Heights and initial tissue rows are
+# this build's choice: room for the wall gap and a front several w rough.
+PAPER_BASE = dict(BASE, lattice="d2q7", H=2048, init_rows=100, init_amp=0.1, sigma=0.1,
+                  growth="division", growth_rate=1e-3, ybc="follow", wall_min_gap=50,
+                  wall_w_factor=10.0, window=True, precision="fp32")
+APPB_BASE = dict(PAPER_BASE, L=640)
 
 
-def appendix_b(nseed: int = 4) -> list[dict]:
-    """nseed runs of each regime: density-dependent divisions everywhere,
-    then uniform divisions in the 30-row rear band."""
+def appendix_b(nseed: int = 4, lattice: str = "d2q7") -> list[dict]:
+    """Appendix B at L = 640: nseed runs of the density-dependent division law
+    (Eq. 5) everywhere, then nseed runs of uniform divisions held to the 30
+    rows above the rear wall."""
     runs = []
     for sd in range(nseed):
         runs.append(dict(APPB_BASE, name=f"appb_density_s{sd}", growth="division_density",
-                         seed=500 + sd, replica=sd))
+                         lattice=lattice, seed=500 + sd, replica=sd))
     for sd in range(nseed):
         runs.append(dict(APPB_BASE, name=f"appb_rearband_s{sd}", growth="division",
-                         region="rear_band", region_width=30, seed=600 + sd, replica=sd))
+                         region="rear_band", region_width=30, lattice=lattice, seed=600 + sd,
+                         replica=sd))
     return runs
+
+
+# Fig. 2: uniform divisions at several widths, for w(L, t) and its exponents.
+SCALING_WIDTHS = (40, 80, 160, 320)
+
+
+def scaling_runs(widths=SCALING_WIDTHS, nseed: int = 8, lattice: str = "d2q7",
+                 growth: str = "division") -> list[dict]:
+    return [dict(PAPER_BASE, name=f"scaling_L{L}_s{sd}", L=L, growth=growth, lattice=lattice,
+                 seed=700 + 17 * i + sd, replica=sd)
+            for i, L in enumerate(widths) for sd in range(nseed)]
+
+
+# Fig. 3c: divisions near h_max and h_min under Eq. 5 at L = 40 and L = 640.
+def extremes_runs(lattice: str = "d2q7") -> list[dict]:
+    runs = [dict(PAPER_BASE, name=f"extremes_L40_s{sd}", L=40, growth="division_density",
+                 division_map=True, lattice=lattice, seed=800 + sd, replica=sd) for sd in range(16)]
+    runs += [dict(PAPER_BASE, name=f"extremes_L640_s{sd}", L=640, growth="division_density",
+                  division_map=True, lattice=lattice, seed=900 + sd, replica=sd) for sd in range(4)]
+    return runs
+
+
+# Eq. 7: flat fronts with one cosine mode of amplitude 8 rows under Eq. 5.
+DISPERSION_MODES = (1, 2, 3, 4, 6, 8)
+
+
+def dispersion_runs(L: int = 640, modes=DISPERSION_MODES, nseed: int = 6,
+                    lattice: str = "d2q7") -> list[dict]:
+    return [dict(PAPER_BASE, name=f"dispersion_n{n}_s{sd}", L=L, growth="division_density",
+                 lattice=lattice, mode=n, amplitude=8.0, init_rows=0, seed=1000 + 31 * n + sd,
+                 replica=sd)
+            for n in modes for sd in range(nseed)]

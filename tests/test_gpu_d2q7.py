@@ -132,8 +132,7 @@ def test_reduced_precision_d2q7_one_step(prec):
     sim.close()
 
 
-def test_d2q7_populations_round_trip_and_batch_refusal():
-    from paper_2303_02210_amd import Ensemble, LbmError
+def test_d2q7_populations_round_trip():
     cfg = cfg7(L=64, H=32, init_rows=10, precision="fp32")
     sim = _sim(cfg)
     f = sim.populations()
@@ -142,5 +141,21 @@ def test_d2q7_populations_round_trip_and_batch_refusal():
     sim.set_populations(f)
     assert np.array_equal(sim.populations(), f)
     sim.close()
-    with pytest.raises(LbmError):
-        Ensemble([cfg])
+
+
+def test_d2q7_batch_members_match_solo_runs_bitwise():
+    """D2Q7 members (their own step kernel) batched beside D2Q9 members."""
+    from paper_2303_02210_amd import Ensemble
+    from tests.test_gpu_batch import _same, _solo
+    cfgs = [cfg7(L=128, H=192, init_rows=48, growth_rate=5e-3, sigma=1e-3, precision="fp32", seed=1),
+            si.cfg(L=128, H=192, init_rows=48, growth_rate=5e-3, sigma=1e-3, precision="fp32", seed=1),
+            cfg7(L=96, H=128, init_rows=60, sigma=1e-2, growth="division_density", growth_rate=1e-2,
+                 ybc="follow", wall_min_gap=10, window=True, precision="fp64", seed=2),
+            cfg7(L=200, H=96, init_rows=30, growth_rate=1e-3, sigma=1e-3, region="front_band",
+                 region_width=6, precision="fp16", seed=3, kernel_ty=3)]
+    ens = Ensemble(cfgs)
+    for n in (8, 8, 13):
+        ens.step(n)
+    ens.synchronize()
+    for i, (c, m) in enumerate(zip(cfgs, ens.members)):
+        _same(m, _solo(c, 29), i)

@@ -126,3 +126,45 @@ def test_division_count_matches_n_s_at_size():
     assert abs(got - expect) <= 5 * np.sqrt(expect), (got, expect)
     assert d["src_total"] == pytest.approx(got * 0.1, rel=1e-6)
     sim.close()
+
+
+@pytest.mark.parametrize("lattice", ["d2q9", "d2q7"])
+def test_division_map_equals_the_oracle_map(lattice):
+    """Per-site division counts, bit for bit, through a front band and a wall
+    that follows the front (the map moves with the window), then cleared."""
+    cfg = si.cfg(L=72, H=96, init_rows=70, sigma=1e-2, growth="division_density",
+                 growth_rate=2e-2, ybc="follow", wall_min_gap=12, wall_w_factor=4.0, window=True,
+                 division_map=True, lattice=lattice, seed=8)
+    sim = _sim(cfg)
+    o = orc.Oracle(cfg)
+    t = 0
+    for c in (1, 5, 60, 150):
+        sim.step(c - t)
+        o.step(c - t)
+        t = c
+        mg, mo = sim.division_map(), o.division_map()
+        assert np.array_equal(mg, mo), (lattice, t, np.argwhere(mg != mo)[:5])
+    assert sim.diagnostics()["y_wall"] > 0 and mg.sum() > 0
+    sim.division_map(clear=True)
+    o.division_map(clear=True)
+    sim.step(3)
+    o.step(3)
+    assert np.array_equal(sim.division_map(), o.division_map())
+    sim.close()
+    o.close()
+
+
+def test_division_map_in_a_batch_equals_solo():
+    from paper_2303_02210_amd import Ensemble, Sim
+    cfgs = [si.cfg(L=128, H=96, init_rows=40, growth="division", growth_rate=1e-2, sigma=1e-3,
+                   region="front_band", region_width=6, division_map=True, precision=p, seed=s)
+            for p, s in (("fp32", 1), ("fp64", 2))]
+    ens = Ensemble(cfgs)
+    ens.step(25)
+    ens.synchronize()
+    for c, m in zip(cfgs, ens.members):
+        solo = Sim(c)
+        solo.step(25)
+        assert np.array_equal(m.division_map(), solo.division_map())
+        assert m.division_map().sum() == m.diagnostics()["divisions"] > 0
+        solo.close()

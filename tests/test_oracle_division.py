@@ -235,3 +235,24 @@ def test_poisson_counts_match_literal_selection_with_replacement(law):
             want = lam * q[j, x]
             se = math.sqrt(max(want, 1e-12) / trials)
             assert abs(literal[j, x] - want) <= 5 * se + 1e-12, (j, x, literal[j, x], want)
+
+
+def test_division_map_counts_every_division_where_it_happened():
+    """The per-site map adds up to the division count, holds nothing outside
+    the tissue, and clears."""
+    cfg = si.cfg(L=24, H=32, init_rows=12, growth="division", growth_rate=2e-2, sigma=1e-2,
+                 region="front_band", region_width=3, seed=9)
+    o = orc.Oracle(cfg)
+    o.step(20)
+    m = o.division_map()
+    d = o.diagnostics()
+    assert m.sum() == d["divisions"] > 0
+    h = o.front_heights()
+    rows = np.arange(cfg["H"])[:, None]
+    assert np.all(m[rows >= h[None, :]] == 0)                       # above the front
+    assert np.all(m[rows < h[None, :] - 3 - 1] == 0)                # below the band
+    o.division_map(clear=True)
+    assert o.division_map().sum() == 0
+    o.step(1)
+    assert o.division_map().sum() == o.diagnostics()["divisions"] - d["divisions"]
+    o.close()
