@@ -159,3 +159,64 @@ def test_d2q7_batch_members_match_solo_runs_bitwise():
     ens.synchronize()
     for i, (c, m) in enumerate(zip(cfgs, ens.members)):
         _same(m, _solo(c, 29), i)
+
+
+def test_full_size_4096_d2q7_fp32_sampled_parity():
+    """4096 x 4096 D2Q7 in its default launch shape: one step checked against
+    the oracle on sampled sites and on every row of sampled columns."""
+    cfg = dict(si.BULK_4096_FP32, lattice="d2q7")
+    sim = _sim(cfg)
+    sim.step(20)
+    f0 = sim.populations()
+    h0 = sim.front_heights()
+    t = sim.last_step
+    sim.step(1)
+    f1 = sim.populations()
+    h1 = sim.front_heights()
+    p = orc.make_params(dict(cfg, precision="fp64"))
+    rng = np.random.default_rng(0)
+    L, H = cfg["L"], cfg["H"]
+    hmax = int(h0.max())
+    sites = [(int(rng.integers(0, hmax + 2)), int(rng.integers(0, L))) for _ in range(3000)]
+    sites += [(int(rng.integers(0, H)), int(rng.integers(0, L))) for _ in range(500)]
+    cols = [0, L - 1] + [int(v) for v in rng.integers(0, L, 4)]
+    for x in cols:
+        sites += [(y, x) for y in range(0, min(H, hmax + 3))]
+    for y, x in sites:
+        fs = orc.pull_site(p, f0, x, y)
+        out, _, _, _ = orc.update_site(p, fs, t, x, y, int(h0[x]), 0, -1)
+        rho_s = fs.sum()
+        if abs(rho_s - cfg["rho_c"]) < 1e-5:
+            continue
+        assert np.max(np.abs(f1[:, y, x] - out)) <= 4e-6 * max(rho_s, 1.0) + 1e-7, (y, x)
+    for x in cols:
+        rows = [y for y in range(0, min(H, hmax + 3))
+                if orc.pull_site(p, f0, x, y).sum() >= cfg["rho_c"]]
+        assert h1[x] == (max(rows) + 1 if rows else 0)
+    d = sim.diagnostics()
+    assert np.all(f1[:, d["h_hi"] + 1:, :] == 0.0)
+    sim.close()
+
+
+@pytest.mark.parametrize("kw", [dict(lattice="d2q7"),
+                                dict(growth="division_density", growth_rate=2e-2),
+                                dict(lattice="d2q7", growth="division", growth_rate=2e-2,
+                                     ybc="follow", wall_min_gap=10, window=True,
+                                     division_map=True)])
+def test_checkpoint_resume_is_bitwise(kw):
+    """A restored run continues bit for bit, division rate, counts and the
+    device-driven window included."""
+    cfg = si.cfg(**dict(dict(L=96, H=80, init_rows=40, tau=0.8, sigma=1e-2, growth_rate=5e-3,
+                             precision="fp32", seed=11), **kw))
+    a = _sim(cfg)
+    a.step(20)
+    blob = a.get_state()
+    a.step(30)
+    b = _sim(cfg)
+    b.set_state(blob)
+    b.step(30)
+    assert np.array_equal(a.populations(), b.populations())
+    assert np.array_equal(a.front_heights(), b.front_heights())
+    assert a.diagnostics() == b.diagnostics()
+    a.close()
+    b.close()
