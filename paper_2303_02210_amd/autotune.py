@@ -40,9 +40,10 @@ def key(cfg: dict) -> str:
 
 def candidates(cfg: dict):
     esize = _BYTES[cfg.get("precision", "fp64")]
-    if cfg.get("lattice", "d2q9") == "d2q7":      # one form: a column per lane
-        for ty in (1, 2, 4, 8):
-            yield {"kernel_vb": 1, "kernel_ty": ty}
+    if cfg.get("lattice", "d2q9") == "d2q7":      # no LDS-staged form
+        for vb in [1] + [vb for vb in (4, 8, 16) if vb >= esize and int(cfg["L"]) % (vb // esize) == 0]:
+            for ty in (1, 2, 4, 8):
+                yield {"kernel_vb": vb, "kernel_ty": ty}
         return
     vbs = [1] + [vb for vb in (4, 8, 16) if vb >= esize and int(cfg["L"]) % (vb // esize) == 0]
     for vb in vbs:

@@ -163,8 +163,8 @@ bool params_ok(const lbm_params *p, std::string *why)
     if (p->kernel_ty < 0 || p->kernel_ty > 64) return bad("kernel_ty must be in [0, 64]");
     if ((p->flags & LBM_FLAG_WINDOW) && p->ybc == LBM_Y_PERIODIC)
         return bad("the sweep window needs a rear wall");
-    if (p->lattice == LBM_LATTICE_D2Q7 && p->kernel_vb > 1)
-        return bad("the D2Q7 step has the one-column-per-lane form only (kernel_vb 0 or 1)");
+    if (p->lattice == LBM_LATTICE_D2Q7 && p->kernel_vb == 2)
+        return bad("the D2Q7 step has no LDS-staged form (kernel_vb 2)");
     if (p->lattice == LBM_LATTICE_D2Q7 && p->ybc == LBM_Y_PERIODIC && p->H % 2 != 0)
         return bad("a periodic D2Q7 lattice needs an even number of rows");
     if ((p->precision == LBM_FP16_OFFSET || p->precision == LBM_BF16_OFFSET) &&
@@ -205,7 +205,9 @@ Layout make_layout(const lbm_params *p)
     int ty_pref = l.esize == 2 ? (p->growth >= LBM_GROWTH_DIVISION ? 4 : 2) : 1;
     bool scalar = false;
     if (p->kernel_vb == 1) scalar = true;                 // one column per lane
-    if (p->lattice == LBM_LATTICE_D2Q7) scalar = true;    // (D2Q7's only form)
+    // D2Q7 measured best at 4096 x 4096 in the vector form with 8 B per lane
+    // for float64 and 4 B otherwise
+    if (p->lattice == LBM_LATTICE_D2Q7 && p->kernel_vb == 0) l.vb = l.esize == 8 ? 8 : 4;
     else if (p->kernel_vb == 2) l.staged = true;          // rows staged through LDS
     else if (p->kernel_vb > 1) l.vb = p->kernel_vb;       // 4, 8 or 16 bytes per lane
     // the staged form moves 16-bit populations in pairs of columns
@@ -225,9 +227,11 @@ Layout make_layout(const lbm_params *p)
     l.nt = lanes <= 64 ? 64 : (lanes <= 128 ? 128 : 256);
     if (l.staged) l.nt = 64 * StagedGeom((int)l.esize).waves();
     l.gx = (lanes + l.nt - 1) / l.nt;
-    // D2Q7 (one column per lane), measured best at 4096 x 4096: float64 1 row,
-    // float32 2 rows, 16-bit 4 rows per thread
-    if (p->lattice == LBM_LATTICE_D2Q7 && p->kernel_ty <= 0) ty_pref = l.esize == 8 ? 1 : (l.esize == 4 ? 2 : 4);
+    // D2Q7, measured best at 4096 x 4096: float64 1 row per thread, the others
+    // 2 rows (one column per lane, used when the width does not split into
+    // vectors: float64 1 row, float32 2, 16-bit 4)
+    if (p->lattice == LBM_LATTICE_D2Q7 && p->kernel_ty <= 0)
+        ty_pref = l.esize == 8 ? 1 : (l.vec || l.esize == 4 ? 2 : 4);
     const bool pref_rows = l.vec || p->kernel_ty > 0 || p->lattice == LBM_LATTICE_D2Q7;
     l.ty = pick_ty(l.gx, p->H, pref_rows ? ty_pref : 2, p->kernel_ty > 0);
     l.gy = (p->H + l.ty - 1) / l.ty;
@@ -426,7 +430,7 @@ int do_step(lbm_handle *h, int64_t n)
         a.h_next = h->hslot(h->t + 1);
         a.h_clear = h->device_driven ? nullptr : h->hslot(h->t + 2);
         a.t = (uint32_t)h->t;
-        int rc = h->hip(l.tl.nq == 7 ? launch_step7<S>(a, grid, l.nt, l.rb, h->stream)
+        int rc = h->hip(l.tl.nq == 7 ? launch_step7<S>(a, grid, l.nt, l.vec ? l.vb : 0, l.rb, h->stream)
                         : l.staged ? launch_step_staged<S>(a, grid, h->stream)
                         : l.vec    ? launch_step_vec<S>(a, grid, l.nt, l.vb, h->stream)
                                    : launch_step<S>(a, grid, l.nt, l.rb, h->stream),
@@ -1008,7 +1012,7 @@ struct lbm_batch {
             const int vbrb = h->lay.vec ? h->lay.vb : h->lay.rb;
             const int win = (h->p.flags & LBM_FLAG_WINDOW) ? 1 : 0;
             const int div = h->p.growth >= LBM_GROWTH_DIVISION ? 1 : 0;
-            const int form = h->lay.tl.nq == 7 ? 2 : (h->lay.vec ? 1 : 0);
+            const int form = h->lay.tl.nq == 7 ? (h->lay.vec ? 3 : 2) : (h->lay.vec ? 1 : 0);
             BatchGroup *g = nullptr;
             for (BatchGroup &c : groups)
                 if (c.prec == h->p.precision && c.form == form && c.nt == h->lay.nt &&

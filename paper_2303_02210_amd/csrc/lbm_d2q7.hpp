@@ -11,8 +11,9 @@
 // unit to the left in the row below or above is column x - 1 + par, half a
 // unit to the right column x + par (par = y mod 2).
 //
-// One column per lane: each lane loads its seven pulls directly (the lanes of
-// a wave read contiguous runs of each row), with the same row bookkeeping,
+// Two forms: one column per lane, each lane loading its seven pulls directly
+// (the lanes of a wave read contiguous runs of each row), and a vector form
+// with several columns per lane; both with the same row bookkeeping,
 // rear-wall reflection, tallies and front heights as the D2Q9 forms.
 // Included by lbm_step.hpp after the shared pieces.
 #pragma once
@@ -336,6 +337,282 @@ __device__ __forceinline__ void step_tile7(const StepArgs<S> &a, const StepIO<S>
     }
 }
 
+// The D2Q7 step with ND dwords (V = 4 ND / sizeof(S) consecutive columns) per
+// lane: per row the seven vector loads and six wave-edge values, the +-x
+// neighbours across lanes by DPP moves, and the same load/store ordering,
+// empty-wavefront skip and tallies as the D2Q9 vector form.  Which diagonal
+// pulls take the neighbouring column depends on the row's parity
+// (wave-uniform): NE and SE from x - 1 on even rows, NW and SW from x + 1 on
+// odd rows, the others from x itself.
+template <class S, int NT, int ND, bool DIV>
+__device__ __forceinline__ void step_vec_tile7(const StepArgs<S> &a, const StepIO<S> &io, int bx,
+                                               int by, int nbx, int nstrips = 1)
+{
+    using R = typename Codec<S>::R;
+    using VT = typename RawVec<ND>::type;
+    constexpr int V = ND * 4 / (int)sizeof(S);
+
+    const int L = a.L, H = a.H;
+    const int lane = threadIdx.x & 63;
+    const int xv = (bx * NT + (int)threadIdx.x) * V;          // first column of this lane
+    const int x0 = xv - lane * V;                               // first column of the wave
+    const bool active = xv < L;
+    const int xl = (x0 == 0 || x0 >= L) ? L - 1 : x0 - 1;     // (a wave past L reads in bounds)
+    const int xr = (x0 + 64 * V < L) ? x0 + 64 * V : 0;
+    const bool edge_l = (lane == 0);
+    const bool edge_r = (lane == 63) || (xv + V >= L);
+
+    int64_t y_wall = 0, y_top = H, nrows = H;
+    if (a.mode == kModeDevice) {
+        y_wall = a.st->y_wall;
+        y_top = a.st->y_valid_top;
+        nrows = a.st->n_rows;
+    }
+    const int j0 = by * a.ty;
+    const int jend = (int)min((int64_t)(j0 + nstrips * a.ty), nrows);
+
+    double m_acc = 0.0, s_acc = 0.0, x_acc = 0.0;
+    long long mfx_acc = 0;
+    DivTally dv;
+    if constexpr (DIV) dv = div_begin(a.st);
+    int32_t jmax[V], hp[V];
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+        jmax[i] = -1;
+        hp[i] = (a.region == kRegionFrontBand && active) ? io.h_prev[xv + i] : 0;
+    }
+    R Wd[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) Wd[i] = a.Wd[i];
+    uint32_t epat[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        if constexpr (sizeof(S) == 2) {
+            const uint32_t b = to_mem<S>(Codec<S>::enc(R(0), Wd[i]));
+            epat[i] = b | (b << 16);
+        } else {
+            epat[i] = 0u;
+        }
+    }
+
+    const Tiles tl = a.tl;
+    const int tws = tl.tws;
+    const int64_t cv = tl.col(active ? xv : L - V), cl = tl.col(xl), cr = tl.col(xr);
+    const MemT<S> LBM_GLOBAL *__restrict__ F = as_global(reinterpret_cast<const MemT<S> *>(io.fin));
+    MemT<S> LBM_GLOBAL *__restrict__ G = as_global(reinterpret_cast<MemT<S> *>(io.fout));
+    int r0 = (a.mode == kModeDevice) ? (int)((y_wall + j0) % H) : j0;
+
+    struct Fetch {
+        VT A[7];
+        S e[6];   // E, W, NE, NW, SW, SE sources beyond the wave's edges
+    };
+    constexpr uint32_t EB = sizeof(MemT<S>);
+    const uint32_t loff = (uint32_t)(cv * EB);
+    const int64_t rowbytes = tl.rs * EB;
+    const auto pl = [&](int q) { return ((uint32_t)q << tws) * EB; };
+    auto fetch = [&](int j, int r, Fetch &f) {
+        const RowSrc s = row_sources(a.mode, j, r, H, y_wall + j, y_top);
+        // NE / NW pull from the row below, or from this site reflected (SW / SE)
+        const int qn2 = s.below ? 5 : 2, qn3 = s.below ? 6 : 3;
+        if constexpr (sizeof(S) != 2) {
+            const MemT<S> LBM_GLOBAL *row0 = F + (int64_t)s.r0 * tl.rs;
+            const MemT<S> LBM_GLOBAL *rowm = F + (int64_t)(s.below ? s.r0 : s.rm) * tl.rs;
+            const MemT<S> LBM_GLOBAL *rowp = F + (int64_t)s.rp * tl.rs;
+            f.A[0] = vload<ND>(row0 + cv + (0 << tws));
+            f.A[1] = vload<ND>(row0 + cv + (1 << tws));
+            f.A[4] = vload<ND>(row0 + cv + (4 << tws));
+            f.A[2] = vload<ND>(rowm + cv + (qn2 << tws));
+            f.A[3] = vload<ND>(rowm + cv + (qn3 << tws));
+            f.A[5] = vload<ND>(rowp + cv + (5 << tws));
+            f.A[6] = vload<ND>(rowp + cv + (6 << tws));
+            f.e[0] = from_mem<S>(row0[cl + (1 << tws)]);
+            f.e[1] = from_mem<S>(row0[cr + (4 << tws)]);
+            f.e[2] = from_mem<S>(rowm[cl + (2 << tws)]);
+            f.e[3] = from_mem<S>(rowm[cr + (3 << tws)]);
+            f.e[4] = from_mem<S>(rowp[cr + (5 << tws)]);
+            f.e[5] = from_mem<S>(rowp[cl + (6 << tws)]);
+            return;
+        }
+        const __amdgpu_buffer_rsrc_t R0 =
+            row_rsrc((const void *)(F + (int64_t)s.r0 * tl.rs), rowbytes);
+        const __amdgpu_buffer_rsrc_t Rm =
+            row_rsrc((const void *)(F + (int64_t)(s.below ? s.r0 : s.rm) * tl.rs), rowbytes);
+        const __amdgpu_buffer_rsrc_t Rp =
+            row_rsrc((const void *)(F + (int64_t)s.rp * tl.rs), rowbytes);
+        f.A[0] = bload<ND>(R0, loff, pl(0));
+        f.A[1] = bload<ND>(R0, loff, pl(1));
+        f.A[4] = bload<ND>(R0, loff, pl(4));
+        f.A[2] = bload<ND>(Rm, loff, pl(qn2));
+        f.A[3] = bload<ND>(Rm, loff, pl(qn3));
+        f.A[5] = bload<ND>(Rp, loff, pl(5));
+        f.A[6] = bload<ND>(Rp, loff, pl(6));
+        f.e[0] = bload_el<S>(R0, (uint32_t)(cl * EB) + pl(1));
+        f.e[1] = bload_el<S>(R0, (uint32_t)(cr * EB) + pl(4));
+        f.e[2] = bload_el<S>(Rm, (uint32_t)(cl * EB) + pl(2));
+        f.e[3] = bload_el<S>(Rm, (uint32_t)(cr * EB) + pl(3));
+        f.e[4] = bload_el<S>(Rp, (uint32_t)(cr * EB) + pl(5));
+        f.e[5] = bload_el<S>(Rp, (uint32_t)(cl * EB) + pl(6));
+    };
+    Fetch cur;
+    VT O[7];
+    auto update_row = [&](int j, int r) -> RowSrc {
+        const int64_t y = y_wall + j;
+        const bool odd = (y & 1) != 0;
+        const RowSrc s = row_sources(a.mode, j, r, H, y, y_top);
+        const VT A0 = cur.A[0], A1 = cur.A[1], A2 = cur.A[2], A3 = cur.A[3];
+        const VT A4 = cur.A[4], A5 = cur.A[5], A6 = cur.A[6];
+        // neighbours across lanes: from x - 1 (E, NE, SE) and x + 1 (W, NW, SW)
+        const S n1 = from_left<S, ND>(A1, cur.e[0], edge_l);
+        const S n4 = from_right<S, ND>(A4, cur.e[1], edge_r);
+        const S n2 = from_left<S, ND>(A2, cur.e[2], edge_l);
+        const S n3 = from_right<S, ND>(A3, cur.e[3], edge_r);
+        const S n5 = from_right<S, ND>(A5, cur.e[4], edge_r);
+        const S n6 = from_left<S, ND>(A6, cur.e[5], edge_l);
+
+        // an exactly empty neighbourhood over the whole wavefront: skip
+        bool busy = false;
+        {
+            const VT *Av[7] = {&A0, &A1, &A2, &A3, &A4, &A5, &A6};
+#pragma unroll
+            for (int q = 0; q < 7; ++q)
+#pragma unroll
+                for (int d = 0; d < ND; ++d) busy = busy || ((*Av[q])[d] != epat[q]);
+            constexpr int eq[6] = {1, 4, 2, 3, 5, 6};
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                typename RawVec<ND>::type t;
+#pragma unroll
+                for (int d = 0; d < ND; ++d) t[d] = epat[eq[i]];
+                busy = busy || (to_mem<S>(cur.e[i]) != to_mem<S>(get_el<S, ND>(t, 0)));
+            }
+        }
+        uint32_t tmask = 0;
+        if (__builtin_amdgcn_ballot_w64(busy) == 0) {
+#pragma unroll
+            for (int q = 0; q < 7; ++q)
+#pragma unroll
+                for (int d = 0; d < ND; ++d) O[q][d] = epat[q];
+        } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            S v[7];
+            const S left1 = (k == 0) ? n1 : get_el<S, ND>(A1, k == 0 ? 0 : k - 1);
+            const S right4 = (k == V - 1) ? n4 : get_el<S, ND>(A4, k == V - 1 ? k : k + 1);
+            const S left2 = (k == 0) ? n2 : get_el<S, ND>(A2, k == 0 ? 0 : k - 1);
+            const S right3 = (k == V - 1) ? n3 : get_el<S, ND>(A3, k == V - 1 ? k : k + 1);
+            const S right5 = (k == V - 1) ? n5 : get_el<S, ND>(A5, k == V - 1 ? k : k + 1);
+            const S left6 = (k == 0) ? n6 : get_el<S, ND>(A6, k == 0 ? 0 : k - 1);
+            v[0] = get_el<S, ND>(A0, k);
+            v[1] = left1;
+            v[4] = right4;
+            if (s.below) {
+                v[2] = get_el<S, ND>(A2, k);
+                v[3] = get_el<S, ND>(A3, k);
+            } else {
+                v[2] = odd ? get_el<S, ND>(A2, k) : left2;
+                v[3] = odd ? right3 : get_el<S, ND>(A3, k);
+            }
+            v[5] = odd ? right5 : get_el<S, ND>(A5, k);
+            v[6] = odd ? get_el<S, ND>(A6, k) : left6;
+            R fs[7];
+#pragma unroll
+            for (int i = 0; i < 7; ++i) fs[i] = Codec<S>::dec(v[i], Wd[i]);
+            if (!s.v0) {
+                v[0] = Codec<S>::enc(R(0), Wd[0]);
+                v[1] = v[4] = Codec<S>::enc(R(0), Wd[1]);
+                fs[0] = fs[1] = fs[4] = R(0);
+            }
+            if (!s.below && !s.vm) {
+                v[2] = v[3] = Codec<S>::enc(R(0), Wd[2]);
+                fs[2] = fs[3] = R(0);
+            }
+            if (!s.vp) {
+                v[5] = v[6] = Codec<S>::enc(R(0), Wd[5]);
+                fs[5] = fs[6] = R(0);
+            }
+            S so[7];
+            double m_site = 0.0, s_site = 0.0, x_site = 0.0;
+            const uint32_t x = (uint32_t)(xv + k);
+            int32_t hpk = hp[0];
+#pragma unroll
+            for (int d = 1; d < V; ++d) hpk = (k == d) ? hp[d] : hpk;
+            long long mfx_site = 0;
+            DivTally dv_site = div_site(dv);
+            const bool tissue = site_step7<S, DIV>(a, io.t, v, fs, Wd, so, x, y, y_wall, hpk,
+                                                   m_site, s_site, x_site, mfx_site, dv_site);
+#pragma unroll
+            for (int i = 0; i < 7; ++i) put_el<S, ND>(O[i], k, so[i]);
+            if (active) {
+                m_acc += m_site;
+                s_acc += s_site;
+                x_acc += x_site;
+                mfx_acc += mfx_site;
+                dv.w += dv_site.w;
+                dv.n += dv_site.n;
+                if constexpr (DIV) count_divisions(a, y, x, dv_site.n);
+                if (tissue) {
+                    tmask |= 1u << k;
+                    if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
+                }
+            }
+        }
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+            if ((tmask >> k) & 1u) jmax[k] = j;
+        return s;
+    };
+    const uint32_t soff = active ? loff : kOffNone;
+    auto store_row = [&](const RowSrc &s) {
+        const __amdgpu_buffer_rsrc_t rr = row_rsrc((const void *)(G + (int64_t)s.r0 * tl.rs), rowbytes);
+#pragma unroll
+        for (int i = 0; i < 7; ++i) bstore<ND>(rr, soff, pl(i), O[i]);
+    };
+    if (j0 < jend) {
+        fetch(j0, r0, cur);
+        RowSrc s = update_row(j0, r0);
+        for (int j = j0 + 1; j < jend; ++j) {
+            __asm__ volatile("" ::: "memory");
+            fetch(j, s.rp, cur);
+            __asm__ volatile("" ::: "memory");
+            store_row(s);
+            s = update_row(j, s.rp);
+        }
+        store_row(s);
+    }
+
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (jmax[k] >= 0) {
+                const int32_t hv = (int32_t)(y_wall + jmax[k] + 1);
+                atomicMax(io.h_next + xv + k, hv);
+                atomicMax(a.colmax + xv + k, hv);
+            }
+            if (io.h_clear && by == 0) io.h_clear[xv + k] = 0;
+        }
+    }
+
+    block_tallies<NT, DIV>(m_acc, s_acc, x_acc, mfx_acc, dv, a.st, by * nbx + bx);
+    double *pb = a.partials + kPartialSlots * (by * nbx + bx);
+    if (threadIdx.x == 0) {
+        pb[0] = m_acc;
+        pb[1] += s_acc;
+        pb[2] += x_acc;
+        for (int i = 1; i < nstrips; ++i) a.partials[kPartialSlots * ((by + i) * nbx + bx)] = 0.0;
+    }
+}
+
+template <class S, int NT, int ND, bool DIV>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vec_waves<S, ND, DIV>())))
+void step_kernel_vec7(StepArgs<S> a)
+{
+    const int nbx = gridDim.x;
+    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
+    const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
+    step_vec_tile7<S, NT, ND, DIV>(a, io, lin % nbx, lin / nbx, nbx);
+}
+
 template <class S, int NT, int RB, bool DIV>
 __global__ __launch_bounds__(NT) void step_kernel7(StepArgs<S> a)
 {
@@ -345,8 +622,9 @@ __global__ __launch_bounds__(NT) void step_kernel7(StepArgs<S> a)
     step_tile7<S, NT, RB, DIV>(a, io, lin % nbx, lin / nbx, nbx);
 }
 
-// Batches: as step_batch, with the D2Q7 tile body.
-template <class S, int NT, int RB, bool DIV>
+// Batches: as step_batch, with a D2Q7 tile body (VEC: ND dwords per lane,
+// else one column per lane with ND rows' loads at once).
+template <class S, int NT, int ND, bool VEC, bool DIV>
 __global__ __launch_bounds__(NT) void step_batch7(BatchRep<S> *const *reps, const TileRef *table,
                                                   const int32_t *count, int k)
 {
@@ -359,7 +637,8 @@ __global__ __launch_bounds__(NT) void step_batch7(BatchRep<S> *const *reps, cons
         stage_dwords<NT>(reps[e.rep], stage, (int)(sizeof(BatchRep<S>) / 4));
         const StepIO<S> io = batch_io(&R, k);
         const int bx = e.local0 % R.gx, by = e.local0 / R.gx;
-        step_tile7<S, NT, RB, DIV>(R.a, io, bx, by, R.gx, e.n);
+        if constexpr (VEC) step_vec_tile7<S, NT, ND, DIV>(R.a, io, bx, by, R.gx, e.n);
+        else step_tile7<S, NT, ND, DIV>(R.a, io, bx, by, R.gx, e.n);
     }
 }
 
@@ -371,11 +650,37 @@ void launch_step7_rb(const StepArgs<S> &a, dim3 grid, int nt, hipStream_t s)
     else hipLaunchKernelGGL((step_kernel7<S, 64, RB, DIV>), grid, dim3(64), 0, s, a);
 }
 
+template <class S, int ND, bool DIV>
+void launch_vec7_nt(const StepArgs<S> &a, dim3 grid, int nt, hipStream_t s)
+{
+    if (nt == 256) hipLaunchKernelGGL((step_kernel_vec7<S, 256, ND, DIV>), grid, dim3(256), 0, s, a);
+    else if (nt == 128) hipLaunchKernelGGL((step_kernel_vec7<S, 128, ND, DIV>), grid, dim3(128), 0, s, a);
+    else hipLaunchKernelGGL((step_kernel_vec7<S, 64, ND, DIV>), grid, dim3(64), 0, s, a);
+}
+
+template <class S, bool DIV>
+void launch_vec7(const StepArgs<S> &a, dim3 grid, int nt, int vb, hipStream_t s)
+{
+    if (vb == 4) {
+        if constexpr (sizeof(S) <= 4) launch_vec7_nt<S, 1, DIV>(a, grid, nt, s);
+    } else if (vb == 8) {
+        launch_vec7_nt<S, 2, DIV>(a, grid, nt, s);
+    } else {
+        launch_vec7_nt<S, 4, DIV>(a, grid, nt, s);
+    }
+}
+
+// vb: bytes per lane of the vector form (4, 8 or 16), 0 for one column per
+// lane with rb rows' loads at once.
 template <class S>
-hipError_t launch_step7(const StepArgs<S> &a, dim3 grid, int nt, int rb, hipStream_t s)
+hipError_t launch_step7(const StepArgs<S> &a, dim3 grid, int nt, int vb, int rb, hipStream_t s)
 {
     const bool div = a.growth >= kGrowthDivision;
-    if (rb >= 2) {
+    if (vb > 0) {
+        if (vb == 4 && sizeof(S) > 4) return hipErrorInvalidValue;
+        if (div) launch_vec7<S, true>(a, grid, nt, vb, s);
+        else launch_vec7<S, false>(a, grid, nt, vb, s);
+    } else if (rb >= 2) {
         if (div) launch_step7_rb<S, 2, true>(a, grid, nt, s);
         else launch_step7_rb<S, 2, false>(a, grid, nt, s);
     } else {

@@ -9,7 +9,7 @@ namespace lbm {
     template hipError_t launch_step<S>(const StepArgs<S> &, dim3, int, int, hipStream_t);    \
     template hipError_t launch_step_vec<S>(const StepArgs<S> &, dim3, int, int, hipStream_t);    \
     template hipError_t launch_step_staged<S>(const StepArgs<S> &, dim3, hipStream_t);          \
-    template hipError_t launch_step7<S>(const StepArgs<S> &, dim3, int, int, hipStream_t);      \
+    template hipError_t launch_step7<S>(const StepArgs<S> &, dim3, int, int, int, hipStream_t); \
     template hipError_t launch_init<S>(const InitArgs<S> &, dim3, int, hipStream_t);    \
     template hipError_t launch_mass<S>(const MassArgs<S> &, dim3, int, hipStream_t);    \
     template hipError_t launch_finalize<S>(const FinalizeArgs<S> &, hipStream_t);           \

@@ -236,9 +236,10 @@ __host__ __device__ inline TileRef run_ref(int rep, int64_t l, int64_t strips, i
 
 template <class S>
 hipError_t launch_step(const StepArgs<S> &a, dim3 grid, int nt, int rb, hipStream_t s);
-// The step on the D2Q7 lattice (one column per lane, rb rows' loads at once).
+// The step on the D2Q7 lattice: vb bytes of columns per lane (4, 8, 16), or
+// vb = 0 for one column per lane with rb rows' loads at once.
 template <class S>
-hipError_t launch_step7(const StepArgs<S> &a, dim3 grid, int nt, int rb, hipStream_t s);
+hipError_t launch_step7(const StepArgs<S> &a, dim3 grid, int nt, int vb, int rb, hipStream_t s);
 // A batch group: n members with the same storage type and kernel form (div:
 // the members grow by the division laws).
 // reps: device array of member descriptors; table: the group's tiles;

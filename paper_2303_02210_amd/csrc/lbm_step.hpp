@@ -2024,11 +2024,20 @@ void launch_batch_div(BatchRep<S> *const *reps, const TileRef *table, const int3
                       int grid, int vec, int vb_or_rb, int k, hipStream_t s)
 {
     const dim3 g(grid), b(NT);
-    if (vec == 2) {   // the D2Q7 step
+    if (vec == 2) {   // the D2Q7 step, one column per lane
         if (vb_or_rb >= 2)
-            hipLaunchKernelGGL((step_batch7<S, NT, 2, DIV>), g, b, 0, s, reps, table, count, k);
+            hipLaunchKernelGGL((step_batch7<S, NT, 2, false, DIV>), g, b, 0, s, reps, table, count, k);
         else
-            hipLaunchKernelGGL((step_batch7<S, NT, 1, DIV>), g, b, 0, s, reps, table, count, k);
+            hipLaunchKernelGGL((step_batch7<S, NT, 1, false, DIV>), g, b, 0, s, reps, table, count, k);
+    } else if (vec == 3) {   // the D2Q7 vector form
+        if (vb_or_rb == 4) {
+            if constexpr (sizeof(S) <= 4)
+                hipLaunchKernelGGL((step_batch7<S, NT, 1, true, DIV>), g, b, 0, s, reps, table, count, k);
+        } else if (vb_or_rb == 8) {
+            hipLaunchKernelGGL((step_batch7<S, NT, 2, true, DIV>), g, b, 0, s, reps, table, count, k);
+        } else {
+            hipLaunchKernelGGL((step_batch7<S, NT, 4, true, DIV>), g, b, 0, s, reps, table, count, k);
+        }
     } else if (vec) {
         if (vb_or_rb == 4) {
             if constexpr (sizeof(S) <= 4)

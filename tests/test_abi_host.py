@@ -84,7 +84,7 @@ def test_workspace_bytes_scales_with_precision():
     dict(init_amp=1.0), dict(region_width=-1), dict(precision="fp64", window=True, ybc="periodic"),
     dict(growth="division", rho_cell=0.0), dict(growth="division_density", rho_cell=float("inf")),
     dict(growth="division_density", rho0=0.5), dict(growth="division_density", rho0=0.4),
-    dict(lattice="d2q7", kernel_vb=4), dict(lattice="d2q7", kernel_vb=2),
+    dict(lattice="d2q7", kernel_vb=2),
     dict(lattice="d2q7", ybc="periodic", H=63, init_rows=10),
 ])
 def test_invalid_parameters_rejected_on_host(bad):

@@ -43,9 +43,14 @@ def test_fp64_d2q7_64x64_bulk_1000_steps():
 
 @pytest.mark.parametrize("L,H", [(130, 48), (7, 40), (256, 32)])
 @pytest.mark.parametrize("ty", [0, 1, 3])
-def test_fp64_d2q7_ragged_noise_front_band(L, H, ty):
+@pytest.mark.parametrize("vb", [0, 1, 16])
+def test_fp64_d2q7_ragged_noise_front_band(L, H, ty, vb):
+    # vb 0: the default (the vector form, 1 column per lane); 1: one column per
+    # lane with direct neighbour loads; 16: the vector form with 2 columns per
+    # lane (widths it does not divide run the one-column form)
     _run(cfg7(L=L, H=H, init_rows=H // 3, tau=0.8, sigma=1e-2, growth_rate=2e-3,
-              region="front_band", region_width=4, seed=11, replica=2, kernel_ty=ty), [1, 7, 60])
+              region="front_band", region_width=4, seed=11, replica=2, kernel_ty=ty,
+              kernel_vb=vb), [1, 7, 60])
 
 
 def test_fp64_d2q7_rear_band_and_no_growth():
@@ -54,9 +59,11 @@ def test_fp64_d2q7_rear_band_and_no_growth():
     _run(cfg7(L=96, H=64, init_rows=30, sigma=1e-2, growth="none", seed=5), [1, 50])
 
 
-def test_fp64_d2q7_follow_wall_and_window():
+@pytest.mark.parametrize("vb", [0, 1, 16])
+def test_fp64_d2q7_follow_wall_and_window(vb):
     d = _run(cfg7(L=72, H=96, init_rows=70, sigma=1e-2, growth_rate=1e-2, ybc="follow",
-                  wall_min_gap=12, wall_w_factor=4.0, window=True, seed=8), [1, 3, 40, 200])
+                  wall_min_gap=12, wall_w_factor=4.0, window=True, seed=8, kernel_vb=vb),
+             [1, 3, 40, 200])
     assert d["y_wall"] > 0
 
 
@@ -79,9 +86,10 @@ def test_fp64_d2q7_periodic_from_set_state():
 
 
 @pytest.mark.parametrize("law", ["division", "division_density"])
-def test_fp64_d2q7_division_laws(law):
+@pytest.mark.parametrize("vb", [0, 1, 16])
+def test_fp64_d2q7_division_laws(law, vb):
     d = _run(cfg7(L=96, H=64, init_rows=24, tau=0.8, sigma=1e-2, growth=law, growth_rate=2e-2,
-                  seed=21, replica=3), [1, 2, 15, 60])
+                  seed=21, replica=3, kernel_vb=vb), [1, 2, 15, 60])
     assert d["divisions"] > 100
 
 
@@ -132,6 +140,29 @@ def test_reduced_precision_d2q7_one_step(prec):
     sim.close()
 
 
+@pytest.mark.parametrize("prec,vb", [("fp32", 4), ("fp32", 8), ("fp16", 4), ("fp16", 8),
+                                     ("bf16", 4), ("fp64", 16)])
+def test_d2q7_vector_form_bitwise_equals_one_column_form(prec, vb):
+    """The launch shape never changes results: the vector form against the
+    one-column form, bit for bit, with noise, a front band and divisions."""
+    for growth in ("bulk", "division_density"):
+        base = cfg7(L=256, H=96, init_rows=40, tau=0.8, sigma=1e-2, growth=growth,
+                    growth_rate=5e-3, region="front_band", region_width=6, precision=prec,
+                    seed=9)
+        a = _sim(dict(base, kernel_vb=1))
+        b = _sim(dict(base, kernel_vb=vb))
+        for n in (1, 10, 40):
+            a.step(n)
+            b.step(n)
+            assert np.array_equal(a.populations(), b.populations()), (prec, vb, growth, n)
+            assert np.array_equal(a.front_heights(), b.front_heights())
+            da, db = a.diagnostics(), b.diagnostics()
+            assert da["divisions"] == db["divisions"] and da["lam"] == db["lam"]
+            assert abs(da["mass"] - db["mass"]) <= 1e-9 * da["mass"]
+        a.close()
+        b.close()
+
+
 def test_d2q7_populations_round_trip():
     cfg = cfg7(L=64, H=32, init_rows=10, precision="fp32")
     sim = _sim(cfg)
@@ -152,7 +183,11 @@ def test_d2q7_batch_members_match_solo_runs_bitwise():
             cfg7(L=96, H=128, init_rows=60, sigma=1e-2, growth="division_density", growth_rate=1e-2,
                  ybc="follow", wall_min_gap=10, window=True, precision="fp64", seed=2),
             cfg7(L=200, H=96, init_rows=30, growth_rate=1e-3, sigma=1e-3, region="front_band",
-                 region_width=6, precision="fp16", seed=3, kernel_ty=3)]
+                 region_width=6, precision="fp16", seed=3, kernel_ty=3),
+            cfg7(L=256, H=128, init_rows=40, growth_rate=2e-3, sigma=1e-3, precision="fp16",
+                 seed=4, kernel_vb=4, kernel_ty=4),
+            cfg7(L=128, H=96, init_rows=40, growth="division", growth_rate=1e-2, sigma=1e-2,
+                 precision="fp64", seed=5, kernel_vb=16)]
     ens = Ensemble(cfgs)
     for n in (8, 8, 13):
         ens.step(n)
