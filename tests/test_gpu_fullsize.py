@@ -1,0 +1,167 @@
+"""Parity at the throughput workloads' full sizes, in the launch shapes the
+benchmark times (library defaults and the shipped tuned shapes): one GPU step
+from the GPU's own state, checked against the oracle site by site on sampled
+sites and on every live row of sampled columns, with the front heights of
+those columns, the exactly empty void, and (float64) bit-for-bit agreement.
+
+Tolerance for float32 arithmetic: |df| <= 4e-6 max(rho*, 1) + 1e-7 (about 30
+rounded float32 operations on values up to rho*), plus half an ulp of the
+stored offset f - W_i for the 16-bit storages.  Sites whose tissue/void
+decision lies within 1e-5 of rho_c are checked against both branches.
+"""
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+_ULP_BITS = {"fp16": 10, "bf16": 7}
+_W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+_W7 = np.array([1 / 2] + [1 / 12] * 6)
+
+
+def _storage_offsets(cfg):
+    """W_i = w_i rho_ref rounded to the storage format (0 for fp32/fp64)."""
+    prec = cfg.get("precision", "fp32")
+    w = _W7 if cfg.get("lattice", "d2q9") == "d2q7" else _W9
+    W = w * cfg.get("rho_ref", 1.0)
+    if prec == "fp16":
+        return W.astype(np.float32).astype(np.float16).astype(np.float64)
+    if prec == "bf16":
+        b = W.astype(np.float32).view(np.uint32)
+        b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+        return b.astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.zeros_like(W)
+
+
+def _half_ulp(prec, v):
+    if prec not in _ULP_BITS:
+        return np.zeros_like(v)
+    a = np.maximum(np.abs(v), 2.0 ** -24 if prec == "fp16" else 2.0 ** -126)
+    e = np.floor(np.log2(a))
+    if prec == "fp16":
+        e = np.maximum(e, -14)
+    return 0.5 * 2.0 ** (e - _ULP_BITS[prec])
+
+
+def _sampled_step(sim, cfg, advance, nsites=3000, ncols=4, seed=0):
+    """Step once with `advance()` and check the step against the oracle."""
+    prec = cfg.get("precision", "fp32")
+    f0 = sim.populations()
+    h0 = sim.front_heights()
+    t = sim.last_step
+    lam = sim.diagnostics()["lam"]
+    advance()
+    f1 = sim.populations()
+    h1 = sim.front_heights()
+    assert sim.last_step == t + 1
+    p = orc.make_params(dict(cfg, precision="fp64"))
+    q = orc.q_of(p)
+    W = _storage_offsets(cfg)
+    rng = np.random.default_rng(seed)
+    L, H = cfg["L"], cfg["H"]
+    hmax = int(h0.max())
+    top = min(H, hmax + 3)
+    sites = [(int(rng.integers(0, min(H, hmax + 2))), int(rng.integers(0, L)))
+             for _ in range(nsites)]
+    sites += [(int(rng.integers(0, H)), int(rng.integers(0, L))) for _ in range(nsites // 6)]
+    cols = sorted({0, L - 1, *[int(v) for v in rng.integers(0, L, ncols)]})
+    for x in cols:
+        sites += [(y, x) for y in range(top)]
+    worst = 0.0
+    for y, x in sites:
+        fs = orc.pull_site(p, f0, x, y)
+        rho_s = fs.sum()
+        got = f1[:, y, x]
+        if prec == "fp64":
+            out = orc.update_site(p, fs, t, x, y, int(h0[x]), 0, -1, lam)[0][:q]
+            assert np.array_equal(got, out), (cfg.get("name"), y, x, got - out)
+            continue
+        branches = (-1,) if abs(rho_s - cfg["rho_c"]) >= 1e-5 else (0, 1)
+        ok = False
+        for force in branches:
+            out = orc.update_site(p, fs, t, x, y, int(h0[x]), 0, force, lam)[0][:q]
+            tol = 4e-6 * max(rho_s, 1.0) + 1e-7 + _half_ulp(prec, out - W)
+            d = np.abs(got - out)
+            if np.all(d <= tol):
+                ok = True
+                if force == -1:
+                    worst = max(worst, float(d.max()))
+                break
+        assert ok, (cfg.get("name"), prec, y, x, got, out)
+    for x in cols:
+        rows = [y for y in range(top) if orc.pull_site(p, f0, x, y).sum() >= cfg["rho_c"]]
+        near = any(abs(orc.pull_site(p, f0, x, y).sum() - cfg["rho_c"]) < 1e-5
+                   for y in range(top))
+        if not near:
+            assert h1[x] == (max(rows) + 1 if rows else 0), (x, h1[x])
+    d = sim.diagnostics()
+    assert d["status"] == 0
+    assert np.all(f1[:, d["h_hi"] + 1:, :] == 0.0)
+    return worst
+
+
+def _tuned(cfg):
+    from paper_2303_02210_amd import autotune
+    c = autotune.apply(cfg)
+    assert "kernel_vb" in c, ("no tuned shape shipped for", autotune.key(cfg))
+    return c
+
+
+_EDGE = si.EDGE_2048x8192
+_BULK = si.BULK_4096_FP32
+_CASES = {
+    "edge_fp32": dict(_EDGE, precision="fp32"),
+    "edge_fp32_tuned": ("tuned", dict(_EDGE, precision="fp32")),
+    "edge_fp16": dict(_EDGE, precision="fp16"),
+    "edge_fp16_tuned": ("tuned", dict(_EDGE, precision="fp16")),
+    "edge_bf16": dict(_EDGE, precision="bf16"),
+    "edge_bf16_tuned": ("tuned", dict(_EDGE, precision="bf16")),
+    "bulk_fp16": dict(_BULK, precision="fp16"),
+    "bulk_bf16": dict(_BULK, precision="bf16"),
+    "bulk_fp64": dict(_BULK, precision="fp64"),
+    "division_fp32_tuned": ("tuned", dict(_BULK, growth="division")),
+    "division_fp16_tuned": ("tuned", dict(_BULK, precision="fp16", growth="division")),
+    "division_density_fp32": dict(_BULK, growth="division_density"),
+    "d2q7_fp16": dict(_BULK, precision="fp16", lattice="d2q7"),
+    "d2q7_fp64": dict(_BULK, precision="fp64", lattice="d2q7"),
+}
+
+
+@pytest.mark.parametrize("name", list(_CASES))
+def test_full_size_sampled_step(name):
+    from paper_2303_02210_amd import Sim
+    case = _CASES[name]
+    cfg = _tuned(case[1]) if isinstance(case, tuple) else case
+    sim = Sim(cfg)
+    sim.step(20)
+    sim.front_heights()
+    worst = _sampled_step(sim, cfg, lambda: sim.step(1))
+    print(name, {k: cfg.get(k) for k in ("kernel_vb", "kernel_ty")}, "max |diff|", worst)
+    sim.close()
+
+
+def test_full_size_ensemble_sampled_members():
+    """The 256-replica ensemble (476 M sites) in its tuned shapes, stepped as
+    one batch: one batch step checked on the smallest, a middle and the
+    largest member."""
+    from paper_2303_02210_amd import Ensemble
+    cfgs = [_tuned(c) for c in si.ensemble()]
+    ens = Ensemble(cfgs)
+    ens.step(20)
+    ens.synchronize()
+    picks = [0, 150, len(cfgs) - 1]
+    for i in picks:
+        m = ens.members[i]
+        m.front_heights()
+    # each pick steps the whole batch once; the other picks are checked after
+    # their own batch step, from their state at that time
+    for n, i in enumerate(picks):
+        m = ens.members[i]
+        m.front_heights()
+        worst = _sampled_step(m, cfgs[i], lambda: (ens.step(1), ens.synchronize()),
+                              nsites=1000, ncols=2, seed=n)
+        print("member", i, cfgs[i]["L"], "x", cfgs[i]["H"], "max |diff|", worst)
+    ens.close()
