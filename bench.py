@@ -124,8 +124,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported in this build "
-              "(the ensemble shards with no communication; see the design notes)",
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
+              "(ensembles shard over GPUs with no communication, one process per GPU)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -52,7 +52,7 @@ typedef enum {
     LBM_E_DEVICE = -3,       /* a HIP runtime call failed                     */
     LBM_E_DOMAIN_FULL = -4,  /* the front reached the last row of the window  */
     LBM_E_NONFINITE = -5,    /* total mass became NaN or infinite             */
-    LBM_E_UNSUPPORTED = -6,  /* valid request this build does not implement   */
+    LBM_E_UNSUPPORTED = -6,  /* valid request the library does not implement */
     LBM_E_STATE = -7         /* handle is in an error state                   */
 } lbm_status;
 

@@ -121,8 +121,9 @@ def served_trace(n: int = 600, rate_hz: float = 20.0, seed: int = 0,
 # Appendix A parameters rescaled to rho_init = 1 (sigma 0.01 -> 0.1,
 # rho_cell 0.01 -> 0.1, rho0 0.15 -> 1.5; initial density uniform on
 # [0.9, 1.1] rho_init), the rear wall kept max(50, 10 w) behind the mean
-# front, the sweep window on, float32.  Heights and initial tissue rows are
-# this build's choice: room for the wall gap and a front several w rough.
+# front, the sweep window on, float32.  The paper does not give heights or
+# initial tissue rows; these leave room for the wall gap and a front several
+# w rough.
 PAPER_BASE = dict(BASE, lattice="d2q7", H=2048, init_rows=100, init_amp=0.1, sigma=0.1,
                   growth="division", growth_rate=1e-3, ybc="follow", wall_min_gap=50,
                   wall_w_factor=10.0, window=True, precision="fp32")
