@@ -267,6 +267,7 @@ struct lbm_handle {
     int64_t t = 0;
     int mode = kModeFixed;
     bool device_driven = false;
+    bool moves = false;             // the wall follows or the sweep window is on
     int err = LBM_OK;
     std::string msg = "no error";
     double Wd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -428,7 +429,7 @@ int do_step(lbm_handle *h, int64_t n)
         a.fout = reinterpret_cast<S *>(h->fbuf(h->cur ^ 1));
         a.h_prev = h->hslot(h->t);
         a.h_next = h->hslot(h->t + 1);
-        a.h_clear = h->device_driven ? nullptr : h->hslot(h->t + 2);
+        a.h_clear = h->moves ? nullptr : h->hslot(h->t + 2);
         a.t = (uint32_t)h->t;
         int rc = h->hip(l.tl.nq == 7 ? launch_step7<S>(a, grid, l.nt, l.vec ? l.vb : 0, l.rb, h->stream)
                         : l.staged ? launch_step_staged<S>(a, grid, h->stream)
@@ -436,7 +437,13 @@ int do_step(lbm_handle *h, int64_t n)
                                    : launch_step<S>(a, grid, l.nt, l.rb, h->stream),
                         "step kernel");
         if (rc) return rc;
-        if (h->device_driven) {
+        if (h->device_driven && !h->moves) {
+            // division law, wall and window fixed: only the next rate
+            rc = h->hip(launch_rates(h->p.growth, h->p.growth_rate, h->p.rho_cell, h->st(),
+                                     h->stream),
+                        "rates kernel");
+            if (rc) return rc;
+        } else if (h->device_driven) {
             fa.f = a.fout;
             fa.h_next = h->hslot(h->t + 1);
             fa.h_clear = h->hslot(h->t + 2);
@@ -605,8 +612,8 @@ int lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *hip_str
     h->lay = lay;
     // (the division laws take their rate from the previous step's tallies,
     // which the per-step finalize reduces)
-    h->device_driven = p->ybc == LBM_Y_WALL_FOLLOW || (p->flags & LBM_FLAG_WINDOW) ||
-                       p->growth >= LBM_GROWTH_DIVISION;
+    h->moves = p->ybc == LBM_Y_WALL_FOLLOW || (p->flags & LBM_FLAG_WINDOW);
+    h->device_driven = h->moves || p->growth >= LBM_GROWTH_DIVISION;
     h->mode = p->ybc == LBM_Y_PERIODIC ? kModePeriodic : (h->device_driven ? kModeDevice : kModeFixed);
     for (int i = 0; i < 9; ++i) h->Wd[i] = offset_base(p->precision, lattice_w(p)[i], p->rho_ref);
     int rc = LBM_DISPATCH(p->precision, do_init, h);
@@ -997,8 +1004,9 @@ struct lbm_batch {
 
     void drop_graph()
     {
-        if (gexec) hipGraphExecDestroy(gexec);
-        if (graph) hipGraphDestroy(graph);
+        // teardown: a failure here leaves nothing to undo
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
         gexec = nullptr;
         graph = nullptr;
         graph_n = -1;
@@ -1181,7 +1189,7 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps)
                 b->graph = g;
                 b->graph_n = nsteps;
             } else {
-                if (g) hipGraphDestroy(g);
+                if (g) (void)hipGraphDestroy(g);
                 b->gexec = nullptr;
                 (void)hipGetLastError();
             }

@@ -34,25 +34,29 @@ __global__ void state_set_kernel(DevState *st, int64_t y_wall, int64_t y_valid_t
     }
 }
 
-// Division laws: the rate of the next step from the tallies of a state set
-// from outside (its creation or lbm_set_populations); nothing is retired and
-// no division is counted.
-__global__ __launch_bounds__(kRedThreads) void rates_kernel(int growth, double g, double rho_cell,
-                                                            DevState *st)
+// Division laws: the next step's rate from the tallies in the device state's
+// slots (one lane per slot), which it clears, and the divisions they count.
+// Used after a state is set from outside (its creation or
+// lbm_set_populations: no divisions counted) and between the steps of a run
+// whose wall and sweep window stay put (nothing retired, so the rate is the
+// one the full between-step kernel would compute from the same integers).
+__global__ __launch_bounds__(kDivSlots) void rates_kernel(int growth, double g, double rho_cell,
+                                                          DevState *st)
 {
-    __shared__ long long shi[2][kRedWaves];
-    long long v[2] = {0, 0};   // fixed-point mass, weight
-    long long ndiv = 0;
-    take_div_slots(st, v[0], v[1], ndiv);
-    block_reduce(v, shi);
+    static_assert(kDivSlots == 64, "one wavefront, one lane per slot");
+    long long mfx = 0, wsum = 0, ndiv = 0;
+    take_div_slots(st, mfx, wsum, ndiv);
+    mfx = wave_reduce(mfx);
+    wsum = wave_reduce(wsum);
+    ndiv = wave_reduce(ndiv);
     if (threadIdx.x == 0)
-        set_division_rate(st, growth, division_lam(growth == kGrowthDivision, g, rho_cell, v[0], v[1]),
-                          0);
+        set_division_rate(st, growth, division_lam(growth == kGrowthDivision, g, rho_cell, mfx, wsum),
+                          ndiv);
 }
 
 hipError_t launch_rates(int growth, double g, double rho_cell, DevState *st, hipStream_t s)
 {
-    hipLaunchKernelGGL(rates_kernel, dim3(1), dim3(kRedThreads), 0, s, growth, g, rho_cell, st);
+    hipLaunchKernelGGL(rates_kernel, dim3(1), dim3(kDivSlots), 0, s, growth, g, rho_cell, st);
     return hipGetLastError();
 }
 
