@@ -610,8 +610,9 @@ int lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *hip_str
     h->ws = reinterpret_cast<char *>(dev_ws);
     h->ws_bytes = ws_bytes;
     h->lay = lay;
-    // (the division laws take their rate from the previous step's tallies,
-    // which the per-step finalize reduces)
+    // Work between steps: the full finalize when the wall or the window
+    // moves; otherwise, under a division law, only the next rate from the
+    // step's tallies (rates_kernel).
     h->moves = p->ybc == LBM_Y_WALL_FOLLOW || (p->flags & LBM_FLAG_WINDOW);
     h->device_driven = h->moves || p->growth >= LBM_GROWTH_DIVISION;
     h->mode = p->ybc == LBM_Y_PERIODIC ? kModePeriodic : (h->device_driven ? kModeDevice : kModeFixed);
