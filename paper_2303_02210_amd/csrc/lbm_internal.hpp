@@ -199,7 +199,7 @@ struct BatchRep {
     int32_t gx;             // tiles along x
     int32_t ty;             // rows per tile
     int32_t nblocks;        // tiles in all
-    int32_t device_driven;  // follow wall / sweep window / division law: finalize each step
+    int32_t device_driven;  // follow wall / sweep window: finalize each step
     int32_t window;         // sweep window: only tiles of live rows run
     int32_t last_live;      // tiles run by the last windowed launch
     int32_t pad2;
