@@ -113,10 +113,11 @@ typedef enum {
 /*
  * Model and run parameters.  Set abi_version = LBM_ABI_VERSION and
  * struct_size = sizeof(lbm_params).
- *   L, H          columns (periodic) and rows of the live window; L >= 2,
- *                 H >= 4, L * H * Q populations must fit the workspace.
- *   lattice       lbm_lattice.  D2Q7 runs the one-column-per-lane form
- *                 (kernel_vb 0 or 1) and needs an even H when periodic.
+ *   L, H          columns (periodic) and rows of the live window;
+ *                 2 <= L <= 2^24, H >= 4 and L * H * Q <= 2^31 populations
+ *                 (Q = 9 on D2Q9, 7 on D2Q7); they must fit the workspace.
+ *   lattice       lbm_lattice.  D2Q7 runs every form but the LDS-staged one
+ *                 (kernel_vb 2) and needs an even H when periodic.
  *   precision     lbm_precision.
  *   tau           relaxation time of Eq. 2, tau > 1/2.
  *   mu            friction: the steady state uses u* = (1 - mu) u (below

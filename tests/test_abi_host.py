@@ -97,6 +97,20 @@ def test_invalid_parameters_rejected_on_host(bad):
     assert rc == _ffi.E_INVALID and not h.value
 
 
+@pytest.mark.parametrize("lattice,q", [("d2q9", 9), ("d2q7", 7)])
+def test_size_limits(lattice, q):
+    """L * H * Q <= 2^31 populations and L <= 2^24: the largest lattice is
+    accepted, one row more is not, and the workspace holds both buffers."""
+    L = 16384
+    H = (1 << 31) // (q * L)
+    c = dict(si.SMALL_FP64, lattice=lattice, L=L, H=H, init_rows=8, precision="fp32")
+    n = _ws(c)
+    assert n >= 2 * q * L * H * 4
+    assert _ws(dict(c, H=H + 1)) == 0
+    assert _ws(dict(c, L=1 << 24, H=4, init_rows=2)) > 0
+    assert _ws(dict(c, L=(1 << 24) + 64, H=4, init_rows=2)) == 0
+
+
 def test_d2q7_workspace_holds_seven_populations():
     base = dict(si.BULK_4096_FP32)
     n9 = _ws(base)

@@ -46,8 +46,10 @@ def _half_ulp(prec, v):
     return 0.5 * 2.0 ** (e - _ULP_BITS[prec])
 
 
-def _sampled_step(sim, cfg, advance, nsites=3000, ncols=4, seed=0):
-    """Step once with `advance()` and check the step against the oracle."""
+def _sampled_step(sim, cfg, advance, nsites=3000, ncols=4, seed=0, extra=()):
+    """Step once with `advance()` and check the step against the oracle
+    (on sampled sites, the sites in `extra`, and every live row of sampled
+    columns)."""
     prec = cfg.get("precision", "fp32")
     f0 = sim.populations()
     h0 = sim.front_heights()
@@ -67,6 +69,7 @@ def _sampled_step(sim, cfg, advance, nsites=3000, ncols=4, seed=0):
     sites = [(int(rng.integers(0, min(H, hmax + 2))), int(rng.integers(0, L)))
              for _ in range(nsites)]
     sites += [(int(rng.integers(0, H)), int(rng.integers(0, L))) for _ in range(nsites // 6)]
+    sites += list(extra)
     cols = sorted({0, L - 1, *[int(v) for v in rng.integers(0, L, ncols)]})
     for x in cols:
         sites += [(y, x) for y in range(top)]
@@ -140,6 +143,29 @@ def test_full_size_sampled_step(name):
     sim.front_heights()
     worst = _sampled_step(sim, cfg, lambda: sim.step(1))
     print(name, {k: cfg.get(k) for k in ("kernel_vb", "kernel_ty")}, "max |diff|", worst)
+    sim.close()
+
+
+@pytest.mark.parametrize("lattice,prec", [("d2q9", "fp32"), ("d2q9", "fp64"), ("d2q7", "fp32")])
+def test_largest_lattice_sampled_step(lattice, prec):
+    """The largest lattice the library accepts (L * H * Q just under 2^31
+    populations: the highest offsets of every buffer), tissue nearly to the
+    top: one step checked on sampled sites and on the last rows and columns."""
+    from paper_2303_02210_amd import Sim
+    q = 9 if lattice == "d2q9" else 7
+    L = 16384
+    H = (1 << 31) // (q * L)
+    cfg = si.cfg(name=f"largest_{lattice}_{prec}", lattice=lattice, L=L, H=H, init_rows=H - 40,
+                 init_amp=0.1, tau=0.8, sigma=1e-3, growth_rate=1e-4, precision=prec, seed=3)
+    sim = Sim(cfg)
+    sim.step(3)
+    sim.front_heights()
+    top = H - 40
+    extra = [(y, x) for y in range(top - 6, top + 3) for x in (0, 1, L - 2, L - 1)]
+    extra += [(y, x) for y in (0, 1, H // 2) for x in (L - 2, L - 1)]
+    worst = _sampled_step(sim, cfg, lambda: sim.step(1), nsites=1500, ncols=1, seed=1,
+                          extra=extra)
+    print(cfg["name"], L, "x", H, "max |diff|", worst)
     sim.close()
 
 
