@@ -628,13 +628,10 @@ template <class S, int NT, int ND, bool VEC, bool DIV>
 __global__ __launch_bounds__(NT) void step_batch7(BatchRep<S> *const *reps, const TileRef *table,
                                                   const int32_t *count, int k)
 {
-    static_assert(sizeof(BatchRep<S>) % 4 == 0, "descriptor is staged as dwords");
-    __shared__ uint32_t stage[sizeof(BatchRep<S>) / 4];
-    const BatchRep<S> &R = *reinterpret_cast<const BatchRep<S> *>(stage);
     const int total = *count;
     for (int c = blockIdx.x; c < total; c += gridDim.x) {
         const TileRef e = table[xcd_order(c, total, 2)];
-        stage_dwords<NT>(reps[e.rep], stage, (int)(sizeof(BatchRep<S>) / 4));
+        const BatchRep<S> R = load_descriptor<BatchRep<S>>(reps[e.rep]);
         const StepIO<S> io = batch_io(&R, k);
         const int bx = e.local0 % R.gx, by = e.local0 / R.gx;
         if constexpr (VEC) step_vec_tile7<S, NT, ND, DIV>(R.a, io, bx, by, R.gx, e.n);

@@ -1789,43 +1789,48 @@ template <class S>
 __device__ __forceinline__ StepIO<S> batch_io(const BatchRep<S> *R, int k)
 {
     const int64_t tt = R->t0 + k;
-    const int cur = (R->cur0 + k) & 1;
+    const bool cur = ((R->cur0 + k) & 1) != 0;
+    // (selects, not indexing: the descriptor stays in registers)
+    const int s = (int)(tt % 3);
+    int32_t *const h0 = R->hs[0], *const h1 = R->hs[1], *const h2 = R->hs[2];
     StepIO<S> io;
-    io.fin = R->f[cur];
-    io.fout = R->f[cur ^ 1];
-    io.h_prev = R->hs[tt % 3];
-    io.h_next = R->hs[(tt + 1) % 3];
-    io.h_clear = R->device_driven ? nullptr : R->hs[(tt + 2) % 3];
+    io.fin = cur ? R->f[1] : R->f[0];
+    io.fout = cur ? R->f[0] : R->f[1];
+    io.h_prev = s == 0 ? h0 : (s == 1 ? h1 : h2);
+    io.h_next = s == 0 ? h1 : (s == 1 ? h2 : h0);
+    io.h_clear = R->device_driven ? nullptr : (s == 0 ? h2 : (s == 1 ? h0 : h1));
     io.t = (uint32_t)tt;
     return io;
 }
 
-// Copy a member descriptor from global memory into LDS (one dword per
-// thread); the tile bodies then read its fields from LDS.
-template <int NT>
-__device__ __forceinline__ void stage_dwords(const void *src, uint32_t *lds, int ndw)
+// A member descriptor, read through the constant address space: it does not
+// change while a step runs and its address is the same for the whole block,
+// so its fields are fetched by scalar loads into scalar registers, as kernel
+// arguments are (the tile bodies then need no vector registers for them).
+template <class T>
+__device__ __forceinline__ T load_descriptor(const void *p)
 {
-    const uint32_t *g = reinterpret_cast<const uint32_t *>(src);
-    lds_barrier();
-    for (int i = threadIdx.x; i < ndw; i += NT) lds[i] = g[i];
-    lds_barrier();
+    static_assert(sizeof(T) % 4 == 0, "descriptor is read as dwords");
+    using C = const __attribute__((address_space(4))) uint32_t;
+    C *src = (C *)p;
+    T out;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&out);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
+    return out;
 }
 
 // Each table entry is a run of tiles of one member stacked in y, which a
-// block updates as one tall tile after fetching the member's descriptor
-// (through LDS).  Windowed groups launch a fixed grid that strides over the
-// entries.
+// block updates as one tall tile after fetching the member's descriptor.
+// Windowed groups launch a fixed grid that strides over the entries.
 template <class S, int NT, int ND, bool VEC, bool DIV>
 __global__ __launch_bounds__(NT) void step_batch(BatchRep<S> *const *reps, const TileRef *table,
                                                  const int32_t *count, int k)
 {
-    static_assert(sizeof(BatchRep<S>) % 4 == 0, "descriptor is staged as dwords");
-    __shared__ uint32_t stage[sizeof(BatchRep<S>) / 4];
-    const BatchRep<S> &R = *reinterpret_cast<const BatchRep<S> *>(stage);
     const int total = *count;
     for (int c = blockIdx.x; c < total; c += gridDim.x) {
         const TileRef e = table[xcd_order(c, total, 2)];
-        stage_dwords<NT>(reps[e.rep], stage, (int)(sizeof(BatchRep<S>) / 4));
+        const BatchRep<S> R = load_descriptor<BatchRep<S>>(reps[e.rep]);
         const StepIO<S> io = batch_io(&R, k);
         const int bx = e.local0 % R.gx, by = e.local0 / R.gx;
         if constexpr (VEC) step_vec_tile<S, NT, ND, DIV>(R.a, io, bx, by, R.gx, e.n);
