@@ -109,6 +109,15 @@ typedef enum {
 #define LBM_FLAG_WINDOW 1u   /* sweep only rows that can hold mass: rows at or
                                 below the highest front seen plus one (the rest
                                 are exactly zero); results are unchanged      */
+#define LBM_FLAG_STOCHASTIC_ROUND 4u  /* FP16 / BF16 offset storage only: a
+                                tissue site's stored offsets are rounded
+                                stochastically (to the neighbour above their
+                                magnitude with probability equal to the
+                                distance from the one below, in ulps) instead
+                                of to nearest, so that increments smaller than
+                                half an ulp survive on average.  Draws one
+                                Philox call per tissue site (stream 3).
+                                LBM_E_INVALID with FP32 / FP64 storage.      */
 
 /*
  * Model and run parameters.  Set abi_version = LBM_ABI_VERSION and

@@ -30,6 +30,7 @@ REGION = {"all": 0, "front_band": 1, "rear_band": 2}
 YBC = {"fixed": 0, "follow": 1, "periodic": 2}
 FLAG_WINDOW = 1
 FLAG_DIVISION_MAP = 2
+FLAG_STOCHASTIC_ROUND = 4
 ST_DOMAIN_FULL = 1
 ST_NONFINITE = 2
 
@@ -142,7 +143,8 @@ def make_params(cfg: dict) -> Params:
     p.seed = int(cfg.get("seed", 0)) & 0xFFFFFFFF
     p.replica = int(cfg.get("replica", 0)) & 0xFFFFFFFF
     p.flags = (FLAG_WINDOW if cfg.get("window", False) else 0) | \
-        (FLAG_DIVISION_MAP if cfg.get("division_map", False) else 0)
+        (FLAG_DIVISION_MAP if cfg.get("division_map", False) else 0) | \
+        (FLAG_STOCHASTIC_ROUND if cfg.get("stochastic_round", False) else 0)
     p.kernel_vb = int(cfg.get("kernel_vb", 0))
     p.kernel_ty = int(cfg.get("kernel_ty", 0))
     p.rho_cell = float(cfg.get("rho_cell", 0.1))

@@ -158,7 +158,13 @@ bool params_ok(const lbm_params *p, std::string *why)
     if (p->ybc < LBM_Y_WALL_FIXED || p->ybc > LBM_Y_PERIODIC) return bad("bad ybc");
     if (p->ybc == LBM_Y_WALL_FOLLOW && (p->wall_min_gap < 0 || !(p->wall_w_factor >= 0.0)))
         return bad("bad wall follow parameters");
-    if ((p->flags & ~(LBM_FLAG_WINDOW | LBM_FLAG_DIVISION_MAP)) != 0) return bad("unknown flags");
+    if ((p->flags & ~(LBM_FLAG_WINDOW | LBM_FLAG_DIVISION_MAP | LBM_FLAG_STOCHASTIC_ROUND)) != 0)
+        return bad("unknown flags");
+    if ((p->flags & LBM_FLAG_STOCHASTIC_ROUND) &&
+        p->precision != LBM_FP16_OFFSET && p->precision != LBM_BF16_OFFSET)
+        return bad("stochastic rounding needs FP16 or BF16 offset storage");
+    if ((p->flags & LBM_FLAG_STOCHASTIC_ROUND) && p->kernel_vb == 2)
+        return bad("the LDS-staged form has no stochastic rounding");
     if (!(p->kernel_vb == 0 || p->kernel_vb == 1 || p->kernel_vb == 2 || p->kernel_vb == 4 ||
           p->kernel_vb == 8 || p->kernel_vb == 16))
         return bad("kernel_vb must be 0, 1, 2, 4, 8 or 16");
@@ -378,6 +384,7 @@ void fill_step_args(const lbm_handle *h, StepArgs<S> &a)
     a.region = p.region;
     a.region_width = p.region_width;
     a.noise = p.sigma > 0.0;
+    a.sround = (p.flags & LBM_FLAG_STOCHASTIC_ROUND) != 0;
     a.xcd_rows = 1;   // one row strip of tiles per run (measured best)
     a.seed = p.seed;
     a.replica = p.replica;
@@ -915,7 +922,7 @@ constexpr int kWindowGrid = 8192;   // blocks of a windowed group's launch
 
 struct BatchGroup {
     // kernel form; form: 0 one column per lane, 1 vector, 2 the D2Q7 step
-    int prec = 0, form = 0, nt = 0, vbrb = 0, ty = 0, windowed = 0, div = 0;
+    int prec = 0, form = 0, nt = 0, vbrb = 0, ty = 0, windowed = 0, div = 0, sr = 0;
     std::vector<lbm_handle *> m;
     int64_t tiles = 0;                           // tiles over all members
     int grid = 0;                                // blocks per step launch
@@ -969,7 +976,7 @@ hipError_t enqueue_group_step(const BatchGroup &g, int k, hipStream_t s)
                                  g.table, g.count, s);
     if (e != hipSuccess) return e;
     return launch_step_batch<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps), g.table, g.count,
-                                g.grid, g.form, g.nt, g.vbrb, g.div, k, s);
+                                g.grid, g.form, g.nt, g.vbrb, g.div, g.sr, k, s);
 }
 template <class S>
 hipError_t enqueue_group_finalize(const BatchGroup &g, int k, hipStream_t s)
@@ -1023,11 +1030,13 @@ struct lbm_batch {
             const int vbrb = h->lay.vec ? h->lay.vb : h->lay.rb;
             const int win = (h->p.flags & LBM_FLAG_WINDOW) ? 1 : 0;
             const int div = h->p.growth >= LBM_GROWTH_DIVISION ? 1 : 0;
+            const int sr = (h->p.flags & LBM_FLAG_STOCHASTIC_ROUND) ? 1 : 0;
             const int form = h->lay.tl.nq == 7 ? (h->lay.vec ? 3 : 2) : (h->lay.vec ? 1 : 0);
             BatchGroup *g = nullptr;
             for (BatchGroup &c : groups)
                 if (c.prec == h->p.precision && c.form == form && c.nt == h->lay.nt &&
-                    c.vbrb == vbrb && c.ty == h->lay.ty && c.windowed == win && c.div == div)
+                    c.vbrb == vbrb && c.ty == h->lay.ty && c.windowed == win && c.div == div &&
+                    c.sr == sr)
                     g = &c;
             if (!g) {
                 if ((int)groups.size() == kMaxGroups) return LBM_E_INVALID;
@@ -1040,6 +1049,7 @@ struct lbm_batch {
                 g->ty = h->lay.ty;
                 g->windowed = win;
                 g->div = div;
+                g->sr = sr;
             }
             g->m.push_back(h);
         }

@@ -156,7 +156,7 @@ __device__ __forceinline__ void tissue_update7(const StepArgs<S> &a, uint32_t t,
 // Steps 2-7 at one D2Q7 site from its seven streamed stored values v (fs: the
 // decoded values, validity applied).  Writes the stored result to so[7];
 // returns true for tissue.
-template <class S, bool DIV>
+template <class S, bool DIV, bool SR = false>
 __device__ __forceinline__ bool site_step7(const StepArgs<S> &a, uint32_t t, const S v[7],
                                            typename Codec<S>::R fs[7],
                                            const typename Codec<S>::R Wd[7], S so[7], uint32_t x,
@@ -170,11 +170,7 @@ __device__ __forceinline__ bool site_step7(const StepArgs<S> &a, uint32_t t, con
         R out[7];
         tissue_update7<S, DIV>(a, t, fs, rho_s, out, x, y, y_wall, hp, s_acc, x_acc, dv);
         R kept[7];
-#pragma unroll
-        for (int i = 0; i < 7; ++i) {
-            so[i] = Codec<S>::enc(out[i], Wd[i]);
-            kept[i] = Codec<S>::dec(so[i], Wd[i]);
-        }
+        encode_site<S, 7, SR>(a, t, x, y, out, Wd, so, kept);
         const R m = sum7(kept);
         m_acc += (double)m;
         if constexpr (DIV) mfx_acc += mass_fx(m);
@@ -195,7 +191,7 @@ __device__ __forceinline__ bool site_step7(const StepArgs<S> &a, uint32_t t, con
 
 // The D2Q7 step over one tile: NT columns (one per lane) by `ty` rows,
 // visited RB rows at a time with all 7 RB loads issued before any is used.
-template <class S, int NT, int RB, bool DIV>
+template <class S, int NT, int RB, bool DIV, bool SR = false>
 __device__ __forceinline__ void step_tile7(const StepArgs<S> &a, const StepIO<S> &io, int bx,
                                            int by, int nbx, int nstrips = 1)
 {
@@ -295,7 +291,7 @@ __device__ __forceinline__ void step_tile7(const StepArgs<S> &a, const StepIO<S>
             double m_site = 0.0, s_site = 0.0, x_site = 0.0;
             long long mfx_site = 0;
             DivTally dv_site = div_site(dv);
-            const bool tissue = site_step7<S, DIV>(a, io.t, v, fs, Wd, so, x, y, y_wall, hp,
+            const bool tissue = site_step7<S, DIV, SR>(a, io.t, v, fs, Wd, so, x, y, y_wall, hp,
                                                    m_site, s_site, x_site, mfx_site, dv_site);
             MemT<S> LBM_GLOBAL *rowg = G + (int64_t)s.r0 * tl.rs + cx;
             if (active) {
@@ -344,7 +340,7 @@ __device__ __forceinline__ void step_tile7(const StepArgs<S> &a, const StepIO<S>
 // pulls take the neighbouring column depends on the row's parity
 // (wave-uniform): NE and SE from x - 1 on even rows, NW and SW from x + 1 on
 // odd rows, the others from x itself.
-template <class S, int NT, int ND, bool DIV>
+template <class S, int NT, int ND, bool DIV, bool SR = false>
 __device__ __forceinline__ void step_vec_tile7(const StepArgs<S> &a, const StepIO<S> &io, int bx,
                                                int by, int nbx, int nstrips = 1)
 {
@@ -538,7 +534,7 @@ __device__ __forceinline__ void step_vec_tile7(const StepArgs<S> &a, const StepI
             for (int d = 1; d < V; ++d) hpk = (k == d) ? hp[d] : hpk;
             long long mfx_site = 0;
             DivTally dv_site = div_site(dv);
-            const bool tissue = site_step7<S, DIV>(a, io.t, v, fs, Wd, so, x, y, y_wall, hpk,
+            const bool tissue = site_step7<S, DIV, SR>(a, io.t, v, fs, Wd, so, x, y, y_wall, hpk,
                                                    m_site, s_site, x_site, mfx_site, dv_site);
 #pragma unroll
             for (int i = 0; i < 7; ++i) put_el<S, ND>(O[i], k, so[i]);
@@ -603,28 +599,28 @@ __device__ __forceinline__ void step_vec_tile7(const StepArgs<S> &a, const StepI
     }
 }
 
-template <class S, int NT, int ND, bool DIV>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vec_waves<S, ND, DIV>())))
+template <class S, int NT, int ND, bool DIV, bool SR>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vec_waves<S, ND, DIV || SR>())))
 void step_kernel_vec7(StepArgs<S> a)
 {
     const int nbx = gridDim.x;
     const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
     const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
-    step_vec_tile7<S, NT, ND, DIV>(a, io, lin % nbx, lin / nbx, nbx);
+    step_vec_tile7<S, NT, ND, DIV, SR>(a, io, lin % nbx, lin / nbx, nbx);
 }
 
-template <class S, int NT, int RB, bool DIV>
+template <class S, int NT, int RB, bool DIV, bool SR>
 __global__ __launch_bounds__(NT) void step_kernel7(StepArgs<S> a)
 {
     const int nbx = gridDim.x;
     const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
     const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
-    step_tile7<S, NT, RB, DIV>(a, io, lin % nbx, lin / nbx, nbx);
+    step_tile7<S, NT, RB, DIV, SR>(a, io, lin % nbx, lin / nbx, nbx);
 }
 
 // Batches: as step_batch, with a D2Q7 tile body (VEC: ND dwords per lane,
 // else one column per lane with ND rows' loads at once).
-template <class S, int NT, int ND, bool VEC, bool DIV>
+template <class S, int NT, int ND, bool VEC, bool DIV, bool SR>
 __global__ __launch_bounds__(NT) void step_batch7(BatchRep<S> *const *reps, const TileRef *table,
                                                   const int32_t *count, int k)
 {
@@ -634,36 +630,36 @@ __global__ __launch_bounds__(NT) void step_batch7(BatchRep<S> *const *reps, cons
         const BatchRep<S> R = load_descriptor<BatchRep<S>>(reps[e.rep]);
         const StepIO<S> io = batch_io(&R, k);
         const int bx = e.local0 % R.gx, by = e.local0 / R.gx;
-        if constexpr (VEC) step_vec_tile7<S, NT, ND, DIV>(R.a, io, bx, by, R.gx, e.n);
-        else step_tile7<S, NT, ND, DIV>(R.a, io, bx, by, R.gx, e.n);
+        if constexpr (VEC) step_vec_tile7<S, NT, ND, DIV, SR>(R.a, io, bx, by, R.gx, e.n);
+        else step_tile7<S, NT, ND, DIV, SR>(R.a, io, bx, by, R.gx, e.n);
     }
 }
 
-template <class S, int RB, bool DIV>
+template <class S, int RB, bool DIV, bool SR>
 void launch_step7_rb(const StepArgs<S> &a, dim3 grid, int nt, hipStream_t s)
 {
-    if (nt == 256) hipLaunchKernelGGL((step_kernel7<S, 256, RB, DIV>), grid, dim3(256), 0, s, a);
-    else if (nt == 128) hipLaunchKernelGGL((step_kernel7<S, 128, RB, DIV>), grid, dim3(128), 0, s, a);
-    else hipLaunchKernelGGL((step_kernel7<S, 64, RB, DIV>), grid, dim3(64), 0, s, a);
+    if (nt == 256) hipLaunchKernelGGL((step_kernel7<S, 256, RB, DIV, SR>), grid, dim3(256), 0, s, a);
+    else if (nt == 128) hipLaunchKernelGGL((step_kernel7<S, 128, RB, DIV, SR>), grid, dim3(128), 0, s, a);
+    else hipLaunchKernelGGL((step_kernel7<S, 64, RB, DIV, SR>), grid, dim3(64), 0, s, a);
 }
 
-template <class S, int ND, bool DIV>
+template <class S, int ND, bool DIV, bool SR>
 void launch_vec7_nt(const StepArgs<S> &a, dim3 grid, int nt, hipStream_t s)
 {
-    if (nt == 256) hipLaunchKernelGGL((step_kernel_vec7<S, 256, ND, DIV>), grid, dim3(256), 0, s, a);
-    else if (nt == 128) hipLaunchKernelGGL((step_kernel_vec7<S, 128, ND, DIV>), grid, dim3(128), 0, s, a);
-    else hipLaunchKernelGGL((step_kernel_vec7<S, 64, ND, DIV>), grid, dim3(64), 0, s, a);
+    if (nt == 256) hipLaunchKernelGGL((step_kernel_vec7<S, 256, ND, DIV, SR>), grid, dim3(256), 0, s, a);
+    else if (nt == 128) hipLaunchKernelGGL((step_kernel_vec7<S, 128, ND, DIV, SR>), grid, dim3(128), 0, s, a);
+    else hipLaunchKernelGGL((step_kernel_vec7<S, 64, ND, DIV, SR>), grid, dim3(64), 0, s, a);
 }
 
-template <class S, bool DIV>
+template <class S, bool DIV, bool SR>
 void launch_vec7(const StepArgs<S> &a, dim3 grid, int nt, int vb, hipStream_t s)
 {
     if (vb == 4) {
-        if constexpr (sizeof(S) <= 4) launch_vec7_nt<S, 1, DIV>(a, grid, nt, s);
+        if constexpr (sizeof(S) <= 4) launch_vec7_nt<S, 1, DIV, SR>(a, grid, nt, s);
     } else if (vb == 8) {
-        launch_vec7_nt<S, 2, DIV>(a, grid, nt, s);
+        launch_vec7_nt<S, 2, DIV, SR>(a, grid, nt, s);
     } else {
-        launch_vec7_nt<S, 4, DIV>(a, grid, nt, s);
+        launch_vec7_nt<S, 4, DIV, SR>(a, grid, nt, s);
     }
 }
 
@@ -672,18 +668,13 @@ void launch_vec7(const StepArgs<S> &a, dim3 grid, int nt, int vb, hipStream_t s)
 template <class S>
 hipError_t launch_step7(const StepArgs<S> &a, dim3 grid, int nt, int vb, int rb, hipStream_t s)
 {
-    const bool div = a.growth >= kGrowthDivision;
-    if (vb > 0) {
-        if (vb == 4 && sizeof(S) > 4) return hipErrorInvalidValue;
-        if (div) launch_vec7<S, true>(a, grid, nt, vb, s);
-        else launch_vec7<S, false>(a, grid, nt, vb, s);
-    } else if (rb >= 2) {
-        if (div) launch_step7_rb<S, 2, true>(a, grid, nt, s);
-        else launch_step7_rb<S, 2, false>(a, grid, nt, s);
-    } else {
-        if (div) launch_step7_rb<S, 1, true>(a, grid, nt, s);
-        else launch_step7_rb<S, 1, false>(a, grid, nt, s);
-    }
+    if (vb == 4 && sizeof(S) > 4) return hipErrorInvalidValue;
+    by_variant<S>(a.growth >= kGrowthDivision, a.sround != 0, [&](auto d, auto r) {
+        constexpr bool DIV = decltype(d)::value, SR = decltype(r)::value;
+        if (vb > 0) launch_vec7<S, DIV, SR>(a, grid, nt, vb, s);
+        else if (rb >= 2) launch_step7_rb<S, 2, DIV, SR>(a, grid, nt, s);
+        else launch_step7_rb<S, 1, DIV, SR>(a, grid, nt, s);
+    });
     return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
 }
 
 // Counter word 3 is 4 * stream + call.
-enum : uint32_t { kStreamNoise = 0, kStreamInit = 1, kStreamDivision = 2 };
+enum : uint32_t { kStreamNoise = 0, kStreamInit = 1, kStreamDivision = 2, kStreamRound = 3 };
 
 // Nine 24-bit draws for the noise of site (x, y) at step t: the top 24 bits of
 // the eight words of calls 0 and 1, and the low bytes of call 0's words 0-2.
@@ -179,11 +179,61 @@ struct Codec<float> {
     __device__ __forceinline__ static float enc(R f, R) { return f; }
 };
 
+// Stochastic rounding of a float32 offset o to a 16-bit storage, with r a
+// 14-bit random number: the magnitude moves to the representable neighbour
+// above it with probability equal to its distance from the one below, in
+// units of the storage's ulp, so the stored value equals o on average.  The
+// result is a float32 that the storage holds exactly.
+//   BF16: 16 mantissa bits are dropped; 4 r is added to the magnitude's bits
+//   before they are cut (probabilities exact to 2^-14).
+//   FP16, |o| >= 2^-14: 13 bits are dropped; r / 2 is added (exact).
+//   FP16, |o| < 2^-14 (subnormal, steps of 2^-24): floor(|o| 2^24 + r 2^-14).
+__device__ __forceinline__ float sround_bf16(float o, uint32_t r)
+{
+    const uint32_t b = __float_as_uint(o);
+    const uint32_t mag = ((b & 0x7FFFFFFFu) + ((r & 0x3FFFu) << 2)) & 0xFFFF0000u;
+    return __uint_as_float((b & 0x80000000u) | mag);
+}
+
+__device__ __forceinline__ float sround_f16(float o, uint32_t r)
+{
+    const uint32_t b = __float_as_uint(o);
+    uint32_t mag = b & 0x7FFFFFFFu;
+    if (mag >= 0x38800000u) {
+        mag = (mag + ((r & 0x3FFFu) >> 1)) & ~0x1FFFu;
+    } else {
+        const float m = __uint_as_float(mag) * 16777216.0f;                  // exact
+        const float q = floorf(m + (float)(r & 0x3FFFu) * (1.0f / 16384.0f));  // integer < 2^10
+        mag = __float_as_uint(q * (1.0f / 16777216.0f));                     // exact
+    }
+    return __uint_as_float((b & 0x80000000u) | mag);
+}
+
+// The fourteen-bit numbers of one site's stochastic rounding: two from each
+// word of one Philox call (bits 0-13 and 14-27) and a ninth from the four
+// words' top nibbles.
+__device__ __forceinline__ void round_bits(uint32_t seed, uint32_t replica, uint32_t t,
+                                           uint32_t x, uint32_t y, uint32_t r[9])
+{
+    const U4 a = philox10(x, y, t, 4u * kStreamRound + 0u, seed, replica);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        r[2 * k] = a.v[k] & 0x3FFFu;
+        r[2 * k + 1] = (a.v[k] >> 14) & 0x3FFFu;
+    }
+    r[8] = ((a.v[0] >> 28) | ((a.v[1] >> 28) << 4) | ((a.v[2] >> 28) << 8) |
+            ((a.v[3] >> 28) << 12)) >> 2;
+}
+
 template <>
 struct Codec<__half> {
     using R = float;
     __device__ __forceinline__ static R dec(__half s, R W) { return __half2float(s) + W; }
     __device__ __forceinline__ static __half enc(R f, R W) { return __float2half_rn(f - W); }
+    __device__ __forceinline__ static __half enc_sr(R f, R W, uint32_t r)
+    {
+        return __float2half_rn(sround_f16(f - W, r));
+    }
 };
 
 template <>
@@ -196,6 +246,10 @@ struct Codec<__hip_bfloat16> {
     __device__ __forceinline__ static __hip_bfloat16 enc(R f, R W)
     {
         return __float2bfloat16(f - W);
+    }
+    __device__ __forceinline__ static __hip_bfloat16 enc_sr(R f, R W, uint32_t r)
+    {
+        return __float2bfloat16(sround_bf16(f - W, r));
     }
 };
 

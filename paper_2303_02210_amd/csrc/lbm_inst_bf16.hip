@@ -14,7 +14,7 @@ namespace lbm {
     template hipError_t launch_mass<S>(const MassArgs<S> &, dim3, int, hipStream_t);    \
     template hipError_t launch_finalize<S>(const FinalizeArgs<S> &, hipStream_t);           \
     template hipError_t launch_step_batch<S>(BatchRep<S> *const *, const TileRef *,           \
-                                             const int32_t *, int, int, int, int, int, int, \
+                                             const int32_t *, int, int, int, int, int, int, int, \
                                              hipStream_t);                                  \
     template hipError_t launch_plan_batch<S>(BatchRep<S> *const *, int, TileRef *, int32_t *, \
                                              hipStream_t);                                  \

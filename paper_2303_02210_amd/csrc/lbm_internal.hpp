@@ -117,6 +117,7 @@ struct StepArgs {
     Tiles tl;
     int32_t mode, growth, region, region_width;
     int32_t noise;
+    int32_t sround;         // 16-bit storage: stochastic rounding of tissue sites
     int32_t xcd_rows;       // row strips per run of tiles given to one XCD (0: none)
     uint32_t t, seed, replica;
     R omega, kmu, rho_c, g, sigma;
@@ -247,7 +248,8 @@ hipError_t launch_step7(const StepArgs<S> &a, dim3 grid, int nt, int vb, int rb,
 // grid: blocks launched (each runs table entries blockIdx.x + i * grid).
 template <class S>
 hipError_t launch_step_batch(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
-                             int grid, int vec, int nt, int vb_or_rb, int div, int k, hipStream_t s);
+                             int grid, int vec, int nt, int vb_or_rb, int div, int sr, int k,
+                             hipStream_t s);
 // Rebuild the table of a windowed group from its members' live rows.
 template <class S>
 hipError_t launch_plan_batch(BatchRep<S> *const *reps, int n, TileRef *table, int32_t *count,

@@ -405,7 +405,33 @@ __device__ __forceinline__ long long mass_fx(float rho)
     return fabsf(v) < 2147483648.0f ? (long long)(int)v : mass_fx((double)rho);
 }
 
-template <class S, bool DIV>
+// A tissue site's N outputs encoded for storage (so) and the values stored
+// (kept): rounded to nearest, or (SR, 16-bit storages) stochastically with
+// the site's rounding bits.
+template <class S, int N, bool SR>
+__device__ __forceinline__ void encode_site(const StepArgs<S> &a, uint32_t t, uint32_t x,
+                                            int64_t y, const typename Codec<S>::R out[N],
+                                            const typename Codec<S>::R Wd[N], S so[N],
+                                            typename Codec<S>::R kept[N])
+{
+    if constexpr (SR && sizeof(S) == 2) {
+        uint32_t r[9];
+        round_bits(a.seed, a.replica, t, x, (uint32_t)y, r);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            so[i] = Codec<S>::enc_sr(out[i], Wd[i], r[i]);
+            kept[i] = Codec<S>::dec(so[i], Wd[i]);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            so[i] = Codec<S>::enc(out[i], Wd[i]);
+            kept[i] = Codec<S>::dec(so[i], Wd[i]);
+        }
+    }
+}
+
+template <class S, bool DIV, bool SR = false>
 __device__ __forceinline__ bool site_step(const StepArgs<S> &a, uint32_t t, const S v[9],
                                           typename Codec<S>::R fs[9], const typename Codec<S>::R Wd[9],
                                           S so[9], uint32_t x, int64_t y, int64_t y_wall, int32_t hp,
@@ -419,11 +445,7 @@ __device__ __forceinline__ bool site_step(const StepArgs<S> &a, uint32_t t, cons
         R out[9];
         tissue_update<S, DIV>(a, t, fs, rho_s, out, x, y, y_wall, hp, s_acc, x_acc, dv);
         R kept[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            so[i] = Codec<S>::enc(out[i], Wd[i]);
-            kept[i] = Codec<S>::dec(so[i], Wd[i]);
-        }
+        encode_site<S, 9, SR>(a, t, x, y, out, Wd, so, kept);
         const R m = sum9(kept);
         m_acc += (double)m;
         if constexpr (DIV) mfx_acc += mass_fx(m);
@@ -506,7 +528,7 @@ struct StepIO {
     uint32_t t;
 };
 
-template <class S, int NT, int RB, bool DIV>
+template <class S, int NT, int RB, bool DIV, bool SR = false>
 __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const StepIO<S> &io, int bx,
                                                  int by, int nbx, int nstrips = 1)
 {
@@ -606,7 +628,7 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
             double m_site = 0.0, s_site = 0.0, x_site = 0.0;
             long long mfx_site = 0;
             DivTally dv_site = div_site(dv);
-            const bool tissue = site_step<S, DIV>(a, io.t, v, fs, Wd, so, x, y, y_wall, hp, m_site,
+            const bool tissue = site_step<S, DIV, SR>(a, io.t, v, fs, Wd, so, x, y, y_wall, hp, m_site,
                                              s_site, x_site, mfx_site, dv_site);
             MemT<S> LBM_GLOBAL *rowg = G + (int64_t)s.r0 * tl.rs + cx;
             if (active) {
@@ -653,13 +675,13 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
     }
 }
 
-template <class S, int NT, int RB, bool DIV>
+template <class S, int NT, int RB, bool DIV, bool SR>
 __global__ __launch_bounds__(NT) void step_kernel(StepArgs<S> a)
 {
     const int nbx = gridDim.x;
     const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
     const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
-    step_scalar_tile<S, NT, RB, DIV>(a, io, lin % nbx, lin / nbx, nbx);
+    step_scalar_tile<S, NT, RB, DIV, SR>(a, io, lin % nbx, lin / nbx, nbx);
 }
 
 // ---------------------------------------------------------------------------
@@ -832,7 +854,7 @@ __device__ __forceinline__ S from_right(const typename RawVec<ND>::type &own, S 
 }
 
 // ND dwords per lane; WPE: waves per SIMD the register allocation aims for.
-template <class S, int NT, int ND, bool DIV>
+template <class S, int NT, int ND, bool DIV, bool SR = false>
 __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO<S> &io, int bx,
                                               int by, int nbx, int nstrips = 1)
 {
@@ -1046,7 +1068,7 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
             for (int d = 1; d < V; ++d) hpk = (k == d) ? hp[d] : hpk;
             long long mfx_site = 0;
             DivTally dv_site = div_site(dv);
-            const bool tissue = site_step<S, DIV>(a, io.t, v, fs, Wd, so, x, y, y_wall, hpk, m_site,
+            const bool tissue = site_step<S, DIV, SR>(a, io.t, v, fs, Wd, so, x, y, y_wall, hpk, m_site,
                                              s_site, x_site, mfx_site, dv_site);
 #pragma unroll
             for (int i = 0; i < 9; ++i) put_el<S, ND>(O[i], k, so[i]);
@@ -1137,14 +1159,14 @@ constexpr int vec_waves()
     else return 1;
 }
 
-template <class S, int NT, int ND, bool DIV>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vec_waves<S, ND, DIV>())))
+template <class S, int NT, int ND, bool DIV, bool SR>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vec_waves<S, ND, DIV || SR>())))
 void step_kernel_vec(StepArgs<S> a)
 {
     const int nbx = gridDim.x;
     const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
     const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
-    step_vec_tile<S, NT, ND, DIV>(a, io, lin % nbx, lin / nbx, nbx);
+    step_vec_tile<S, NT, ND, DIV, SR>(a, io, lin % nbx, lin / nbx, nbx);
 }
 
 // ---------------------------------------------------------------------------
@@ -1823,7 +1845,7 @@ __device__ __forceinline__ T load_descriptor(const void *p)
 // Each table entry is a run of tiles of one member stacked in y, which a
 // block updates as one tall tile after fetching the member's descriptor.
 // Windowed groups launch a fixed grid that strides over the entries.
-template <class S, int NT, int ND, bool VEC, bool DIV>
+template <class S, int NT, int ND, bool VEC, bool DIV, bool SR>
 __global__ __launch_bounds__(NT) void step_batch(BatchRep<S> *const *reps, const TileRef *table,
                                                  const int32_t *count, int k)
 {
@@ -1833,8 +1855,8 @@ __global__ __launch_bounds__(NT) void step_batch(BatchRep<S> *const *reps, const
         const BatchRep<S> R = load_descriptor<BatchRep<S>>(reps[e.rep]);
         const StepIO<S> io = batch_io(&R, k);
         const int bx = e.local0 % R.gx, by = e.local0 / R.gx;
-        if constexpr (VEC) step_vec_tile<S, NT, ND, DIV>(R.a, io, bx, by, R.gx, e.n);
-        else step_scalar_tile<S, NT, ND, DIV>(R.a, io, bx, by, R.gx, e.n);
+        if constexpr (VEC) step_vec_tile<S, NT, ND, DIV, SR>(R.a, io, bx, by, R.gx, e.n);
+        else step_scalar_tile<S, NT, ND, DIV, SR>(R.a, io, bx, by, R.gx, e.n);
     }
 }
 
@@ -1928,6 +1950,22 @@ __global__ void batch_advance(BatchRep<S> *const *reps, int n, int K)
     }
 }
 
+// Calls f(DIV, SR) with std::bool_constant arguments for the run's growth
+// law and rounding (stochastic rounding exists for the 16-bit storages).
+template <class S, class F>
+void by_variant(bool div, bool sr, F &&f)
+{
+    if constexpr (sizeof(S) == 2) {
+        if (sr) {
+            if (div) f(std::true_type{}, std::true_type{});
+            else f(std::false_type{}, std::true_type{});
+            return;
+        }
+    }
+    if (div) f(std::true_type{}, std::false_type{});
+    else f(std::false_type{}, std::false_type{});
+}
+
 }  // namespace lbm
 
 #include "lbm_d2q7.hpp"
@@ -1940,29 +1978,23 @@ namespace lbm {
 template <class S, int RB>
 void launch_step_rb(const StepArgs<S> &a, dim3 grid, int nt, hipStream_t s)
 {
-    if (a.growth >= kGrowthDivision) {
-        if (nt == 256) hipLaunchKernelGGL((step_kernel<S, 256, RB, true>), grid, dim3(256), 0, s, a);
-        else if (nt == 128) hipLaunchKernelGGL((step_kernel<S, 128, RB, true>), grid, dim3(128), 0, s, a);
-        else hipLaunchKernelGGL((step_kernel<S, 64, RB, true>), grid, dim3(64), 0, s, a);
-    } else {
-        if (nt == 256) hipLaunchKernelGGL((step_kernel<S, 256, RB, false>), grid, dim3(256), 0, s, a);
-        else if (nt == 128) hipLaunchKernelGGL((step_kernel<S, 128, RB, false>), grid, dim3(128), 0, s, a);
-        else hipLaunchKernelGGL((step_kernel<S, 64, RB, false>), grid, dim3(64), 0, s, a);
-    }
+    by_variant<S>(a.growth >= kGrowthDivision, a.sround != 0, [&](auto d, auto r) {
+        constexpr bool DIV = decltype(d)::value, SR = decltype(r)::value;
+        if (nt == 256) hipLaunchKernelGGL((step_kernel<S, 256, RB, DIV, SR>), grid, dim3(256), 0, s, a);
+        else if (nt == 128) hipLaunchKernelGGL((step_kernel<S, 128, RB, DIV, SR>), grid, dim3(128), 0, s, a);
+        else hipLaunchKernelGGL((step_kernel<S, 64, RB, DIV, SR>), grid, dim3(64), 0, s, a);
+    });
 }
 
 template <class S, int ND>
 void launch_vec_nt(const StepArgs<S> &a, dim3 grid, int nt, hipStream_t s)
 {
-    if (a.growth >= kGrowthDivision) {
-        if (nt == 256) hipLaunchKernelGGL((step_kernel_vec<S, 256, ND, true>), grid, dim3(256), 0, s, a);
-        else if (nt == 128) hipLaunchKernelGGL((step_kernel_vec<S, 128, ND, true>), grid, dim3(128), 0, s, a);
-        else hipLaunchKernelGGL((step_kernel_vec<S, 64, ND, true>), grid, dim3(64), 0, s, a);
-    } else {
-        if (nt == 256) hipLaunchKernelGGL((step_kernel_vec<S, 256, ND, false>), grid, dim3(256), 0, s, a);
-        else if (nt == 128) hipLaunchKernelGGL((step_kernel_vec<S, 128, ND, false>), grid, dim3(128), 0, s, a);
-        else hipLaunchKernelGGL((step_kernel_vec<S, 64, ND, false>), grid, dim3(64), 0, s, a);
-    }
+    by_variant<S>(a.growth >= kGrowthDivision, a.sround != 0, [&](auto d, auto r) {
+        constexpr bool DIV = decltype(d)::value, SR = decltype(r)::value;
+        if (nt == 256) hipLaunchKernelGGL((step_kernel_vec<S, 256, ND, DIV, SR>), grid, dim3(256), 0, s, a);
+        else if (nt == 128) hipLaunchKernelGGL((step_kernel_vec<S, 128, ND, DIV, SR>), grid, dim3(128), 0, s, a);
+        else hipLaunchKernelGGL((step_kernel_vec<S, 64, ND, DIV, SR>), grid, dim3(64), 0, s, a);
+    });
 }
 
 // vb: bytes per lane (4, 8 or 16).
@@ -2024,58 +2056,61 @@ hipError_t launch_finalize(const FinalizeArgs<S> &a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <class S, int NT, bool DIV>
+template <class S, int NT, bool DIV, bool SR>
 void launch_batch_div(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
                       int grid, int vec, int vb_or_rb, int k, hipStream_t s)
 {
     const dim3 g(grid), b(NT);
     if (vec == 2) {   // the D2Q7 step, one column per lane
         if (vb_or_rb >= 2)
-            hipLaunchKernelGGL((step_batch7<S, NT, 2, false, DIV>), g, b, 0, s, reps, table, count, k);
+            hipLaunchKernelGGL((step_batch7<S, NT, 2, false, DIV, SR>), g, b, 0, s, reps, table, count, k);
         else
-            hipLaunchKernelGGL((step_batch7<S, NT, 1, false, DIV>), g, b, 0, s, reps, table, count, k);
+            hipLaunchKernelGGL((step_batch7<S, NT, 1, false, DIV, SR>), g, b, 0, s, reps, table, count, k);
     } else if (vec == 3) {   // the D2Q7 vector form
         if (vb_or_rb == 4) {
             if constexpr (sizeof(S) <= 4)
-                hipLaunchKernelGGL((step_batch7<S, NT, 1, true, DIV>), g, b, 0, s, reps, table, count, k);
+                hipLaunchKernelGGL((step_batch7<S, NT, 1, true, DIV, SR>), g, b, 0, s, reps, table, count, k);
         } else if (vb_or_rb == 8) {
-            hipLaunchKernelGGL((step_batch7<S, NT, 2, true, DIV>), g, b, 0, s, reps, table, count, k);
+            hipLaunchKernelGGL((step_batch7<S, NT, 2, true, DIV, SR>), g, b, 0, s, reps, table, count, k);
         } else {
-            hipLaunchKernelGGL((step_batch7<S, NT, 4, true, DIV>), g, b, 0, s, reps, table, count, k);
+            hipLaunchKernelGGL((step_batch7<S, NT, 4, true, DIV, SR>), g, b, 0, s, reps, table, count, k);
         }
     } else if (vec) {
         if (vb_or_rb == 4) {
             if constexpr (sizeof(S) <= 4)
-                hipLaunchKernelGGL((step_batch<S, NT, 1, true, DIV>), g, b, 0, s, reps, table, count, k);
+                hipLaunchKernelGGL((step_batch<S, NT, 1, true, DIV, SR>), g, b, 0, s, reps, table, count, k);
         } else if (vb_or_rb == 8) {
-            hipLaunchKernelGGL((step_batch<S, NT, 2, true, DIV>), g, b, 0, s, reps, table, count, k);
+            hipLaunchKernelGGL((step_batch<S, NT, 2, true, DIV, SR>), g, b, 0, s, reps, table, count, k);
         } else {
-            hipLaunchKernelGGL((step_batch<S, NT, 4, true, DIV>), g, b, 0, s, reps, table, count, k);
+            hipLaunchKernelGGL((step_batch<S, NT, 4, true, DIV, SR>), g, b, 0, s, reps, table, count, k);
         }
     } else {
         if (vb_or_rb >= 2)
-            hipLaunchKernelGGL((step_batch<S, NT, 2, false, DIV>), g, b, 0, s, reps, table, count, k);
+            hipLaunchKernelGGL((step_batch<S, NT, 2, false, DIV, SR>), g, b, 0, s, reps, table, count, k);
         else
-            hipLaunchKernelGGL((step_batch<S, NT, 1, false, DIV>), g, b, 0, s, reps, table, count, k);
+            hipLaunchKernelGGL((step_batch<S, NT, 1, false, DIV, SR>), g, b, 0, s, reps, table, count, k);
     }
 }
 
 template <class S, int NT>
 void launch_batch_nt(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
-                     int grid, int vec, int vb_or_rb, int div, int k, hipStream_t s)
+                     int grid, int vec, int vb_or_rb, int div, int sr, int k, hipStream_t s)
 {
-    if (div) launch_batch_div<S, NT, true>(reps, table, count, grid, vec, vb_or_rb, k, s);
-    else launch_batch_div<S, NT, false>(reps, table, count, grid, vec, vb_or_rb, k, s);
+    by_variant<S>(div != 0, sr != 0, [&](auto d, auto r) {
+        launch_batch_div<S, NT, decltype(d)::value, decltype(r)::value>(reps, table, count, grid, vec,
+                                                                        vb_or_rb, k, s);
+    });
 }
 
 template <class S>
 hipError_t launch_step_batch(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
-                             int grid, int vec, int nt, int vb_or_rb, int div, int k, hipStream_t s)
+                             int grid, int vec, int nt, int vb_or_rb, int div, int sr, int k,
+                             hipStream_t s)
 {
     if (grid <= 0) return hipSuccess;
-    if (nt == 256) launch_batch_nt<S, 256>(reps, table, count, grid, vec, vb_or_rb, div, k, s);
-    else if (nt == 128) launch_batch_nt<S, 128>(reps, table, count, grid, vec, vb_or_rb, div, k, s);
-    else launch_batch_nt<S, 64>(reps, table, count, grid, vec, vb_or_rb, div, k, s);
+    if (nt == 256) launch_batch_nt<S, 256>(reps, table, count, grid, vec, vb_or_rb, div, sr, k, s);
+    else if (nt == 128) launch_batch_nt<S, 128>(reps, table, count, grid, vec, vb_or_rb, div, sr, k, s);
+    else launch_batch_nt<S, 64>(reps, table, count, grid, vec, vb_or_rb, div, sr, k, s);
     return hipGetLastError();
 }
 

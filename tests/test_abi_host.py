@@ -86,6 +86,8 @@ def test_workspace_bytes_scales_with_precision():
     dict(growth="division_density", rho0=0.5), dict(growth="division_density", rho0=0.4),
     dict(lattice="d2q7", kernel_vb=2),
     dict(lattice="d2q7", ybc="periodic", H=63, init_rows=10),
+    dict(precision="fp32", stochastic_round=True), dict(precision="fp64", stochastic_round=True),
+    dict(precision="fp16", stochastic_round=True, kernel_vb=2),
 ])
 def test_invalid_parameters_rejected_on_host(bad):
     c = dict(si.SMALL_FP64)
@@ -109,6 +111,13 @@ def test_size_limits(lattice, q):
     assert _ws(dict(c, H=H + 1)) == 0
     assert _ws(dict(c, L=1 << 24, H=4, init_rows=2)) > 0
     assert _ws(dict(c, L=(1 << 24) + 64, H=4, init_rows=2)) == 0
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("lattice", ["d2q9", "d2q7"])
+def test_stochastic_rounding_accepted_for_16_bit_storage(prec, lattice):
+    c = dict(si.SMALL_FP64, precision=prec, lattice=lattice)
+    assert _ws(dict(c, stochastic_round=True)) == _ws(c) > 0
 
 
 def test_d2q7_workspace_holds_seven_populations():

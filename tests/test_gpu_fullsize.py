@@ -46,10 +46,11 @@ def _half_ulp(prec, v):
     return 0.5 * 2.0 ** (e - _ULP_BITS[prec])
 
 
-def _sampled_step(sim, cfg, advance, nsites=3000, ncols=4, seed=0, extra=()):
+def _sampled_step(sim, cfg, advance, nsites=3000, ncols=4, seed=0, extra=(), round_ulps=0.5):
     """Step once with `advance()` and check the step against the oracle
     (on sampled sites, the sites in `extra`, and every live row of sampled
-    columns)."""
+    columns).  round_ulps: the storage rounding allowed (half an ulp to
+    nearest, one ulp stochastically)."""
     prec = cfg.get("precision", "fp32")
     f0 = sim.populations()
     h0 = sim.front_heights()
@@ -86,7 +87,7 @@ def _sampled_step(sim, cfg, advance, nsites=3000, ncols=4, seed=0, extra=()):
         ok = False
         for force in branches:
             out = orc.update_site(p, fs, t, x, y, int(h0[x]), 0, force, lam)[0][:q]
-            tol = 4e-6 * max(rho_s, 1.0) + 1e-7 + _half_ulp(prec, out - W)
+            tol = 4e-6 * max(rho_s, 1.0) + 1e-7 + 2 * round_ulps * _half_ulp(prec, out - W)
             d = np.abs(got - out)
             if np.all(d <= tol):
                 ok = True
