@@ -120,6 +120,9 @@ def main():
                     help="appb / scaling / extremes / dispersion: noise amplitude in units of "
                          "rho_init (default: the paper's 0.01 on 0.1, i.e. 0.1)")
     ap.add_argument("--tuned", action="store_true", help="launch shapes from the autotuner cache")
+    ap.add_argument("--stochastic-round", action="store_true",
+                    help="bulk / edge with fp16 / bf16 storage: round the stored offsets "
+                         "stochastically instead of to nearest")
     ap.add_argument("--shape", default=None, help="force a launch shape: kernel_vb,kernel_ty")
     args = ap.parse_args()
 
@@ -151,6 +154,8 @@ def main():
         cfg.update(growth=args.growth, name=f"{cfg['name']}_{args.growth}")
     if args.lattice != "d2q9":
         cfg.update(lattice=args.lattice, name=f"{cfg['name']}_{args.lattice}")
+    if args.stochastic_round:
+        cfg.update(stochastic_round=True, name=f"{cfg['name']}_sr")
     if args.tuned:
         from paper_2303_02210_amd import autotune
         cfg = autotune.apply(cfg)
@@ -214,6 +219,7 @@ def main():
                    "growth_rate": cfg["growth_rate"], "tau": cfg["tau"], "sigma": cfg["sigma"],
                    "init_rows": cfg["init_rows"], "h_every": every, "sweep": "full",
                    "bytes_per_update": bpu,
+                   "rounding": "stochastic" if cfg.get("stochastic_round") else "nearest",
                    "launch": {"kernel_vb": cfg.get("kernel_vb", 0),
                               "kernel_ty": cfg.get("kernel_ty", 0)}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -641,20 +647,25 @@ def bench_dispersion(args):
 
 def bench_precision(args):
     """W(L,t), mean front height and mass balance of the float32 and 16-bit
-    offset storages against float64 (bit-identical to the oracle).  (a) The
-    2048 x 8192 edge-growth strip at full size, one run per storage; (b) the
-    same model at 256 x 1024 as 8 seeds per storage, batched, for means and
-    95% intervals."""
+    offset storages (rounded to nearest, and stochastically: "_sr") against
+    float64 (bit-identical to the oracle).  (a) The 2048 x 8192 edge-growth
+    strip at full size, one run per storage; (b) the same model at
+    256 x 1024 as 8 seeds per storage, batched, for means and 95%
+    intervals."""
     import numpy as np
     import synth_inputs as si
     from paper_2303_02210_amd import Ensemble
 
-    precs = ["fp64", "fp32", "fp16", "bf16"]
+    precs = ["fp64", "fp32", "fp16", "bf16", "fp16_sr", "bf16_sr"]
+
+    def storage(p):
+        return dict(precision=p[:4], stochastic_round=p.endswith("_sr"))
+
     steps = args.steps
     every = max(100, steps // 100)
     res = {"full": {}, "seeds": {}}
     # (a) full size, all four storages in one batch
-    cfgs = [dict(si.EDGE_2048x8192, precision=p) for p in precs]
+    cfgs = [dict(si.EDGE_2048x8192, **storage(p)) for p in precs]
     ens = Ensemble(cfgs)
     log(f"precision (a): 2048x8192 x {steps} steps, {precs}")
     c = _curves(ens, steps, every, ens.synchronize)
@@ -671,13 +682,13 @@ def bench_precision(args):
             "mass_balance_drift_rel": float(np.max(np.abs(c["mass"][:, i] - m0[i])) / m0[i]),
         }
     res["full_curves"] = {"t": c["t"].tolist(), "hbar": c["hbar"].tolist(), "W": c["W"].tolist()}
-    # (b) 8 seeds x 4 storages at 256 x 1024
+    # (b) 8 seeds per storage at 256 x 1024
     nseed = 8
     small = []
     for p in precs:
         for sd in range(nseed):
             small.append(dict(si.EDGE_2048x8192, name=f"edge256_{p}_s{sd}", L=256, H=1024,
-                              init_rows=128, precision=p, seed=100 + sd, replica=sd))
+                              init_rows=128, seed=100 + sd, replica=sd, **storage(p)))
     ens = Ensemble(small)
     log(f"precision (b): 256x1024 x {steps} steps, {nseed} seeds x {precs}")
     c = _curves(ens, steps, every, ens.synchronize)
@@ -714,7 +725,7 @@ def bench_precision(args):
     summ = {k: v for k, v in res.items() if k in ("full", "seeds")}
     out = {"metric": METRIC, "value": None, "unit": None, "n_gpus": 1, "steps": steps,
            "warmup": 0, "higher_is_better": True, "vs_baseline": None, "data": "synthetic",
-           "dtype": "f64/f32/f16-offset/bf16-offset",
+           "dtype": "f64/f32/f16-offset/bf16-offset (nearest and stochastic rounding)",
            "config": {"workload": "precision_edge", "full": "2048x8192", "seeds": "8 x 256x1024",
                       "every": every},
            "accuracy": summ}
