@@ -104,6 +104,11 @@ def test_batch_members_match_solo_runs():
             for i, (p, lat) in enumerate([("fp16", "d2q9"), ("bf16", "d2q9"), ("fp16", "d2q7"),
                                           ("bf16", "d2q7")])]
     cfgs.append(dict(cfgs[0], stochastic_round=False, seed=30))
+    # a windowed member with a following wall (a group whose tile table the
+    # device rebuilds each step)
+    cfgs.append(si.cfg(L=64, H=96, init_rows=60, init_amp=0.1, sigma=1e-2, growth_rate=2e-2,
+                       rho_init=2.0, rho_ref=1.0, precision="bf16", stochastic_round=True,
+                       ybc="follow", wall_min_gap=12, wall_w_factor=2.0, window=True, seed=41))
     ens = Ensemble(cfgs)
     ens.step(7)
     ens.step(9)
