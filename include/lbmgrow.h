@@ -117,7 +117,8 @@ typedef enum {
                                 of to nearest, so that increments smaller than
                                 half an ulp survive on average.  Draws one
                                 Philox call per tissue site (stream 3).
-                                LBM_E_INVALID with FP32 / FP64 storage.      */
+                                LBM_E_INVALID with FP32 / FP64 storage or
+                                with kernel_vb 2 (the LDS-staged form).      */
 
 /*
  * Model and run parameters.  Set abi_version = LBM_ABI_VERSION and
