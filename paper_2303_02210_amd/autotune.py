@@ -32,10 +32,13 @@ def _pow2(n: int) -> int:
 
 def key(cfg: dict) -> str:
     """Storage, width and height rounded up to powers of two, and whether a
-    division law runs (its kernels hold more registers)."""
+    division law runs or the 16-bit storage rounds stochastically (those
+    kernels hold more registers)."""
     div = "/div" if str(cfg.get("growth", "bulk")).startswith("division") else ""
     lat = "/d2q7" if cfg.get("lattice", "d2q9") == "d2q7" else ""
-    return f"{cfg.get('precision', 'fp64')}/L{_pow2(int(cfg['L']))}/H{_pow2(int(cfg['H']))}{div}{lat}"
+    sr = "/sr" if cfg.get("stochastic_round", False) else ""
+    return (f"{cfg.get('precision', 'fp64')}/L{_pow2(int(cfg['L']))}/H{_pow2(int(cfg['H']))}"
+            f"{div}{lat}{sr}")
 
 
 def candidates(cfg: dict):
@@ -49,7 +52,7 @@ def candidates(cfg: dict):
     for vb in vbs:
         for ty in (1, 2, 4, 8):
             yield {"kernel_vb": vb, "kernel_ty": ty}
-    if esize != 2 or int(cfg["L"]) % 2 == 0:
+    if (esize != 2 or int(cfg["L"]) % 2 == 0) and not cfg.get("stochastic_round", False):
         for ty in (16, 32, 64):
             yield {"kernel_vb": 2, "kernel_ty": ty}
 
@@ -70,10 +73,16 @@ def cache() -> dict:
 
 def apply(cfg: dict) -> dict:
     """cfg with the tuned launch shape for its key, if one is known and the
-    dict does not set one itself."""
+    dict does not set one itself (a stochastically rounded run without a key
+    of its own takes the shape of the same run rounded to nearest, unless
+    that is the LDS-staged form, which has no stochastic rounding)."""
     if "kernel_vb" in cfg or "kernel_ty" in cfg:
         return cfg
     shape = cache().get(key(cfg))
+    if shape is None and cfg.get("stochastic_round", False):
+        shape = cache().get(key(dict(cfg, stochastic_round=False)))
+        if shape and shape.get("kernel_vb") == 2:
+            shape = None
     return dict(cfg, **shape) if shape else cfg
 
 

@@ -149,3 +149,17 @@ def test_create_rejects_bad_workspace_before_device_work():
                         ctypes.byref(h)) == _ffi.E_NOMEM
     assert L.lbm_step(None, 1) == _ffi.E_INVALID
     assert L.lbm_destroy(None) == _ffi.E_INVALID
+
+
+def test_autotune_keys_and_candidates_for_stochastic_rounding(monkeypatch):
+    from paper_2303_02210_amd import autotune
+    c = dict(si.BULK_4096_FP32, precision="fp16")
+    sr = dict(c, stochastic_round=True)
+    assert autotune.key(sr) == autotune.key(c) + "/sr"
+    assert any(s["kernel_vb"] == 2 for s in autotune.candidates(c))
+    assert not any(s["kernel_vb"] == 2 for s in autotune.candidates(sr))
+    # no key of its own: the nearest-rounding shape, unless it is the staged form
+    monkeypatch.setattr(autotune, "cache", lambda: {autotune.key(c): {"kernel_vb": 4, "kernel_ty": 2}})
+    assert autotune.apply(sr)["kernel_vb"] == 4
+    monkeypatch.setattr(autotune, "cache", lambda: {autotune.key(c): {"kernel_vb": 2, "kernel_ty": 32}})
+    assert "kernel_vb" not in autotune.apply(sr)
