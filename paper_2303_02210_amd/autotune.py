@@ -139,6 +139,8 @@ def main(argv=None):
              for p in ("fp64", "fp32", "fp16", "bf16")]
     work += [dict(si.BULK_4096_FP32, precision=p, lattice="d2q7")
              for p in ("fp64", "fp32", "fp16", "bf16")]
+    work += [dict(base, precision=p, stochastic_round=True)
+             for base in (si.BULK_4096_FP32, si.EDGE_2048x8192) for p in ("fp16", "bf16")]
     seen = set()
     for c in si.ensemble():
         if c["L"] not in seen:
