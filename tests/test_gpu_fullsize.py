@@ -131,6 +131,8 @@ _CASES = {
     "division_density_fp32": dict(_BULK, growth="division_density"),
     "d2q7_fp16": dict(_BULK, precision="fp16", lattice="d2q7"),
     "d2q7_fp64": dict(_BULK, precision="fp64", lattice="d2q7"),
+    "bulk_fp16_sr_tuned": ("tuned", dict(_BULK, precision="fp16", stochastic_round=True)),
+    "edge_bf16_sr_tuned": ("tuned", dict(_EDGE, precision="bf16", stochastic_round=True)),
 }
 
 
@@ -142,7 +144,8 @@ def test_full_size_sampled_step(name):
     sim = Sim(cfg)
     sim.step(20)
     sim.front_heights()
-    worst = _sampled_step(sim, cfg, lambda: sim.step(1))
+    ulps = 1.0 if cfg.get("stochastic_round") else 0.5
+    worst = _sampled_step(sim, cfg, lambda: sim.step(1), round_ulps=ulps)
     print(name, {k: cfg.get(k) for k in ("kernel_vb", "kernel_ty")}, "max |diff|", worst)
     sim.close()
 
