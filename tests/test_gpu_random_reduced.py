@@ -38,7 +38,7 @@ def _draw(seed):
         growth_rate=float(rng.choice([1e-3, 5e-3, 2e-2])),
         kernel_vb=int(rng.choice(vbs)), kernel_ty=int(rng.choice([0, 1, 2, 3, 5])),
         seed=int(rng.integers(0, 2 ** 31)), replica=int(rng.integers(0, 8)))
-    # a front moves at most one row per step: keep it below the top
+    # mass spreads at most one row per step, so no tissue reaches the top row
     k = min(int(rng.integers(0, 25)), H - cfg["init_rows"] - 3)
     return cfg, max(k, 0)
 
