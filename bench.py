@@ -66,7 +66,18 @@ def cpu_baseline(cfg: dict, steps: int) -> dict:
     mlups = cfg["L"] * cfg["H"] * steps / dt / 1e6
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
             "sample": f"first {steps} steps of the same {cfg['L']}x{cfg['H']} workload, "
-                      f"float64 oracle, single thread, {dt:.1f} s"}
+                      f"float64 oracle, single thread, {dt:.1f} s, on {_cpu_model()}"}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "an unidentified CPU"
 
 
 def copy_ceiling(nbytes: int, reps: int = 10) -> float:
