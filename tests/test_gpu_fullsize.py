@@ -133,6 +133,10 @@ _CASES = {
     "division_density_fp32": dict(_BULK, growth="division_density"),
     "d2q7_fp16": dict(_BULK, precision="fp16", lattice="d2q7"),
     "d2q7_fp64": dict(_BULK, precision="fp64", lattice="d2q7"),
+    "d2q7_bf16": dict(_BULK, precision="bf16", lattice="d2q7"),
+    "d2q7_division_fp32": dict(_BULK, lattice="d2q7", growth="division"),
+    "d2q7_division_density_fp64": dict(_BULK, precision="fp64", lattice="d2q7",
+                                       growth="division_density"),
     "bulk_fp16_sr_tuned": ("tuned", dict(_BULK, precision="fp16", stochastic_round=True)),
     "edge_bf16_sr_tuned": ("tuned", dict(_EDGE, precision="bf16", stochastic_round=True)),
 }
