@@ -86,21 +86,26 @@ def apply(cfg: dict) -> dict:
     return dict(cfg, **shape) if shape else cfg
 
 
-def time_shape(cfg: dict, shape: dict, steps: int = 30, warmup: int = 5) -> float:
-    """Milliseconds per step of cfg launched with shape."""
+def time_shape(cfg: dict, shape: dict, steps: int = 100, warmup: int = 10,
+               repeats: int = 2) -> float:
+    """Milliseconds per step of cfg launched with shape: the fastest of
+    `repeats` timings of `steps` steps each, after a warm-up."""
     torch = _torch()
     sim = Sim(dict(cfg, **shape))
     sim.step(warmup)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(sim.stream)
-    sim.step(steps)
-    e1.record(sim.stream)
-    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.step(steps)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) / steps)
     sim.close()
-    return e0.elapsed_time(e1) / steps
+    return best
 
 
-def tune(cfg: dict, steps: int = 30, save: str | None = USER, verbose: bool = False) -> dict:
+def tune(cfg: dict, steps: int = 100, save: str | None = USER, verbose: bool = False) -> dict:
     """Time every candidate shape for cfg and remember the fastest."""
     best, best_ms = None, float("inf")
     for shape in candidates(cfg):
@@ -131,7 +136,7 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser(description=main.__doc__)
     ap.add_argument("--out", default=USER)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=100)
     args = ap.parse_args(argv)
     work = [dict(si.BULK_4096_FP32, precision=p) for p in ("fp64", "fp32", "fp16", "bf16")]
     work += [dict(si.EDGE_2048x8192, precision=p) for p in ("fp32", "fp16", "bf16")]
