@@ -107,7 +107,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--precision", default="fp32", choices=sorted(STORE_BYTES))
     ap.add_argument("--h-every", type=int, default=100)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=600, help="served: trace length")
     ap.add_argument("--time-limit", type=float, default=300.0, help="served: wall-clock limit (s)")
