@@ -266,6 +266,9 @@ def bench_ensemble(args):
     bpu = 2 * 9 * STORE_BYTES["fp32"]
     log(f"ensemble: {len(cfgs)} replicas, {sites} sites, {K} steps each")
     ens = Ensemble(cfgs)
+    n_alone = len(ens.stepped_alone)
+    log(f"{n_alone} members of at least {ens.solo_min_sites} sites step alone, "
+        f"{len(cfgs) - n_alone} through the batch")
     ens.step(args.warmup)
     ens.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -307,7 +310,8 @@ def bench_ensemble(args):
         "data": "synthetic",
         "config": {"workload": "ensemble_256_fp32", "replicas": len(cfgs),
                    "widths": list(si.ENSEMBLE_WIDTHS), "counts": list(si.ENSEMBLE_COUNTS),
-                   "height": "4L", "sites": sites, "bytes_per_update": bpu},
+                   "height": "4L", "sites": sites, "bytes_per_update": bpu,
+                   "members_stepped_alone": n_alone},
         "roofline": {"bound": "hbm", "achieved": round(sites * bpu / (t_batch / K) / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(sites * bpu / (t_batch / K) / 1e9 / HBM_PEAK_GBS, 4),

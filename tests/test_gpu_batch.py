@@ -107,6 +107,32 @@ def test_batch_membership_changes_and_solo_steps():
     _same(mc, _solo(c, 11), "c")
 
 
+def test_large_members_step_alone_and_match():
+    """With a size threshold, members at or above it without a window step
+    by their own launches, the rest through the batch (a windowed member
+    above it stays batched); every member matches its solo run, also after
+    a member leaves, and an ensemble whose members all step alone works."""
+    from paper_2303_02210_amd import Ensemble
+    ens = Ensemble(MIXED, solo_min_sites=128 * 192)
+    members = list(ens.members)                 # in the order of MIXED
+    alone = ens.stepped_alone
+    assert {(m.cfg["L"], m.cfg["H"]) for m in alone} == {(128, 256), (256, 192)}
+    ens.step(6)
+    ens.remove(alone[0])
+    ens.step(5)
+    ens.synchronize()
+    for c, m in zip(MIXED, members):
+        _same(m, _solo(c, 6 if m is alone[0] else 11), (c["L"], c["H"]))
+    ens.close()
+    ens = Ensemble(MIXED[:2], solo_min_sites=1)
+    assert len(ens.stepped_alone) == 2
+    ens.step(4)
+    ens.synchronize()
+    for c, m in zip(MIXED[:2], ens.members):
+        _same(m, _solo(c, 4), "all alone")
+    ens.close()
+
+
 def test_batch_on_null_stream_runs_without_graph():
     import torch
     from paper_2303_02210_amd import Ensemble

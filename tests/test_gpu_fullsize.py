@@ -179,13 +179,15 @@ def test_largest_lattice_sampled_step(lattice, prec):
     sim.close()
 
 
-def test_full_size_ensemble_sampled_members():
+@pytest.mark.parametrize("solo_min_sites", [None, "default"])
+def test_full_size_ensemble_sampled_members(solo_min_sites):
     """The 256-replica ensemble (476 M sites) in its tuned shapes, stepped as
-    one batch: one batch step checked on the smallest, a middle and the
-    largest member."""
+    one batch (None) or with its large members stepped alone (the default):
+    one ensemble step checked on the smallest, a middle and the largest
+    member."""
     from paper_2303_02210_amd import Ensemble
     cfgs = [_tuned(c) for c in si.ensemble()]
-    ens = Ensemble(cfgs)
+    ens = Ensemble(cfgs) if solo_min_sites == "default" else Ensemble(cfgs, solo_min_sites=None)
     ens.step(20)
     ens.synchronize()
     picks = [0, 150, len(cfgs) - 1]
