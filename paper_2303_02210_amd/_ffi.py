@@ -12,7 +12,7 @@ import os
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "liblbmgrow.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 OK = 0
 E_INVALID, E_NOMEM, E_DEVICE, E_DOMAIN_FULL, E_NONFINITE, E_UNSUPPORTED, E_STATE = (
@@ -63,6 +63,7 @@ class Diag(ctypes.Structure):
         ("step", ctypes.c_int64), ("y_wall", ctypes.c_int64), ("h_hi", ctypes.c_int64),
         ("status", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
         ("lam", ctypes.c_double), ("divisions", ctypes.c_int64),
+        ("rows_swept", ctypes.c_int64),
     ]
 
 
@@ -84,6 +85,7 @@ _SIGS = [
     ("lbm_state_bytes", ctypes.c_size_t, [_VP]),
     ("lbm_get_state", ctypes.c_int, [_VP, _VP, ctypes.c_size_t]),
     ("lbm_set_state", ctypes.c_int, [_VP, _VP, ctypes.c_size_t]),
+    ("lbm_stream_copy", ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP]),
     ("lbm_last_error", ctypes.c_char_p, [_VP]),
     ("lbm_destroy", ctypes.c_int, [_VP]),
     ("lbm_tiles", ctypes.c_int64, [ctypes.POINTER(Params)]),
@@ -104,6 +106,14 @@ def lib() -> ctypes.CDLL:
     """Load ``liblbmgrow.so`` from the package directory (no fallback)."""
     global _lib
     if _lib is None:
+        # torch carries its own copy of the HIP runtime (same soname as the
+        # system's): load torch first so that the library binds to that one
+        # copy, or the process would hold two runtimes and torch's streams
+        # and memory would be foreign to the library's
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(
                 f"{LIB_PATH} is missing: build it first (python -c 'import __graft_entry__ as g; "
@@ -113,8 +123,26 @@ def lib() -> ctypes.CDLL:
             fn = getattr(lib_, name)
             fn.restype = res
             fn.argtypes = args
+        check_source(lib_)
         _lib = lib_
     return _lib
+
+
+def built_source_hash(lib_=None) -> str:
+    """The source hash a library reports in lbm_version() (its last word)."""
+    v = (lib_ or lib()).lbm_version().decode()
+    return v.rsplit(" ", 1)[-1]
+
+
+def check_source(lib_) -> None:
+    """Refuse a library built from other sources than the ones in this tree
+    (a stale build would otherwise run silently)."""
+    from .build import source_hash
+    got, want = built_source_hash(lib_), source_hash()
+    if got != want:
+        raise ImportError(
+            f"{LIB_PATH} was built from sources with hash {got}, but the sources in this "
+            f"tree hash to {want}: rebuild it (python paper_2303_02210_amd/build.py)")
 
 
 def make_params(cfg: dict) -> Params:

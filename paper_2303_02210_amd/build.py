@@ -1,6 +1,7 @@
 """Build the gfx950 library ``liblbmgrow.so`` in-tree with hipcc."""
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -24,22 +25,50 @@ HIPFLAGS = [
 ]
 
 
+def source_files() -> list:
+    """Every file the library is compiled from: the C ABI header and the
+    sources and headers under csrc/, in a fixed order."""
+    files = [os.path.join(ROOT, "include", "lbmgrow.h")]
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            files.append(os.path.join(CSRC, f))
+    return files
+
+
+def source_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the library's sources; the
+    library built from them reports it in lbm_version()."""
+    h = hashlib.sha256()
+    for f in source_files():
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every translation unit (in parallel) and link liblbmgrow.so."""
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every translation unit (in parallel) and link liblbmgrow.so.
+    incremental: keep the kernel objects that are newer than every source
+    (the C ABI unit, which carries the source hash, is always rebuilt)."""
     from concurrent.futures import ThreadPoolExecutor
 
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     flags = [f for f in HIPFLAGS if f != "-shared"]
+    # (the kernel units do not include the C ABI unit)
+    newest = max(os.path.getmtime(f) for f in source_files() if not f.endswith("lbm_api.cpp"))
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc(), *flags, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
+        extra = [f'-DLBM_SOURCE_HASH="{source_hash()}"'] if src == "lbm_api.cpp" else []
+        if (incremental and not extra and os.path.exists(obj)
+                and os.path.getmtime(obj) > newest):
+            return obj
+        cmd = [hipcc(), *flags, *extra, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -61,4 +90,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, incremental="-i" in sys.argv)

@@ -196,40 +196,17 @@ def test_d2q7_batch_members_match_solo_runs_bitwise():
         _same(m, _solo(c, 29), i)
 
 
-def test_full_size_4096_d2q7_fp32_sampled_parity():
+def test_full_size_4096_d2q7_fp32_whole_lattice_parity():
     """4096 x 4096 D2Q7 in its default launch shape: one step checked against
-    the oracle on sampled sites and on every row of sampled columns."""
+    one oracle step on every site and column."""
+    from tests.fullstep import whole_step
     cfg = dict(si.BULK_4096_FP32, lattice="d2q7")
     sim = _sim(cfg)
     sim.step(20)
-    f0 = sim.populations()
-    h0 = sim.front_heights()
-    t = sim.last_step
-    sim.step(1)
-    f1 = sim.populations()
-    h1 = sim.front_heights()
-    p = orc.make_params(dict(cfg, precision="fp64"))
-    rng = np.random.default_rng(0)
-    L, H = cfg["L"], cfg["H"]
-    hmax = int(h0.max())
-    sites = [(int(rng.integers(0, hmax + 2)), int(rng.integers(0, L))) for _ in range(3000)]
-    sites += [(int(rng.integers(0, H)), int(rng.integers(0, L))) for _ in range(500)]
-    cols = [0, L - 1] + [int(v) for v in rng.integers(0, L, 4)]
-    for x in cols:
-        sites += [(y, x) for y in range(0, min(H, hmax + 3))]
-    for y, x in sites:
-        fs = orc.pull_site(p, f0, x, y)
-        out, _, _, _ = orc.update_site(p, fs, t, x, y, int(h0[x]), 0, -1)
-        rho_s = fs.sum()
-        if abs(rho_s - cfg["rho_c"]) < 1e-5:
-            continue
-        assert np.max(np.abs(f1[:, y, x] - out)) <= 4e-6 * max(rho_s, 1.0) + 1e-7, (y, x)
-    for x in cols:
-        rows = [y for y in range(0, min(H, hmax + 3))
-                if orc.pull_site(p, f0, x, y).sum() >= cfg["rho_c"]]
-        assert h1[x] == (max(rows) + 1 if rows else 0)
+    stats = whole_step(sim, cfg, lambda: sim.step(1))
     d = sim.diagnostics()
-    assert np.all(f1[:, d["h_hi"] + 1:, :] == 0.0)
+    assert np.all(sim.populations()[:, d["h_hi"] + 1:, :] == 0.0)
+    print("d2q7 full-size whole-lattice step", stats)
     sim.close()
 
 

@@ -275,46 +275,42 @@ def test_reduced_precision_void_is_exactly_empty(prec):
 
 
 # ---------------------------------------------------------------- full size
-def test_full_size_4096_fp32_sampled_parity():
+def test_full_size_4096_fp32_whole_lattice_parity():
     """The throughput workload at its full size and launch configuration:
-    one step checked against the oracle on sampled sites and on every row of
-    sampled columns, plus the exact-empty void and the mass balance."""
+    one step checked against one oracle step on every site and column, plus
+    the exactly empty void."""
+    from tests.fullstep import whole_step
     cfg = dict(si.BULK_4096_FP32)
     sim = _sim(cfg)
     sim.step(20)
-    f0 = sim.populations()
-    h0 = sim.front_heights()
-    t = sim.last_step
-    sim.step(1)
-    f1 = sim.populations()
-    h1 = sim.front_heights()
-    p = orc.make_params(dict(cfg, precision="fp64"))
-    rng = np.random.default_rng(0)
-    L, H = cfg["L"], cfg["H"]
-    hmax = int(h0.max())
-    sites = [(int(rng.integers(0, hmax + 2)), int(rng.integers(0, L))) for _ in range(3000)]
-    sites += [(int(rng.integers(0, H)), int(rng.integers(0, L))) for _ in range(500)]
-    cols = [0, L - 1] + [int(v) for v in rng.integers(0, L, 4)]
-    for x in cols:
-        sites += [(y, x) for y in range(0, min(H, hmax + 3))]
-    worst = 0.0
-    for y, x in sites:
-        fs = orc.pull_site(p, f0, x, y)
-        out, tissue, _, _ = orc.update_site(p, fs, t, x, y, int(h0[x]), 0, -1)
-        rho_s = fs.sum()
-        if abs(rho_s - cfg["rho_c"]) < 1e-5:
-            continue
-        d = np.max(np.abs(f1[:, y, x] - out))
-        worst = max(worst, d)
-        assert d <= 4e-6 * max(rho_s, 1.0) + 1e-7, (y, x, d)
-    # front heights of the sampled columns from the per-row classification
-    for x in cols:
-        rows = [y for y in range(0, min(H, hmax + 3))
-                if orc.pull_site(p, f0, x, y).sum() >= cfg["rho_c"]]
-        assert h1[x] == (max(rows) + 1 if rows else 0)
+    stats = whole_step(sim, cfg, lambda: sim.step(1))
     d = sim.diagnostics()
-    assert np.all(f1[:, d["h_hi"] + 1:, :] == 0.0)
-    print("full-size sampled max |diff|", worst)
+    assert np.all(sim.populations()[:, d["h_hi"] + 1:, :] == 0.0)
+    print("full-size whole-lattice step", stats)
+    sim.close()
+
+
+def test_rows_swept_counts_the_sweep_window():
+    """lbm_diag.rows_swept: with the sweep window each step updates the rows
+    up to the highest front so far plus one (the initial rows plus two on
+    the first step); without it every step updates all H rows."""
+    cfg = si.cfg(L=64, H=96, init_rows=20, sigma=1e-2, growth_rate=3e-2, window=True,
+                 precision="fp32", seed=4)
+    sim = _sim(cfg)
+    assert sim.diagnostics()["rows_swept"] == 0
+    want, hi = 0, None
+    for k in range(60):
+        want += min(cfg["H"], cfg["init_rows"] + 2 if k == 0 else max(1, hi + 2))
+        sim.step(1)
+        d = sim.diagnostics()
+        assert d["rows_swept"] == want, (k, d["rows_swept"], want)
+        hi = d["h_hi"]
+    assert hi > cfg["init_rows"] + 2, "the front must move"
+    sim.close()
+    plain = _sim(dict(cfg, window=False))
+    plain.step(7)
+    assert plain.diagnostics()["rows_swept"] == 7 * cfg["H"]
+    plain.close()
 
 
 # ---------------------------------------------------------------- ABI behaviour
