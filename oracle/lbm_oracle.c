@@ -104,7 +104,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 }
 
 /* Random streams: the fourth counter word is 4*stream + call. */
-enum { STREAM_NOISE = 0, STREAM_INIT = 1, STREAM_DIVISION = 2 };
+enum { STREAM_NOISE = 0, STREAM_INIT = 1, STREAM_DIVISION = 2, STREAM_SELECTION = 4 };
 
 static double u24(uint32_t k24)
 {
@@ -158,6 +158,32 @@ void orc_division_draws(uint32_t seed, uint32_t replica, int64_t t, int32_t x,
     uint64_t n = ((uint64_t)(r[0] >> 6) << 26) | (uint64_t)(r[1] >> 6);
     *U_out = ((double)n + 0.5) * (1.0 / 4503599627370496.0);
     *axes_out = ((uint64_t)r[3] << 32) | (uint64_t)r[2];
+}
+
+/* The selection procedure of Sec. II (ORC_DIVISION_SELECTION): attempt a of
+ * step t is one Philox call with the attempt number in the first two counter
+ * words. */
+void orc_selection_draws(uint32_t seed, uint32_t replica, int64_t t, int64_t a,
+                         double *U_site, double *U_acc, uint32_t *axis_bits)
+{
+    uint32_t key[2] = {seed, replica};
+    uint32_t ctr[4] = {(uint32_t)a, (uint32_t)((uint64_t)a >> 32), (uint32_t)t,
+                       4u * STREAM_SELECTION + 0u};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    uint64_t n = ((uint64_t)(r[0] >> 6) << 26) | (uint64_t)(r[1] >> 6);
+    *U_site = ((double)n + 0.5) * (1.0 / 4503599627370496.0);
+    *U_acc = ((double)r[2] + 0.5) * (1.0 / 4294967296.0);
+    *axis_bits = r[3];
+}
+
+double orc_selection_round_uniform(uint32_t seed, uint32_t replica, int64_t t)
+{
+    uint32_t key[2] = {seed, replica};
+    uint32_t ctr[4] = {0u, 0u, (uint32_t)t, 4u * STREAM_SELECTION + 1u};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    return ((double)r[0] + 0.5) * (1.0 / 4294967296.0);
 }
 
 /* ----------------------------------------------------------------------- */
@@ -255,6 +281,8 @@ struct orc_state {
     double     lam;        /* division laws: lam of the next step              */
     int64_t    divisions;  /* cumulative divisions                             */
     int32_t   *divmap;     /* [H][L] divisions per window site since cleared   */
+    int32_t   *sel;        /* selection procedure: the last step's divisions,
+                              [H][L][axes] (NULL under the per-site form)    */
 };
 
 static size_t idx(const orc_params *p, int i, int32_t j, int32_t x)
@@ -441,8 +469,8 @@ static double division_lam(const orc_params *p, int64_t mfx, int64_t wsum)
 /* ----------------------------------------------------------------------- */
 static int update_site7(const orc_params *p, const double fstar_in[7], int64_t t, int32_t x,
                         int64_t y_abs, int32_t h_prev_x, int64_t y_wall, int force, double lam,
-                        double out[7], double *S_out, double *dfix_out, int32_t *ndiv_out,
-                        int64_t *wfx_out)
+                        const int32_t *given, double out[7], double *S_out, double *dfix_out,
+                        int32_t *ndiv_out, int64_t *wfx_out)
 {
     double fs[7];
     for (int i = 0; i < 7; ++i) fs[i] = fstar_in[i];
@@ -473,7 +501,18 @@ static int update_site7(const orc_params *p, const double fstar_in[7], int64_t t
     /* step 3, division laws: as on D2Q9, with three axes; each division's
      * axis is one base-3 digit of the 64 random bits */
     double q;
-    if (division_eligible(p, rho_star, in_region(p, y_abs, h_prev_x, y_wall), &q)) {
+    if (given) {
+        /* the selection procedure chose this site's divisions per axis */
+        int k = given[0] + given[1] + given[2];
+        double half = p->rho_cell * 0.5;
+        for (int a = 0; a < 3; ++a) {
+            double amount = (double)given[a] * half;
+            fs[a + 1] = fs[a + 1] + amount;
+            fs[OPP7[a + 1]] = fs[OPP7[a + 1]] + amount;
+        }
+        S = (double)k * p->rho_cell;
+        *ndiv_out = k;
+    } else if (division_eligible(p, rho_star, in_region(p, y_abs, h_prev_x, y_wall), &q)) {
         *wfx_out = division_weight(p, q);
         double l = lam * q;
         if (l > 8.0) l = 8.0;
@@ -548,14 +587,16 @@ static int update_site7(const orc_params *p, const double fstar_in[7], int64_t t
 /* ----------------------------------------------------------------------- */
 /* Steps 2-7 at one site                                                     */
 /* ----------------------------------------------------------------------- */
-int orc_update_site(const orc_params *p, const double fstar_in[9], int64_t t,
-                    int32_t x, int64_t y_abs, int32_t h_prev_x, int64_t y_wall,
-                    int force, double lam, double out[9], double *S_out,
-                    double *dfix_out, int32_t *ndiv_out, int64_t *wfx_out)
+/* given: the selection procedure's divisions of this site per axis (D2Q9:
+ * 4, D2Q7: 3 counts), or NULL for the per-site Poisson draw */
+static int update_site(const orc_params *p, const double fstar_in[9], int64_t t,
+                       int32_t x, int64_t y_abs, int32_t h_prev_x, int64_t y_wall,
+                       int force, double lam, const int32_t *given, double out[9],
+                       double *S_out, double *dfix_out, int32_t *ndiv_out, int64_t *wfx_out)
 {
     if (p->lattice == ORC_LATTICE_D2Q7)
-        return update_site7(p, fstar_in, t, x, y_abs, h_prev_x, y_wall, force, lam, out, S_out,
-                            dfix_out, ndiv_out, wfx_out);
+        return update_site7(p, fstar_in, t, x, y_abs, h_prev_x, y_wall, force, lam, given, out,
+                            S_out, dfix_out, ndiv_out, wfx_out);
     double fs[9];
     for (int i = 0; i < 9; ++i) fs[i] = fstar_in[i];
     *S_out = 0.0;
@@ -592,7 +633,19 @@ int orc_update_site(const orc_params *p, const double fstar_in[9], int64_t t,
      * site and independently, gives the same expected divisions per site;
      * lam spreads n_s over the eligible sites' total weight. */
     double q;
-    if (division_eligible(p, rho_star, in_region(p, y_abs, h_prev_x, y_wall), &q)) {
+    static const int AXIS[4] = {1, 2, 5, 6};
+    if (given) {
+        /* the selection procedure chose this site's divisions per axis */
+        int k = given[0] + given[1] + given[2] + given[3];
+        double half = p->rho_cell * 0.5;
+        for (int a = 0; a < 4; ++a) {
+            double amount = (double)given[a] * half;
+            fs[AXIS[a]] = fs[AXIS[a]] + amount;
+            fs[OPP[AXIS[a]]] = fs[OPP[AXIS[a]]] + amount;
+        }
+        S = (double)k * p->rho_cell;
+        *ndiv_out = k;
+    } else if (division_eligible(p, rho_star, in_region(p, y_abs, h_prev_x, y_wall), &q)) {
         *wfx_out = division_weight(p, q);
         double l = lam * q;
         if (l > 8.0) l = 8.0;
@@ -602,7 +655,6 @@ int orc_update_site(const orc_params *p, const double fstar_in[9], int64_t t,
             orc_division_draws(p->seed, p->replica, t, x, y_abs, &U, &axes);
             int k = orc_poisson_k(U, l);
             /* two bits per division choose the axis: 1-3, 2-4, 5-7 or 6-8 */
-            static const int AXIS[4] = {1, 2, 5, 6};
             int count[4] = {0, 0, 0, 0};
             for (int d = 0; d < k; ++d) count[(axes >> (2 * d)) & 3u] += 1;
             double half = p->rho_cell * 0.5;
@@ -664,6 +716,15 @@ int orc_update_site(const orc_params *p, const double fstar_in[9], int64_t t,
         *dfix_out = sum9(out) - before;
     }
     return 1;
+}
+
+int orc_update_site(const orc_params *p, const double fstar_in[9], int64_t t,
+                    int32_t x, int64_t y_abs, int32_t h_prev_x, int64_t y_wall,
+                    int force, double lam, double out[9], double *S_out,
+                    double *dfix_out, int32_t *ndiv_out, int64_t *wfx_out)
+{
+    return update_site(p, fstar_in, t, x, y_abs, h_prev_x, y_wall, force, lam, NULL, out, S_out,
+                       dfix_out, ndiv_out, wfx_out);
 }
 
 /* ----------------------------------------------------------------------- */
@@ -768,6 +829,11 @@ orc_state *orc_create(const orc_params *p)
     s->h = (int32_t *)calloc((size_t)p->L, sizeof(int32_t));
     s->divmap = (int32_t *)calloc((size_t)p->L * (size_t)p->H, sizeof(int32_t));
     if (!s->f || !s->fn || !s->h || !s->divmap) { orc_destroy(s); return NULL; }
+    if (division_law(p) && p->division_mode == ORC_DIVISION_SELECTION) {
+        size_t na = p->lattice == ORC_LATTICE_D2Q7 ? 3 : 4;
+        s->sel = (int32_t *)calloc((size_t)p->L * (size_t)p->H * na, sizeof(int32_t));
+        if (!s->sel) { orc_destroy(s); return NULL; }
+    }
 
     /* Appendix A initialisation: u = 0, rho uniform around rho_init in the
      * first init_rows rows, f_i = f_i^SS(rho, 0); empty above */
@@ -806,6 +872,7 @@ void orc_destroy(orc_state *s)
     free(s->fn);
     free(s->h);
     free(s->divmap);
+    free(s->sel);
     free(s);
 }
 
@@ -848,13 +915,76 @@ static void advance_wall(orc_state *s)
         if (s->h[x] < s->y_wall) s->h[x] = (int32_t)s->y_wall;
 }
 
+/* Step 3 as Sec. II states it (ORC_DIVISION_SELECTION), before any site is
+ * updated.  The streamed state's total mass m_tot gives n_s = g m_tot /
+ * rho_cell divisions (rounded to an integer stochastically: floor(n_s), plus
+ * one with probability n_s - floor(n_s), so that g m_tot is added on
+ * average).  Sites are drawn uniformly, with replacement, from the occupied
+ * sites (tissue: streamed density >= rho_c) of the proliferating region, and
+ * a drawn site divides with probability p_div: 1 for the uniform law, Eq. 5
+ * on its streamed density for the density law.  Draws go on until n_s
+ * divisions have happened; each division picks its axis at random.
+ * counts[naxes * (j * L + x) + a] receives the divisions of window site
+ * (x, j) along axis a.  Returns n_s over the occupied sites' total
+ * acceptance probability (a site's expected divisions per unit of p_div),
+ * or 0 if none may divide. */
+static double selection_divisions(orc_state *s, int32_t *counts)
+{
+    const orc_params *p = &s->p;
+    const int naxes = p->lattice == ORC_LATTICE_D2Q7 ? 3 : 4;
+    const size_t nsites = (size_t)p->L * (size_t)p->H;
+    memset(counts, 0, nsites * (size_t)naxes * sizeof(int32_t));
+    int64_t *occ = (int64_t *)malloc(nsites * sizeof(int64_t));
+    double *pdiv = (double *)malloc(nsites * sizeof(double));
+    size_t nocc = 0;
+    double m_tot = 0.0, wtot = 0.0;
+    for (int32_t j = 0; j < p->H; ++j) {
+        int64_t y_abs = s->y_wall + j;
+        for (int32_t x = 0; x < p->L; ++x) {
+            double fstar[9], q;
+            orc_pull_site_abs(p, s->f, x, j, y_abs, fstar);
+            double rho = sumq(p, fstar);
+            m_tot += rho;
+            if (rho < p->rho_c || !in_region(p, y_abs, s->h[x], s->y_wall)) continue;
+            occ[nocc] = (int64_t)j * p->L + x;
+            pdiv[nocc] = division_eligible(p, rho, 1, &q) ? q : 0.0;
+            wtot += pdiv[nocc];
+            nocc += 1;
+        }
+    }
+    double ns = p->growth_rate * m_tot / p->rho_cell;
+    double base = floor(ns);
+    int64_t n = (int64_t)base;
+    if (orc_selection_round_uniform(p->seed, p->replica, s->t) < ns - base) n += 1;
+    int64_t done = 0;
+    for (int64_t a = 0; done < n && nocc > 0 && wtot > 0.0; ++a) {
+        double Us, Ua;
+        uint32_t bits;
+        orc_selection_draws(p->seed, p->replica, s->t, a, &Us, &Ua, &bits);
+        size_t c = (size_t)(Us * (double)nocc);
+        if (c >= nocc) c = nocc - 1;
+        if (!(Ua < pdiv[c])) continue;
+        /* the axis: uniform over the lattice's axes */
+        int axis = (int)(((uint64_t)bits * (uint64_t)naxes) >> 32);
+        counts[(size_t)naxes * (size_t)occ[c] + (size_t)axis] += 1;
+        done += 1;
+    }
+    free(occ);
+    free(pdiv);
+    return wtot > 0.0 ? ns / wtot : 0.0;
+}
+
 int orc_step(orc_state *s, int64_t nsteps)
 {
     const orc_params *p = &s->p;
+    const int selection = s->sel != NULL;
+    const int naxes = p->lattice == ORC_LATTICE_D2Q7 ? 3 : 4;
+    int32_t *counts = s->sel;
     for (int64_t n = 0; n < nsteps; ++n) {
-        if (s->status & ORC_ST_DOMAIN_FULL) return -4;
+        if (s->status & ORC_ST_DOMAIN_FULL) break;
         double src = 0.0, fix = 0.0;
         int64_t wsum = 0;
+        double lam_sel = selection ? selection_divisions(s, counts) : 0.0;
         int32_t *h_new = (int32_t *)malloc((size_t)p->L * sizeof(int32_t));
         for (int32_t x = 0; x < p->L; ++x) h_new[x] = (int32_t)s->y_wall;
         for (int32_t j = 0; j < p->H; ++j) {
@@ -864,8 +994,10 @@ int orc_step(orc_state *s, int64_t nsteps)
                 int32_t ndiv;
                 int64_t wfx;
                 orc_pull_site_abs(p, s->f, x, j, y_abs, fstar);
-                int tissue = orc_update_site(p, fstar, s->t, x, y_abs, s->h[x], s->y_wall, -1,
-                                             s->lam, out, &S, &dfix, &ndiv, &wfx);
+                const int32_t *given =
+                    counts ? counts + (size_t)naxes * ((size_t)j * p->L + x) : NULL;
+                int tissue = update_site(p, fstar, s->t, x, y_abs, s->h[x], s->y_wall, -1,
+                                         s->lam, given, out, &S, &dfix, &ndiv, &wfx);
                 for (int i = 0; i < orc_q(p); ++i) s->fn[idx(p, i, j, x)] = out[i];
                 src += S;
                 fix += dfix;
@@ -889,8 +1021,13 @@ int orc_step(orc_state *s, int64_t nsteps)
         }
         /* division laws: the next step shares g m_tot / rho_cell divisions
          * over the weight of the sites eligible at this step (the sites
-         * eligible at the next step are known only as it runs) */
-        s->lam = division_lam(p, window_mass_fx(s), wsum);
+         * eligible at the next step are known only as it runs).  The
+         * selection procedure reports the mean divisions per unit weight
+         * its step used instead. */
+        if (selection)
+            s->lam = lam_sel;
+        else
+            s->lam = division_lam(p, window_mass_fx(s), wsum);
         check_front(s);
     }
     return (s->status & ORC_ST_DOMAIN_FULL) ? -4 : 0;
@@ -949,6 +1086,14 @@ void orc_set_lam(orc_state *s, double lam)
 void orc_division_map(const orc_state *s, int32_t *out)
 {
     memcpy(out, s->divmap, (size_t)s->p.L * (size_t)s->p.H * sizeof(int32_t));
+}
+
+int orc_selection_counts(const orc_state *s, int32_t *out)
+{
+    if (!s->sel) return 0;
+    size_t na = s->p.lattice == ORC_LATTICE_D2Q7 ? 3 : 4;
+    memcpy(out, s->sel, (size_t)s->p.L * (size_t)s->p.H * na * sizeof(int32_t));
+    return (int)na;
 }
 
 void orc_clear_division_map(orc_state *s)

@@ -37,6 +37,19 @@ enum { ORC_REGION_ALL = 0, ORC_REGION_FRONT_BAND = 1, ORC_REGION_REAR_BAND = 2 }
 /* boundary along the growth axis: fixed bounce-back rear wall, rear wall that
  * follows the front (Appendix A, last paragraph), or periodic (test mode) */
 enum { ORC_Y_WALL_FIXED = 0, ORC_Y_WALL_FOLLOW = 1, ORC_Y_PERIODIC = 2 };
+/* how the division laws choose their sites in step 3:
+ *   ORC_DIVISION_PER_SITE  each eligible site draws a Poisson number of
+ *                          divisions of mean lam q, lam = n_s over the total
+ *                          weight of the sites eligible at the previous step
+ *                          (the data-parallel form the GPU library computes)
+ *   ORC_DIVISION_SELECTION the procedure as Sec. II states it: n_s =
+ *                          g m_tot / rho_cell with m_tot the total mass of
+ *                          the streamed state, sites drawn uniformly with
+ *                          replacement from the occupied (tissue) sites of the
+ *                          region, each draw accepted with probability
+ *                          p_div (1, or Eq. 5), until n_s divisions happened
+ *                          (n_s rounded stochastically to an integer) */
+enum { ORC_DIVISION_PER_SITE = 0, ORC_DIVISION_SELECTION = 1 };
 /* status bits */
 enum { ORC_ST_DOMAIN_FULL = 1u, ORC_ST_NONFINITE = 2u };
 /* lattice: square D2Q9 (populations [9][H][L]) or the paper's triangular D2Q7
@@ -68,6 +81,7 @@ typedef struct {
     double   rho_cell;       /* mass of one cell (division laws), Sec. II     */
     double   rho0;           /* density above which division stops, Eq. 5     */
     int32_t  lattice;        /* ORC_LATTICE_*                                 */
+    int32_t  division_mode;  /* ORC_DIVISION_*                                */
 } orc_params;
 
 typedef struct {
@@ -98,6 +112,14 @@ void orc_noise_uniforms(uint32_t seed, uint32_t replica, int64_t t, int32_t x,
                         int64_t y_abs, double u_out[9]);
 /* Uniform of the initial-density draw at (x, y). */
 double orc_init_uniform(uint32_t seed, uint32_t replica, int32_t x, int64_t y_abs);
+
+/* Draws of the selection procedure (ORC_DIVISION_SELECTION) at step t:
+ * attempt a gives the uniform that picks the site (U_site, 52 bits), the
+ * acceptance uniform (U_acc, 32 bits) and 32 bits for the axis; the rounding
+ * of a fractional n_s uses U_round. */
+void orc_selection_draws(uint32_t seed, uint32_t replica, int64_t t, int64_t a,
+                         double *U_site, double *U_acc, uint32_t *axis_bits);
+double orc_selection_round_uniform(uint32_t seed, uint32_t replica, int64_t t);
 
 /* Division draws of one site at step t: a uniform U = (n + 1/2) 2^-52 on
  * (0, 1) from 52 random bits (the Poisson count) and 64 bits of division
@@ -164,6 +186,11 @@ void       orc_set_lam(orc_state *s, double lam);
  * since creation or the last clear; rows the wall retires leave the map. */
 void       orc_division_map(const orc_state *s, int32_t *out);
 void       orc_clear_division_map(orc_state *s);
+/* Selection procedure: the last step's divisions per window site and axis,
+ * [H][L][axes]; returns the number of axes (4 on D2Q9, 3 on D2Q7; D2Q9 axes
+ * E-W, N-S, NE-SW, NW-SE; D2Q7 E-W, NE-SW, NW-SE), or 0 (nothing written)
+ * under the per-site form. */
+int        orc_selection_counts(const orc_state *s, int32_t *out);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,9 @@ GROWTH = {"none": 0, "bulk": 1, "division": 2, "division_density": 3}
 REGION = {"all": 0, "front_band": 1, "rear_band": 2}
 YBC = {"fixed": 0, "follow": 1, "periodic": 2}
 LATTICE = {"d2q9": 0, "d2q7": 1}
+# how the division laws pick their sites: "per_site" (a Poisson count per
+# eligible site, the GPU library's form) or "selection" (Sec. II literally)
+DIVISION_MODE = {"per_site": 0, "selection": 1}
 Q = {"d2q9": 9, "d2q7": 7}
 ST_DOMAIN_FULL = 1
 ST_NONFINITE = 2
@@ -55,7 +58,7 @@ class _Params(ctypes.Structure):
         ("wall_w_factor", ctypes.c_double),
         ("seed", ctypes.c_uint32), ("replica", ctypes.c_uint32),
         ("rho_cell", ctypes.c_double), ("rho0", ctypes.c_double),
-        ("lattice", ctypes.c_int32),
+        ("lattice", ctypes.c_int32), ("division_mode", ctypes.c_int32),
     ]
 
 
@@ -103,6 +106,11 @@ def lib():
                                       ctypes.c_int64, ctypes.c_int, ctypes.c_double, dp, dp, dp,
                                       i32p, ctypes.POINTER(ctypes.c_int64)]
         L.orc_update_site.restype = ctypes.c_int
+        L.orc_selection_draws.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
+                                          ctypes.c_int64, dp, dp, u32p]
+        L.orc_selection_round_uniform.argtypes = [ctypes.c_uint32, ctypes.c_uint32,
+                                                  ctypes.c_int64]
+        L.orc_selection_round_uniform.restype = ctypes.c_double
         L.orc_division_draws.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
                                          ctypes.c_int32, ctypes.c_int64, dp,
                                          ctypes.POINTER(ctypes.c_uint64)]
@@ -124,6 +132,8 @@ def lib():
         L.orc_set_lam.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.orc_division_map.argtypes = [ctypes.c_void_p, i32p]
         L.orc_clear_division_map.argtypes = [ctypes.c_void_p]
+        L.orc_selection_counts.argtypes = [ctypes.c_void_p, i32p]
+        L.orc_selection_counts.restype = ctypes.c_int
     return _lib
 
 
@@ -155,6 +165,7 @@ def make_params(cfg: dict) -> _Params:
     p.rho_cell = float(cfg.get("rho_cell", 0.1))
     p.rho0 = float(cfg.get("rho0", 1.5))
     p.lattice = LATTICE[cfg.get("lattice", "d2q9")]
+    p.division_mode = DIVISION_MODE[cfg.get("division_mode", "per_site")]
     return p
 
 
@@ -194,6 +205,19 @@ def division_draws(seed, replica, t, x, y):
     ax = ctypes.c_uint64()
     lib().orc_division_draws(seed, replica, t, x, y, ctypes.byref(U), ctypes.byref(ax))
     return U.value, ax.value
+
+
+def selection_draws(seed, replica, t, a):
+    """(U_site, U_acc, axis_bits) of attempt a of the selection procedure."""
+    us, ua = ctypes.c_double(), ctypes.c_double()
+    bits = ctypes.c_uint32()
+    lib().orc_selection_draws(seed, replica, t, a, ctypes.byref(us), ctypes.byref(ua),
+                              ctypes.byref(bits))
+    return us.value, ua.value, bits.value
+
+
+def selection_round_uniform(seed, replica, t) -> float:
+    return float(lib().orc_selection_round_uniform(seed, replica, t))
 
 
 def exp_neg(lam: float) -> float:
@@ -318,6 +342,14 @@ class Oracle:
 
     def set_lam(self, lam: float) -> None:
         lib().orc_set_lam(self._h, float(lam))
+
+    def selection_counts(self) -> np.ndarray:
+        """The selection procedure's divisions of the last step, [H][L][axes]."""
+        na = 3 if self.p.lattice == LATTICE["d2q7"] else 4
+        out = np.zeros((self.H, self.L, na), np.int32)
+        if lib().orc_selection_counts(self._h, _ptr(out, ctypes.c_int32)) == 0:
+            raise ValueError("not a selection-procedure run")
+        return out
 
     def division_map(self, clear: bool = False) -> np.ndarray:
         out = np.zeros((self.H, self.L), np.int32)
