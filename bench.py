@@ -69,6 +69,59 @@ def cpu_baseline(cfg: dict, steps: int) -> dict:
                       f"float64 oracle, single thread, {dt:.1f} s, on {_cpu_model()}"}
 
 
+# One host process of the all-cores baseline: builds its oracle, reports
+# "ready", waits for "go" on stdin, steps and prints its elapsed seconds.
+_CPU_WORKER = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+from oracle import oracle as orc
+cfg, steps = json.loads(sys.argv[2]), int(sys.argv[3])
+o = orc.Oracle(cfg)
+print("ready", flush=True)
+sys.stdin.readline()
+t0 = time.perf_counter()
+o.step(steps)
+print(time.perf_counter() - t0, flush=True)
+"""
+
+
+def host_cores() -> int:
+    """Cores this process may use, at most 16 (one GPU's share of its host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline_all_cores(cfg: dict, steps: int, procs: int) -> dict:
+    """The same single-threaded oracle on every host core at once: `procs`
+    independent processes (each its own copy of the workload, as independent
+    runs on a host share it), started together; throughput = all their site
+    updates over the slowest one's time."""
+    import subprocess
+    c = dict(cfg, precision="fp64")
+    c = {k: v for k, v in c.items() if isinstance(v, (int, float, str, bool))}
+    ps = [subprocess.Popen([sys.executable, "-c", _CPU_WORKER, ROOT, json.dumps(c), str(steps)],
+                           stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True)
+          for _ in range(procs)]
+    for p in ps:
+        if p.stdout.readline().strip() != "ready":
+            raise RuntimeError("oracle worker failed to start")
+    for p in ps:
+        p.stdin.write("go\n")
+        p.stdin.flush()
+    times = [float(p.stdout.readline()) for p in ps]
+    for p in ps:
+        p.wait()
+    dt = max(times)
+    mlups = procs * cfg["L"] * cfg["H"] * steps / dt / 1e6
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": procs, "kind": "oracle",
+            "sample": f"{procs} concurrent single-threaded oracle processes, each the first "
+                      f"{steps} steps of the same {cfg['L']}x{cfg['H']} workload in float64; "
+                      f"slowest {dt:.1f} s, fastest {min(times):.1f} s, on {_cpu_model()}"}
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -80,24 +133,46 @@ def _cpu_model() -> str:
     return "an unidentified CPU"
 
 
-def copy_ceiling(nbytes: int, reps: int = 10) -> float:
-    """GB/s of a plain device-to-device copy moving nbytes (read + write) per
-    call: the practical HBM ceiling to compare the step kernel with."""
+def copy_ceiling(nbytes: int, reps: int = 10) -> dict:
+    """Device copies moving nbytes (half read, half written) per call: the
+    runtime's device-to-device copy (torch's copy_) and the library's
+    streaming copy kernel (16-byte nontemporal loads and stores).  The faster
+    is the practical HBM ceiling the step kernel is compared with."""
+    import ctypes
     import torch
-    half = nbytes // 2
+    from paper_2303_02210_amd import _ffi
+    half = (nbytes // 2) // 16 * 16
     src = torch.empty(half // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    dt = e0.elapsed_time(e1) / 1e3 / reps
+    stream = torch.cuda.current_stream()
+    lib = _ffi.lib()
+
+    def kernel_copy():
+        rc = lib.lbm_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                 half, ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise _ffi.LbmError(rc, "lbm_stream_copy")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / 1e3 / reps)
+        return 2 * half / best / 1e9
+
+    memcpy = timed(lambda: dst.copy_(src))
+    kern = timed(kernel_copy)
+    assert torch.equal(dst, src)
     del src, dst
-    return 2 * half / dt / 1e9
+    return {"memcpy_gbs": round(memcpy, 1), "stream_copy_kernel_gbs": round(kern, 1),
+            "ceiling_gbs": round(max(memcpy, kern), 1)}
 
 
 def main():
@@ -108,7 +183,19 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=sorted(STORE_BYTES))
     ap.add_argument("--h-every", type=int, default=100)
     ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--cpu-all-steps", type=int, default=6,
+                    help="steps per process of the all-cores CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="bulk: skip the 256-replica ensemble figures")
+    ap.add_argument("--ensemble-steps", type=int, default=200,
+                    help="bulk: steps of the ensemble figures (batched and sequential)")
+    ap.add_argument("--no-served", action="store_true",
+                    help="bulk: skip the served-trace figures")
+    ap.add_argument("--served-requests", type=int, default=40,
+                    help="bulk: arrivals of the short served trace")
+    ap.add_argument("--served-time-limit", type=float, default=90.0,
+                    help="bulk: wall-clock limit of each served-trace run (s)")
     ap.add_argument("--requests", type=int, default=600, help="served: trace length")
     ap.add_argument("--time-limit", type=float, default=300.0, help="served: wall-clock limit (s)")
     ap.add_argument("--no-sequential", action="store_true",
@@ -131,6 +218,8 @@ def main():
                     help="appb / scaling / extremes / dispersion: noise amplitude in units of "
                          "rho_init (default: the paper's 0.01 on 0.1, i.e. 0.1)")
     ap.add_argument("--tuned", action="store_true", help="launch shapes from the autotuner cache")
+    ap.add_argument("--all-batched", action="store_true",
+                    help="ensemble: step every member through the batch (no solo members)")
     ap.add_argument("--stochastic-round", action="store_true",
                     help="bulk / edge with fp16 / bf16 storage: round the stored offsets "
                          "stochastically instead of to nearest")
@@ -218,8 +307,12 @@ def main():
     alg_bytes = L * H * bpu
     achieved = alg_bytes / per_launch_s / 1e9
     traffic = measured_traffic(cfg["name"], args.precision)
-    ceiling = copy_ceiling(alg_bytes)
-    log(f"step kernel {achieved:.0f} GB/s; device copy of the same bytes {ceiling:.0f} GB/s")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    copies = copy_ceiling(alg_bytes)
+    ceiling = copies["ceiling_gbs"]
+    log(f"step kernel {achieved:.0f} GB/s; copies of the same bytes: {copies}")
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1,
         "steps": K, "warmup": args.warmup, "ms_per_step": round(total_ms / K, 5),
@@ -238,38 +331,48 @@ def main():
                      "traffic": traffic,
                      "kernel": "step_kernel", "bytes_per_launch": alg_bytes,
                      "launch_ms": round(per_launch_s * 1e3, 5),
-                     "copy_ceiling_gbs": round(ceiling, 1),
+                     "copy": copies,
+                     "copy_ceiling_gbs": ceiling,
                      "frac_of_copy": round(achieved / ceiling, 4)},
         "cpu_baseline": None,
     }
-    sim.close()
+    if args.workload == "bulk" and not args.no_ensemble:
+        out["ensemble"] = run_ensemble(args.ensemble_steps, 10, tuned=True,
+                                       sequential=not args.no_sequential)
+    if args.workload == "bulk" and not args.no_served:
+        out["served"] = run_served(args.served_requests, args.served_time_limit, tuned=True,
+                                   sequential=not args.no_sequential)
     if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle, {args.cpu_steps} steps ...")
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+        log(f"cpu baseline: oracle, {args.cpu_steps} steps, one thread ...")
+        single = cpu_baseline(cfg, args.cpu_steps)
+        procs = host_cores()
+        log(f"cpu baseline: oracle, {args.cpu_all_steps} steps, {procs} processes ...")
+        out["cpu_baseline"] = dict(cpu_baseline_all_cores(cfg, args.cpu_all_steps, procs),
+                                   single_thread=single)
     print(json.dumps(out), flush=True)
 
 
-def bench_ensemble(args):
+def run_ensemble(K: int, warmup: int, tuned: bool = True, sequential: bool = True,
+                 solo_min_sites="default") -> dict:
     """256 replicas (widths 128..2048 with 96/64/48/32/16 copies, height 4L,
-    bulk growth 1e-4, noise 1e-3, float32) advanced together by the batch API,
+    bulk growth 1e-4, noise 1e-3, float32) advanced together for K steps,
     against the same runs stepped one after another on their own."""
     import torch
     import synth_inputs as si
     from paper_2303_02210_amd import Ensemble, Sim
 
     cfgs = si.ensemble()
-    if args.tuned:
+    if tuned:
         from paper_2303_02210_amd import autotune
         cfgs = [autotune.apply(c) for c in cfgs]
-    K = args.steps
     sites = sum(c["L"] * c["H"] for c in cfgs)
     bpu = 2 * 9 * STORE_BYTES["fp32"]
     log(f"ensemble: {len(cfgs)} replicas, {sites} sites, {K} steps each")
-    ens = Ensemble(cfgs)
+    ens = Ensemble(cfgs) if solo_min_sites == "default" else \
+        Ensemble(cfgs, solo_min_sites=solo_min_sites)
     n_alone = len(ens.stepped_alone)
-    log(f"{n_alone} members of at least {ens.solo_min_sites} sites step alone, "
-        f"{len(cfgs) - n_alone} through the batch")
-    ens.step(args.warmup)
+    log(f"{n_alone} members step alone, {len(cfgs) - n_alone} through the batch")
+    ens.step(warmup)
     ens.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(ens.stream)
@@ -290,9 +393,9 @@ def bench_ensemble(args):
     log(f"batched: {t_batch:.3f} s; mean W {sum(W) / len(W):.3f}")
     # the same runs, one after another, each on its own
     t_seq = 0.0
-    for c in ([] if args.no_sequential else cfgs):
+    for c in (cfgs if sequential else []):
         sim = Sim(c)
-        sim.step(args.warmup)
+        sim.step(warmup)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(sim.stream)
         sim.step(K)
@@ -300,78 +403,108 @@ def bench_ensemble(args):
         torch.cuda.synchronize()
         t_seq += a.elapsed_time(b) / 1e3
         sim.close()
-    log(f"sequential: {t_seq:.3f} s")
-    mlups = sites * K / t_batch / 1e6
+    if sequential:
+        log(f"sequential: {t_seq:.3f} s")
     full_steps = si.ensemble()[0]["steps"]
-    out = {
-        "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": K,
-        "warmup": args.warmup, "ms_per_step": round(t_batch / K * 1e3, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "ensemble_256_fp32", "replicas": len(cfgs),
-                   "widths": list(si.ENSEMBLE_WIDTHS), "counts": list(si.ENSEMBLE_COUNTS),
-                   "height": "4L", "sites": sites, "bytes_per_update": bpu,
-                   "members_stepped_alone": n_alone},
-        "roofline": {"bound": "hbm", "achieved": round(sites * bpu / (t_batch / K) / 1e9, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(sites * bpu / (t_batch / K) / 1e9 / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+    gbs = sites * bpu / (t_batch / K) / 1e9
+    return {
+        "workload": "ensemble_256_fp32", "replicas": len(cfgs),
+        "widths": list(si.ENSEMBLE_WIDTHS), "counts": list(si.ENSEMBLE_COUNTS),
+        "height": "4L", "sites": sites, "steps": K, "bytes_per_update": bpu,
+        "members_stepped_alone": n_alone,
+        "mlups": round(sites * K / t_batch / 1e6, 1), "ms_per_step": round(t_batch / K * 1e3, 4),
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)},
         "runs_per_hour": round(len(cfgs) / (t_batch * full_steps / K) * 3600, 1),
         "sequential": None if not t_seq else {
-            "value": round(sites * K / t_seq / 1e6, 1), "unit": "MLUPS",
+            "mlups": round(sites * K / t_seq / 1e6, 1),
             "runs_per_hour": round(len(cfgs) / (t_seq * full_steps / K) * 3600, 1)},
         "speedup_vs_sequential": round(t_seq / t_batch, 3) if t_seq else None,
-        "cpu_baseline": None,
+        "mean_W": round(sum(W) / len(W), 4),
+    }
+
+
+def bench_ensemble(args):
+    """The ensemble on its own JSON line."""
+    e = run_ensemble(args.steps, args.warmup, tuned=args.tuned, sequential=not args.no_sequential,
+                     solo_min_sites=None if args.all_batched else "default")
+    out = {
+        "metric": METRIC, "value": e["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": e["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {k: e[k] for k in ("workload", "replicas", "widths", "counts", "height",
+                                     "sites", "bytes_per_update", "members_stepped_alone")},
+        "roofline": dict(e["roofline"], traffic=None),
+        "runs_per_hour": e["runs_per_hour"], "sequential": e["sequential"],
+        "speedup_vs_sequential": e["speedup_vs_sequential"], "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 
 
-def bench_served(args):
+def run_served(n: int, time_limit: float, tuned: bool = True, sequential: bool = True) -> dict:
     """Poisson arrivals at 20 requests/s of runs with L in {128..4096}, H in
     [2L, 4L], 1000-50000 steps, bulk or front-band growth, FP64 / FP32 /
     FP16-offset; admitted by HBM footprint into the running batch; rear wall
-    following the front; front heights streamed back every tick."""
+    following the front; only live rows swept; front heights streamed back
+    every tick.  Throughput counts the rows actually swept (active MLUPS);
+    its roofline fraction is their algorithmic bytes over the GPU-busy time."""
+    import torch
     import synth_inputs as si
-    from paper_2303_02210_amd.serve import Server
+    from paper_2303_02210_amd.serve import Server, serve_sequential
 
-    reqs = si.served_trace(n=args.requests)
-    if args.tuned:
+    reqs = si.served_trace(n=n)
+    if tuned:
         from paper_2303_02210_amd import autotune
         reqs = [autotune.apply(c) for c in reqs]
     srv = Server(hbm_budget=200e9, tick_steps=100)
-    summ = srv.serve(reqs, time_limit=args.time_limit, log=log)
+    summ = srv.serve(reqs, time_limit=time_limit, log=log)
     srv.close()
     log(json.dumps(summ))
     seq = None
-    if not args.no_sequential:
-        # the same trace through a plain queue: one run at a time, alone
-        import torch
-        from paper_2303_02210_amd.serve import serve_sequential
+    if sequential:
         torch.cuda.empty_cache()
-        seq = serve_sequential(reqs, time_limit=args.time_limit, tick_steps=100, log=log)
+        seq = serve_sequential(reqs, time_limit=time_limit, tick_steps=100, log=log)
         log("sequential: " + json.dumps(seq))
+
+    def figures(sm):
+        gbs = sm["active_bytes"] / sm["gpu_busy_s"] / 1e9 if sm["gpu_busy_s"] > 0 else 0.0
+        return {"runs_per_hour": round(sm["runs_per_hour"], 1), "completed": sm["completed"],
+                "unfinished": sm["running"] + sm["queued"],
+                "p50_latency_s": sm["p50_latency_s"], "p99_latency_s": sm["p99_latency_s"],
+                "mlups_active": round(sm["mlups_active"], 1),
+                "mlups_active_busy": round(sm["mlups_active_busy"], 1),
+                "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "over": "GPU-busy time, swept rows only"},
+                "gpu_busy_frac": round(sm["gpu_busy_frac"], 4), "wall_s": round(sm["wall_s"], 2)}
+
+    out = {"workload": f"served_poisson20_{n}", "requests": n, "rate_hz": 20.0,
+           "widths": [128, 256, 512, 1024, 2048, 4096], "steps_range": [1000, 50000],
+           "wall": "follow", "sweep": "window", "hbm_budget_bytes": 200e9, "tick_steps": 100,
+           "time_limit_s": time_limit}
+    out.update(figures(summ))
+    out["sequential"] = None if seq is None else figures(seq)
+    out["speedup_vs_sequential"] = (None if seq is None or not seq["runs_per_hour"] else
+                                    round(summ["runs_per_hour"] / seq["runs_per_hour"], 3))
+    return out
+
+
+def bench_served(args):
+    """The served trace on its own JSON line."""
+    sv = run_served(args.requests, args.time_limit, tuned=args.tuned,
+                    sequential=not args.no_sequential)
     out = {
-        "metric": METRIC, "value": round(summ["runs_per_hour"], 1), "unit": "runs/hour",
+        "metric": METRIC, "value": sv["runs_per_hour"], "unit": "runs/hour",
         "n_gpus": 1, "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "mixed f64/f32/f16-offset",
         "data": "synthetic",
-        "config": {"workload": f"served_poisson20_{args.requests}", "requests": args.requests,
-                   "rate_hz": 20.0, "widths": [128, 256, 512, 1024, 2048, 4096],
-                   "steps_range": [1000, 50000], "wall": "follow", "sweep": "window",
-                   "hbm_budget_bytes": 200e9, "tick_steps": 100,
-                   "time_limit_s": args.time_limit},
-        "p50_latency_s": summ["p50_latency_s"], "p99_latency_s": summ["p99_latency_s"],
-        "completed": summ["completed"], "unfinished": summ["running"] + summ["queued"],
-        "mlups_nominal": round(summ["mlups_nominal"], 1),
-        "gpu_busy_frac": round(summ["gpu_busy_frac"], 4), "wall_s": round(summ["wall_s"], 2),
-        "sequential": None if seq is None else {
-            "runs_per_hour": round(seq["runs_per_hour"], 1), "completed": seq["completed"],
-            "p50_latency_s": seq["p50_latency_s"], "p99_latency_s": seq["p99_latency_s"],
-            "mlups_nominal": round(seq["mlups_nominal"], 1), "wall_s": round(seq["wall_s"], 2)},
-        "speedup_vs_sequential": None if seq is None or not seq["runs_per_hour"] else
-            round(summ["runs_per_hour"] / seq["runs_per_hour"], 3),
-        "roofline": None, "cpu_baseline": None,
+        "config": {k: sv[k] for k in ("workload", "requests", "rate_hz", "widths", "steps_range",
+                                      "wall", "sweep", "hbm_budget_bytes", "tick_steps",
+                                      "time_limit_s")},
+        "cpu_baseline": None,
     }
+    out.update({k: v for k, v in sv.items() if k not in out["config"]})
     print(json.dumps(out), flush=True)
 
 

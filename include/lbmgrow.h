@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 3u
+#define LBM_ABI_VERSION 4u
 
 typedef struct lbm_handle lbm_handle;
 typedef struct lbm_batch lbm_batch;
@@ -212,12 +212,18 @@ typedef struct {
     uint32_t reserved;
     double   lam;         /* division laws: lam of the next step              */
     int64_t  divisions;   /* division laws: cell divisions since creation     */
+    int64_t  rows_swept;  /* window rows updated since creation: L * rows_swept
+                             site updates (H per step without the sweep
+                             window, fewer with it)                           */
 } lbm_diag;
 
 #define LBM_ST_DOMAIN_FULL 1u
 #define LBM_ST_NONFINITE   2u
 
-/* Library version string, e.g. "lbmgrow 1.0 gfx950". */
+/* Library version string, e.g. "lbmgrow 1.1 gfx950 src 0123456789abcdef":
+ * the last word is the first 16 hex digits of the SHA-256 of the sources
+ * the library was compiled from (this header and the kernel and host
+ * sources), so a build can be matched to its source tree. */
 const char *lbm_version(void);
 
 /* Device workspace size for p; 0 if p is invalid. */
@@ -275,6 +281,14 @@ int lbm_division_map(lbm_handle *h, int32_t *host_counts, int clear);
 size_t lbm_state_bytes(const lbm_handle *h);
 int lbm_get_state(lbm_handle *h, void *host_blob, size_t bytes);
 int lbm_set_state(lbm_handle *h, const void *host_blob, size_t bytes);
+
+/* Bandwidth reference for measurements: enqueue a copy of `bytes` bytes from
+ * src to dst (device memory, both 16-byte aligned, not overlapping; bytes a
+ * multiple of 16) by a streaming kernel of this library (16-byte nontemporal
+ * loads and stores).  A benchmark times it beside the step kernel as the HBM
+ * ceiling a plain read-and-write stream reaches.  LBM_E_INVALID on bad
+ * arguments, LBM_E_DEVICE if the launch fails.  Does not synchronize. */
+int lbm_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
 
 /* Human-readable description of the last error on h (never NULL). */
 const char *lbm_last_error(const lbm_handle *h);

@@ -594,7 +594,10 @@ constexpr uint64_t kMagic = 0x31626C6D62676C6Cull;
 // ============================================================================
 extern "C" {
 
-const char *lbm_version(void) { return "lbmgrow 1.0 gfx950"; }
+#ifndef LBM_SOURCE_HASH
+#define LBM_SOURCE_HASH "unknown"
+#endif
+const char *lbm_version(void) { return "lbmgrow 1.1 gfx950 src " LBM_SOURCE_HASH; }
 
 size_t lbm_workspace_bytes(const lbm_params *p)
 {
@@ -706,6 +709,8 @@ int lbm_diagnostics(lbm_handle *h, lbm_diag *out)
     out->reserved = 0;
     out->lam = d.lam;
     out->divisions = d.divisions;
+    // a run without the sweep window sweeps all H rows every step
+    out->rows_swept = (h->p.flags & LBM_FLAG_WINDOW) ? d.rows_swept : h->t * (int64_t)h->p.H;
     if (d.status & kStDomainFull) h->fail(LBM_E_DOMAIN_FULL, "front reached the top row of the window");
     if (d.status & kStNonFinite) h->fail(LBM_E_NONFINITE, "total mass is not finite");
     return LBM_OK;
@@ -895,6 +900,19 @@ int lbm_set_state(lbm_handle *h, const void *host_blob, size_t bytes)
         (rc = h->hip(launch_fill_i32(h->hslot(h->t + 2), h->p.L, 0, h->stream), "fill")))
         return rc;
     return h->hip(hipStreamSynchronize(h->stream), "synchronize");
+}
+
+int lbm_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream)
+{
+    if (!dst || !src || bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(dst) % 16) != 0 ||
+        (reinterpret_cast<uintptr_t>(src) % 16) != 0)
+        return LBM_E_INVALID;
+    const char *d = reinterpret_cast<const char *>(dst), *sp = reinterpret_cast<const char *>(src);
+    if (d < sp + bytes && sp < d + bytes && bytes > 0) return LBM_E_INVALID;   // overlap
+    return launch_stream_copy(dst, src, (int64_t)(bytes / 16),
+                              reinterpret_cast<hipStream_t>(hip_stream)) == hipSuccess
+               ? LBM_OK
+               : LBM_E_DEVICE;
 }
 
 const char *lbm_last_error(const lbm_handle *h)

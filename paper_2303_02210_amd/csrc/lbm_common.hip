@@ -102,12 +102,47 @@ __global__ __launch_bounds__(kRedThreads) void diag_kernel(DiagArgs a)
         o->status = st;
         o->lam = a.st->lam;
         o->divisions = a.st->divisions;
+        o->rows_swept = a.st->rows_swept;
     }
 }
 
 hipError_t launch_diag(const DiagArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(diag_kernel, dim3(1), dim3(kRedThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+// Streaming copy: each thread moves four 16-byte vectors with nontemporal
+// loads and stores, all four loads in flight before the first store; a block
+// covers 4 x 256 consecutive vectors, so every access is coalesced.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kCopyThreads = 256, kCopyUnroll = 4;
+
+__global__ __launch_bounds__(kCopyThreads) void stream_copy_kernel(u32x4 *dst, const u32x4 *src,
+                                                                   int64_t n)
+{
+    const int64_t base = (int64_t)blockIdx.x * (kCopyThreads * kCopyUnroll) + threadIdx.x;
+    u32x4 v[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const int64_t i = base + (int64_t)u * kCopyThreads;
+        if (i < n) v[u] = __builtin_nontemporal_load(src + i);
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+        const int64_t i = base + (int64_t)u * kCopyThreads;
+        if (i < n) __builtin_nontemporal_store(v[u], dst + i);
+    }
+}
+
+hipError_t launch_stream_copy(void *dst, const void *src, int64_t n16, hipStream_t s)
+{
+    if (n16 <= 0) return hipSuccess;
+    const int64_t per_block = kCopyThreads * kCopyUnroll;
+    const int64_t blocks = (n16 + per_block - 1) / per_block;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)blocks), dim3(kCopyThreads), 0, s,
+                       reinterpret_cast<u32x4 *>(dst), reinterpret_cast<const u32x4 *>(src), n16);
     return hipGetLastError();
 }
 

@@ -89,7 +89,8 @@ struct DevState {
     double   lam;           // division laws: expected divisions per unit weight this step
     double   p0;            // uniform division law: e^-min(lam, 8), no division at a site
     int64_t  divisions;     // divisions so far
-    unsigned long long div_acc[kDivSlots][kDivSlotWords];
+    int64_t  rows_swept;    // sweep window: window rows the steps so far swept
+    alignas(64) unsigned long long div_acc[kDivSlots][kDivSlotWords];
 };
 
 // Diagnostics record written by diag_kernel (layout of lbm_diag).
@@ -99,6 +100,7 @@ struct DiagOut {
     uint32_t status, reserved;
     double   lam;
     int64_t  divisions;
+    int64_t  rows_swept;
 };
 
 template <class S>
@@ -274,6 +276,8 @@ hipError_t launch_diag(const DiagArgs &a, hipStream_t s);
 // from outside (creation, lbm_set_populations), nothing retired.
 hipError_t launch_rates(int growth, double g, double rho_cell, DevState *st, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+// Streaming copy of n 16-byte vectors (the benchmark's bandwidth reference).
+hipError_t launch_stream_copy(void *dst, const void *src, int64_t n16, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 hipError_t launch_state_set(DevState *st, int64_t y_wall, int64_t y_valid_top, int64_t n_rows,
                             int64_t h_hi, hipStream_t s);

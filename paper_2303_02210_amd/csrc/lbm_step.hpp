@@ -1782,6 +1782,7 @@ __device__ __forceinline__ void finalize_body(const FinalizeArgs<S> &a)
         st->retired_last = gone[0];
         st->retired_total += gone[0];
         st->y_valid_top = y_wall + nrows_done;
+        st->rows_swept += nrows_done;
         st->y_wall = y_new;
         st->h_hi = hi;
         int64_t nr = a.H;

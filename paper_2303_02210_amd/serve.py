@@ -28,6 +28,20 @@ def workspace_bytes(cfg: dict) -> int:
     return int(_ffi.lib().lbm_workspace_bytes(ctypes.byref(p)))
 
 
+def bytes_per_update(cfg: dict) -> int:
+    """Algorithmic HBM bytes of one site update: every population read and
+    written once."""
+    q = _ffi.Q[cfg.get("lattice", "d2q9")]
+    return 2 * q * _ffi.STORAGE_BYTES[cfg.get("precision", "fp64")]
+
+
+def active_work(cfg: dict, diag: dict) -> tuple:
+    """(site updates, algorithmic bytes) a run has swept so far: its width
+    times the window rows its steps updated."""
+    n = float(cfg["L"]) * float(diag["rows_swept"])
+    return n, n * bytes_per_update(cfg)
+
+
 class Run:
     """One admitted request."""
 
@@ -60,7 +74,8 @@ class Server:
         self.keep_results = keep_results
         self.clock = clock
         self.t0 = None
-        self.site_updates = 0.0
+        self.active_updates = 0.0     # site updates of swept rows, finished runs
+        self.active_bytes = 0.0
         self.gpu_busy = 0.0
         self.ticks = 0
 
@@ -106,10 +121,12 @@ class Server:
         for r in self.running:
             r.remaining -= k
             r.h_updates += 1
-            self.site_updates += float(r.req["L"]) * float(r.req["H"]) * k
             if r.remaining == 0:
                 r.finished = now
                 r.diag = r.sim.diagnostics()
+                n, b = active_work(r.req, r.diag)
+                self.active_updates += n
+                self.active_bytes += b
                 if self.keep_results:
                     r.result = (r.sim.populations(), r.sim.front_heights(), r.diag)
                 self.ens.remove(r.sim)
@@ -145,6 +162,13 @@ class Server:
     def summary(self) -> dict:
         wall = self.now()
         lat = np.array([r.finished - r.arrival for r in self.done]) if self.done else np.zeros(0)
+        # work of the runs still resident counts too
+        upd, byt = self.active_updates, self.active_bytes
+        for r in self.running:
+            if r.sim is not None:
+                n, b = active_work(r.req, r.sim.diagnostics())
+                upd += n
+                byt += b
         return {
             "completed": len(self.done), "running": len(self.running), "queued": len(self.queue),
             "wall_s": wall,
@@ -152,8 +176,11 @@ class Server:
             "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
             "mean_latency_s": float(lat.mean()) if lat.size else None,
-            "site_updates": self.site_updates,
-            "mlups_nominal": self.site_updates / wall / 1e6 if wall > 0 else 0.0,
+            "site_updates_active": upd,
+            "active_bytes": byt,
+            "mlups_active": upd / wall / 1e6 if wall > 0 else 0.0,
+            "mlups_active_busy": upd / self.gpu_busy / 1e6 if self.gpu_busy > 0 else 0.0,
+            "gpu_busy_s": self.gpu_busy,
             "gpu_busy_frac": self.gpu_busy / wall if wall > 0 else 0.0,
             "ticks": self.ticks,
         }
@@ -177,7 +204,7 @@ def serve_sequential(requests, time_limit: float | None = None, tick_steps: int 
     torch = _torch()
     reqs = sorted(requests, key=lambda q: q.get("arrival_s", 0.0))
     t0 = clock()
-    lat, site_updates, busy = [], 0.0, 0.0
+    lat, upd, byt, busy = [], 0.0, 0.0, 0.0
     done = 0
     for i, req in enumerate(reqs):
         now = clock() - t0
@@ -203,9 +230,11 @@ def serve_sequential(requests, time_limit: float | None = None, tick_steps: int 
                 break
         ev1.record(sim.stream)
         sim.stream.synchronize()
-        sim.diagnostics()                      # raises if the run latched an error
+        d = sim.diagnostics()                  # raises if the run latched an error
         busy += ev0.elapsed_time(ev1) / 1e3
-        site_updates += float(req["L"]) * float(req["H"]) * (int(req["steps"]) - left)
+        n, b = active_work(req, d)
+        upd += n
+        byt += b
         sim.close()
         if cut:
             break
@@ -221,8 +250,11 @@ def serve_sequential(requests, time_limit: float | None = None, tick_steps: int 
         "p50_latency_s": float(np.percentile(lat, 50)) if lat.size else None,
         "p99_latency_s": float(np.percentile(lat, 99)) if lat.size else None,
         "mean_latency_s": float(lat.mean()) if lat.size else None,
-        "site_updates": site_updates,
-        "mlups_nominal": site_updates / wall / 1e6 if wall > 0 else 0.0,
+        "site_updates_active": upd,
+        "active_bytes": byt,
+        "mlups_active": upd / wall / 1e6 if wall > 0 else 0.0,
+        "mlups_active_busy": upd / busy / 1e6 if busy > 0 else 0.0,
+        "gpu_busy_s": busy,
         "gpu_busy_frac": busy / wall if wall > 0 else 0.0,
         "ticks": None,
     }

@@ -24,7 +24,7 @@ def _same(member, ref, tag):
     assert np.array_equal(member.populations(), f), tag
     assert np.array_equal(member.front_heights(), h), tag
     dm = member.diagnostics()
-    for k in ("step", "y_wall", "h_hi", "status", "hbar", "W", "divisions", "lam"):
+    for k in ("step", "y_wall", "h_hi", "status", "hbar", "W", "divisions", "lam", "rows_swept"):
         assert dm[k] == d[k], (tag, k, dm[k], d[k])
     for k in ("mass", "src_total", "fix_total", "retired"):
         assert abs(dm[k] - d[k]) <= 1e-12 * max(1.0, abs(d["mass"])), (tag, k)
