@@ -120,6 +120,16 @@ typedef enum {
                                 LBM_E_INVALID with FP32 / FP64 storage or
                                 with kernel_vb 2 (the LDS-staged form).      */
 
+#define LBM_FLAG_BATCH_TABLE 8u   /* in a batch, always step this member
+                                through the batch's shared tile table        */
+#define LBM_FLAG_BATCH_OWN 16u    /* in a batch, step this member by its own
+                                launches inside the batch's graph (ignored
+                                for members that move their wall or window
+                                or grow by a division law).  Without either
+                                flag members of at least 2^22 sites that do
+                                neither step by their own launches.  Results
+                                are the same either way.                     */
+
 /*
  * Model and run parameters.  Set abi_version = LBM_ABI_VERSION and
  * struct_size = sizeof(lbm_params).
@@ -170,6 +180,10 @@ typedef enum {
  *                 splits evenly); kernel_ty = rows per thread (1..64).
  *                 Batches run staged members in the 4-byte (float64: 8-byte)
  *                 vector form.
+ *   kernel_order  order in which a step's row strips of tiles are handed to
+ *                 the GPU (results do not depend on it): 0 = library
+ *                 default, 1 = from the wall up, 2 = spread over the height
+ *                 (the tiles in flight then mix tissue and empty rows).
  */
 typedef struct {
     uint32_t abi_version;
@@ -195,7 +209,7 @@ typedef struct {
     double   rho_cell;
     double   rho0;
     int32_t  lattice;
-    int32_t  reserved0;
+    int32_t  kernel_order;
 } lbm_params;
 
 /* Diagnostics after the last enqueued step (all reductions in float64). */
@@ -301,8 +315,10 @@ int lbm_destroy(lbm_handle *h);
  * step there is one kernel launch per group of members sharing a storage
  * type and kernel form, over the flattened table of all their tiles (plus,
  * when any member follows the front or sweeps a window, one launch of the
- * between-step bookkeeping for all of them); a run of K steps is captured in
- * a HIP graph and replayed while the membership stays the same.  Every
+ * between-step bookkeeping for all of them); large members that do neither
+ * are stepped by their own kernels instead (LBM_FLAG_BATCH_OWN), inside the
+ * same graph; a run of K steps is captured in a HIP graph and replayed while
+ * the membership stays the same.  Every
  * member keeps its own workspace, state and status, and its populations come
  * out bit for bit as with lbm_step on the handle alone.
  *   lbm_tiles            tiles (thread blocks per step) of a simulation

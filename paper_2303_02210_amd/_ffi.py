@@ -31,6 +31,8 @@ YBC = {"fixed": 0, "follow": 1, "periodic": 2}
 FLAG_WINDOW = 1
 FLAG_DIVISION_MAP = 2
 FLAG_STOCHASTIC_ROUND = 4
+FLAG_BATCH_TABLE = 8
+FLAG_BATCH_OWN = 16
 ST_DOMAIN_FULL = 1
 ST_NONFINITE = 2
 
@@ -51,7 +53,7 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint32), ("replica", ctypes.c_uint32),
         ("kernel_vb", ctypes.c_int32), ("kernel_ty", ctypes.c_int32),
         ("rho_cell", ctypes.c_double), ("rho0", ctypes.c_double),
-        ("lattice", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("lattice", ctypes.c_int32), ("kernel_order", ctypes.c_int32),
     ]
 
 
@@ -172,12 +174,15 @@ def make_params(cfg: dict) -> Params:
     p.replica = int(cfg.get("replica", 0)) & 0xFFFFFFFF
     p.flags = (FLAG_WINDOW if cfg.get("window", False) else 0) | \
         (FLAG_DIVISION_MAP if cfg.get("division_map", False) else 0) | \
-        (FLAG_STOCHASTIC_ROUND if cfg.get("stochastic_round", False) else 0)
+        (FLAG_STOCHASTIC_ROUND if cfg.get("stochastic_round", False) else 0) | \
+        (FLAG_BATCH_TABLE if cfg.get("batch_table", False) else 0) | \
+        (FLAG_BATCH_OWN if cfg.get("batch_own", False) else 0)
     p.kernel_vb = int(cfg.get("kernel_vb", 0))
     p.kernel_ty = int(cfg.get("kernel_ty", 0))
     p.rho_cell = float(cfg.get("rho_cell", 0.1))
     p.rho0 = float(cfg.get("rho0", 1.5))
     p.lattice = LATTICE[cfg.get("lattice", "d2q9")]
+    p.kernel_order = int(cfg.get("kernel_order", 0))
     return p
 
 

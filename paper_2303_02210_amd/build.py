@@ -51,23 +51,27 @@ def hipcc() -> str:
 
 def build(verbose: bool = False, incremental: bool = False) -> str:
     """Compile every translation unit (in parallel) and link liblbmgrow.so.
-    incremental: keep the kernel objects that are newer than every source
-    (the C ABI unit, which carries the source hash, is always rebuilt)."""
+    incremental: keep the objects compiled from exactly the current sources
+    (each object records the source hash taken before it was compiled, so a
+    source edited during a build cannot leave a stale object behind)."""
     from concurrent.futures import ThreadPoolExecutor
 
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     flags = [f for f in HIPFLAGS if f != "-shared"]
-    # (the kernel units do not include the C ABI unit)
-    newest = max(os.path.getmtime(f) for f in source_files() if not f.endswith("lbm_api.cpp"))
+    tree = source_hash()
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        extra = [f'-DLBM_SOURCE_HASH="{source_hash()}"'] if src == "lbm_api.cpp" else []
-        if (incremental and not extra and os.path.exists(obj)
-                and os.path.getmtime(obj) > newest):
-            return obj
+        stamp = obj + ".src"
+        extra = [f'-DLBM_SOURCE_HASH="{tree}"'] if src == "lbm_api.cpp" else []
+        if incremental and os.path.exists(obj) and os.path.exists(stamp):
+            with open(stamp) as fh:
+                if fh.read().strip() == tree:
+                    return obj
+        if os.path.exists(stamp):
+            os.remove(stamp)
         cmd = [hipcc(), *flags, *extra, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -77,6 +81,8 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
             raise RuntimeError(f"hipcc failed on {src}:\n{err}")
         if err.strip() and verbose:
             print(err, flush=True)
+        with open(stamp, "w") as fh:
+            fh.write(tree)
         return obj
 
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
@@ -86,6 +92,8 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    if source_hash() != tree:
+        raise RuntimeError("a source changed while the library was being built: build again")
     return LIB
 
 

@@ -158,8 +158,11 @@ bool params_ok(const lbm_params *p, std::string *why)
     if (p->ybc < LBM_Y_WALL_FIXED || p->ybc > LBM_Y_PERIODIC) return bad("bad ybc");
     if (p->ybc == LBM_Y_WALL_FOLLOW && (p->wall_min_gap < 0 || !(p->wall_w_factor >= 0.0)))
         return bad("bad wall follow parameters");
-    if ((p->flags & ~(LBM_FLAG_WINDOW | LBM_FLAG_DIVISION_MAP | LBM_FLAG_STOCHASTIC_ROUND)) != 0)
+    if ((p->flags & ~(LBM_FLAG_WINDOW | LBM_FLAG_DIVISION_MAP | LBM_FLAG_STOCHASTIC_ROUND |
+                      LBM_FLAG_BATCH_TABLE | LBM_FLAG_BATCH_OWN)) != 0)
         return bad("unknown flags");
+    if ((p->flags & LBM_FLAG_BATCH_TABLE) && (p->flags & LBM_FLAG_BATCH_OWN))
+        return bad("LBM_FLAG_BATCH_TABLE and LBM_FLAG_BATCH_OWN exclude each other");
     if ((p->flags & LBM_FLAG_STOCHASTIC_ROUND) &&
         p->precision != LBM_FP16_OFFSET && p->precision != LBM_BF16_OFFSET)
         return bad("stochastic rounding needs FP16 or BF16 offset storage");
@@ -169,6 +172,7 @@ bool params_ok(const lbm_params *p, std::string *why)
           p->kernel_vb == 8 || p->kernel_vb == 16))
         return bad("kernel_vb must be 0, 1, 2, 4, 8 or 16");
     if (p->kernel_ty < 0 || p->kernel_ty > 64) return bad("kernel_ty must be in [0, 64]");
+    if (p->kernel_order < 0 || p->kernel_order > 2) return bad("kernel_order must be 0, 1 or 2");
     if ((p->flags & LBM_FLAG_WINDOW) && p->ybc == LBM_Y_PERIODIC)
         return bad("the sweep window needs a rear wall");
     if (p->lattice == LBM_LATTICE_D2Q7 && p->kernel_vb == 2)
@@ -179,6 +183,26 @@ bool params_ok(const lbm_params *p, std::string *why)
         (!(p->rho_ref >= 0.0) || !std::isfinite(p->rho_ref)))
         return bad("rho_ref must be >= 0");
     return true;
+}
+
+// A multiplier m coprime to M near M (3 - sqrt 5)/2: the sequence (k m) mod M
+// then visits 0..M-1 with consecutive entries far apart and every stretch of
+// it spread evenly over the range (the golden-ratio sequence).
+int spread_multiplier(int M)
+{
+    if (M <= 2) return 0;
+    int m = (int)std::lround(0.3819660112501051 * M);
+    if (m < 1) m = 1;
+    auto gcd = [](int a, int b) {
+        while (b) {
+            const int t = a % b;
+            a = b;
+            b = t;
+        }
+        return a;
+    };
+    while (gcd(m, M) != 1) ++m;
+    return m;
 }
 
 int pick_ty(int gx, int H, int pref, bool forced)
@@ -268,8 +292,9 @@ Layout make_layout(const lbm_params *p)
 struct lbm_handle {
     lbm_params p{};
     hipStream_t stream = nullptr;
-    char *ws = nullptr;
-    size_t ws_bytes = 0;
+    char *ws = nullptr;             // the two population buffers (and, unless
+    size_t ws_bytes = 0;            // static, the scratch after them)
+    char *scratch = nullptr;        // front heights, tallies, device state, ...
     Layout lay;
     int cur = 0;
     int64_t t = 0;
@@ -284,8 +309,10 @@ struct lbm_handle {
     int64_t rep_t0 = 0;
     int rep_cur0 = 0;
 
+    // everything after the population buffers lives in the scratch area, at
+    // its offset from the first front-height slot
     template <class T>
-    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+    T *at(size_t off) const { return reinterpret_cast<T *>(scratch + (off - lay.off_h[0])); }
     void *fbuf(int k) const { return ws + lay.off_f[k]; }
     int32_t *hslot(int64_t step) const { return at<int32_t>(lay.off_h[step % 3]); }
     int32_t *colmax() const { return at<int32_t>(lay.off_colmax); }
@@ -361,7 +388,9 @@ int do_init(lbm_handle *h)
     h->t = 0;
     // empty second buffer: rows never written read as empty through the
     // device window bookkeeping, but clear it so snapshots are clean
-    return h->hip(hipMemsetAsync(h->fbuf(1), 0, l.fbytes, s), "clear");
+    // (a fill kernel rather than a memset: callers may capture this in a graph)
+    return h->hip(launch_fill_i32(reinterpret_cast<int32_t *>(h->fbuf(1)), (int64_t)(l.fbytes / 4), 0, s),
+                  "clear");
 }
 
 template <class S>
@@ -386,6 +415,7 @@ void fill_step_args(const lbm_handle *h, StepArgs<S> &a)
     a.noise = p.sigma > 0.0;
     a.sround = (p.flags & LBM_FLAG_STOCHASTIC_ROUND) != 0;
     a.xcd_rows = 1;   // one row strip of tiles per run (measured best)
+    a.strip_mul = (p.kernel_order == 2) ? spread_multiplier(l.gy / 8) : 0;
     a.seed = p.seed;
     a.replica = p.replica;
     a.omega = (R)(1.0 / p.tau);
@@ -587,40 +617,19 @@ struct BlobHeader {
 };
 constexpr uint64_t kMagic = 0x31626C6D62676C6Cull;
 
-}  // namespace
-
-// ============================================================================
-// C ABI
-// ============================================================================
-extern "C" {
-
-#ifndef LBM_SOURCE_HASH
-#define LBM_SOURCE_HASH "unknown"
-#endif
-const char *lbm_version(void) { return "lbmgrow 1.1 gfx950 src " LBM_SOURCE_HASH; }
-
-size_t lbm_workspace_bytes(const lbm_params *p)
+// The handle over populations `pops` (two buffers) and scratch `scr` (the
+// rest of the layout, from the first front-height slot on): initial state
+// and, for the division laws, the first step's rate.
+int create_handle(const lbm_params *p, const Layout &lay, char *pops, size_t pops_bytes,
+                  char *scr, void *hip_stream, lbm_handle **out)
 {
-    if (!params_ok(p, nullptr)) return 0;
-    return make_layout(p).total;
-}
-
-int lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *hip_stream,
-               lbm_handle **out)
-{
-    if (!out) return LBM_E_INVALID;
-    *out = nullptr;
-    std::string why;
-    if (!params_ok(p, &why)) return LBM_E_INVALID;
-    if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) != 0) return LBM_E_INVALID;
-    const Layout lay = make_layout(p);
-    if (ws_bytes < lay.total) return LBM_E_NOMEM;
     lbm_handle *h = new (std::nothrow) lbm_handle();
     if (!h) return LBM_E_NOMEM;
     h->p = *p;
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    h->ws = reinterpret_cast<char *>(dev_ws);
-    h->ws_bytes = ws_bytes;
+    h->ws = pops;
+    h->ws_bytes = pops_bytes;
+    h->scratch = scr;
     h->lay = lay;
     // Work between steps: the full finalize when the wall or the window
     // moves; otherwise, under a division law, only the next rate from the
@@ -645,6 +654,37 @@ int lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *hip_str
     }
     *out = h;
     return LBM_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+#ifndef LBM_SOURCE_HASH
+#define LBM_SOURCE_HASH "unknown"
+#endif
+const char *lbm_version(void) { return "lbmgrow 1.1 gfx950 src " LBM_SOURCE_HASH; }
+
+size_t lbm_workspace_bytes(const lbm_params *p)
+{
+    if (!params_ok(p, nullptr)) return 0;
+    return make_layout(p).total;
+}
+
+int lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *hip_stream,
+               lbm_handle **out)
+{
+    if (!out) return LBM_E_INVALID;
+    *out = nullptr;
+    if (!params_ok(p, nullptr)) return LBM_E_INVALID;
+    if (!dev_ws || (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) != 0) return LBM_E_INVALID;
+    const Layout lay = make_layout(p);
+    if (ws_bytes < lay.total) return LBM_E_NOMEM;
+    char *ws = reinterpret_cast<char *>(dev_ws);
+    return create_handle(p, lay, ws, ws_bytes, ws + lay.off_h[0], hip_stream, out);
 }
 
 int lbm_step(lbm_handle *h, int64_t nsteps)
@@ -871,7 +911,11 @@ int lbm_set_state(lbm_handle *h, const void *host_blob, size_t bytes)
     const char *b = reinterpret_cast<const char *>(host_blob);
     BlobHeader hd;
     std::memcpy(&hd, b, sizeof hd);
-    if (hd.magic != kMagic || std::memcmp(&hd.p, &h->p, sizeof(lbm_params)) != 0 ||
+    // (how a batch steps the run does not change its state)
+    lbm_params saved = hd.p, mine = h->p;
+    saved.flags &= ~(int32_t)(LBM_FLAG_BATCH_TABLE | LBM_FLAG_BATCH_OWN);
+    mine.flags &= ~(int32_t)(LBM_FLAG_BATCH_TABLE | LBM_FLAG_BATCH_OWN);
+    if (hd.magic != kMagic || std::memcmp(&saved, &mine, sizeof(lbm_params)) != 0 ||
         hd.fbytes != (uint64_t)(l.nelem * l.esize))
         return LBM_E_INVALID;
     h->t = hd.t;
@@ -938,9 +982,25 @@ namespace {
 constexpr int kMaxGroups = 16;
 constexpr int kWindowGrid = 8192;   // blocks of a windowed group's launch
 
+// Members of at least this many sites that neither move their wall or
+// window nor grow by a division law are stepped by their own launches inside
+// the batch's graph (LBM_FLAG_BATCH_OWN / LBM_FLAG_BATCH_TABLE override it):
+// a step of such a member keeps the GPU busy long enough for its launch to
+// cost nothing, and the solo kernels run it faster than the shared table.
+constexpr int64_t kOwnSites = (int64_t)1 << 22;
+
+bool steps_on_its_own(const lbm_handle *h)
+{
+    if (h->device_driven) return false;
+    if (h->p.flags & LBM_FLAG_BATCH_TABLE) return false;
+    if (h->p.flags & LBM_FLAG_BATCH_OWN) return true;
+    return (int64_t)h->p.L * h->p.H >= kOwnSites;
+}
+
 struct BatchGroup {
-    // kernel form; form: 0 one column per lane, 1 vector, 2 the D2Q7 step
-    int prec = 0, form = 0, nt = 0, vbrb = 0, ty = 0, windowed = 0, div = 0, sr = 0;
+    // kernel form; form: 0 one column per lane, 1 vector, 2 the D2Q7 step;
+    // own: the members are stepped by their own launches (no tile table)
+    int prec = 0, form = 0, nt = 0, vbrb = 0, ty = 0, windowed = 0, div = 0, sr = 0, own = 0;
     std::vector<lbm_handle *> m;
     int64_t tiles = 0;                           // tiles over all members
     int grid = 0;                                // blocks per step launch
@@ -972,7 +1032,7 @@ int write_rep(lbm_handle *h)
     r.device_driven = h->device_driven ? 1 : 0;
     r.window = (h->p.flags & LBM_FLAG_WINDOW) ? 1 : 0;
     r.last_live = h->lay.nblocks;   // first windowed launch clears every idle tile
-    int rc = h->hip(hipMemcpyAsync(h->ws + h->lay.off_rep, &r, sizeof r, hipMemcpyHostToDevice,
+    int rc = h->hip(hipMemcpyAsync(h->at<char>(h->lay.off_rep), &r, sizeof r, hipMemcpyHostToDevice,
                                    h->stream),
                     "batch descriptor copy");
     if (rc) return rc;
@@ -985,9 +1045,32 @@ int write_rep(lbm_handle *h)
     return LBM_OK;
 }
 
+// The members of an own-launch group: each one's solo kernel, its per-step
+// inputs read from its descriptor at step k of the run.
+template <class S>
+hipError_t enqueue_own_steps(const BatchGroup &g, int k, hipStream_t s)
+{
+    for (lbm_handle *h : g.m) {
+        const Layout &l = h->lay;
+        StepArgs<S> a;
+        fill_step_args<S>(h, a);
+        a.clock = h->at<char>(l.off_rep);
+        a.clock_k = k;
+        const dim3 grid(l.gx, l.gy);
+        const hipError_t e =
+            l.tl.nq == 7 ? launch_step7<S>(a, grid, l.nt, l.vec ? l.vb : 0, l.rb, s)
+            : l.staged   ? launch_step_staged<S>(a, grid, s)
+            : l.vec      ? launch_step_vec<S>(a, grid, l.nt, l.vb, s)
+                         : launch_step<S>(a, grid, l.nt, l.rb, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 template <class S>
 hipError_t enqueue_group_step(const BatchGroup &g, int k, hipStream_t s)
 {
+    if (g.own) return enqueue_own_steps<S>(g, k, s);
     hipError_t e = hipSuccess;
     if (g.windowed)
         e = launch_plan_batch<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps), (int)g.m.size(),
@@ -1050,11 +1133,13 @@ struct lbm_batch {
             const int div = h->p.growth >= LBM_GROWTH_DIVISION ? 1 : 0;
             const int sr = (h->p.flags & LBM_FLAG_STOCHASTIC_ROUND) ? 1 : 0;
             const int form = h->lay.tl.nq == 7 ? (h->lay.vec ? 3 : 2) : (h->lay.vec ? 1 : 0);
+            const int own = steps_on_its_own(h) ? 1 : 0;
             BatchGroup *g = nullptr;
             for (BatchGroup &c : groups)
-                if (c.prec == h->p.precision && c.form == form && c.nt == h->lay.nt &&
-                    c.vbrb == vbrb && c.ty == h->lay.ty && c.windowed == win && c.div == div &&
-                    c.sr == sr)
+                if (c.own ? (own && c.prec == h->p.precision)
+                          : (!own && c.prec == h->p.precision && c.form == form &&
+                             c.nt == h->lay.nt && c.vbrb == vbrb && c.ty == h->lay.ty &&
+                             c.windowed == win && c.div == div && c.sr == sr))
                     g = &c;
             if (!g) {
                 if ((int)groups.size() == kMaxGroups) return LBM_E_INVALID;
@@ -1068,6 +1153,7 @@ struct lbm_batch {
                 g->windowed = win;
                 g->div = div;
                 g->sr = sr;
+                g->own = own;
             }
             g->m.push_back(h);
         }
@@ -1083,8 +1169,8 @@ struct lbm_batch {
             g.tiles = 0;
             g.ndev = 0;
             for (size_t i = 0; i < g.m.size(); ++i) {
-                reps[i] = g.m[i]->ws + g.m[i]->lay.off_rep;
-                g.tiles += g.m[i]->lay.nblocks;
+                reps[i] = g.m[i]->at<char>(g.m[i]->lay.off_rep);
+                if (!g.own) g.tiles += g.m[i]->lay.nblocks;
                 g.ndev += g.m[i]->device_driven ? 1 : 0;
             }
             if (used + g.tiles > max_tiles || g.tiles > INT32_MAX) return LBM_E_NOMEM;
@@ -1092,7 +1178,9 @@ struct lbm_batch {
             used += g.tiles;
             std::vector<TileRef> tab;
             int32_t cnt = 0;
-            if (g.windowed) {
+            if (g.own) {
+                g.grid = 0;
+            } else if (g.windowed) {
                 g.grid = (int)std::min<int64_t>(g.tiles, kWindowGrid);
             } else {
                 // every tile, member by member, in runs stacked in y

@@ -604,8 +604,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vec_waves<S,
 void step_kernel_vec7(StepArgs<S> a)
 {
     const int nbx = gridDim.x;
-    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
-    const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
+    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows,
+                              a.strip_mul);
+    const StepIO<S> io = step_io(a);
     step_vec_tile7<S, NT, ND, DIV, SR>(a, io, lin % nbx, lin / nbx, nbx);
 }
 
@@ -613,8 +614,9 @@ template <class S, int NT, int RB, bool DIV, bool SR>
 __global__ __launch_bounds__(NT) void step_kernel7(StepArgs<S> a)
 {
     const int nbx = gridDim.x;
-    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
-    const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
+    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows,
+                              a.strip_mul);
+    const StepIO<S> io = step_io(a);
     step_tile7<S, NT, RB, DIV, SR>(a, io, lin % nbx, lin / nbx, nbx);
 }
 

@@ -121,11 +121,18 @@ struct StepArgs {
     int32_t noise;
     int32_t sround;         // 16-bit storage: stochastic rounding of tissue sites
     int32_t xcd_rows;       // row strips per run of tiles given to one XCD (0: none)
+    int32_t strip_mul;      // > 1: each XCD visits its runs in the spread order (m mul) mod M
     uint32_t t, seed, replica;
     R omega, kmu, rho_c, g, sigma;
     R w[9];
     R Wd[9];
     double rho_cell, rho0;  // division laws: cell mass, density where division stops
+    // A batch member stepped by its own launches inside the batch's graph:
+    // its buffers, front-height slots and step counter come from its member
+    // descriptor (a BatchRep<S>) in device memory, at step clock_k of the
+    // run, so that a replayed graph steps on; null: from the fields above.
+    const void *clock;
+    int32_t clock_k;
 };
 
 template <class S>

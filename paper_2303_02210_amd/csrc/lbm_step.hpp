@@ -507,13 +507,19 @@ __device__ __forceinline__ RowSrc row_sources(int mode, int j, int r0, int H, in
 // the cache lines at their edges, mostly meet in one L2, and every XCD gets
 // its share of each part of the lattice (tissue rows cost far more than
 // empty ones; one XCD must not get them all).  ch <= 0: dispatch order.
-__device__ __forceinline__ int xcd_order(int lin, int nb, int ch)
+// mul > 1 spreads each XCD's runs over the lattice: its m-th run is run
+// (m mul) mod M of its M runs (mul coprime to M), so that the tiles in flight
+// at any moment come from all heights -- tissue rows and empty rows are then
+// worked on side by side instead of one after the other.
+__device__ __forceinline__ int xcd_order(int lin, int nb, int ch, int mul = 0)
 {
     if (ch <= 0) return lin;
     const int full = nb - nb % (8 * ch);
     if (lin >= full) return lin;
     const int k = lin >> 3;
-    return ((k / ch) * 8 + (lin & 7)) * ch + k % ch;
+    int m = k / ch;
+    if (mul > 1) m = (int)(((int64_t)m * mul) % (full / (8 * ch)));
+    return (m * 8 + (lin & 7)) * ch + k % ch;
 }
 
 // Per-step inputs of one tile: the buffers and front-height slots of this
@@ -527,6 +533,36 @@ struct StepIO {
     int32_t *h_clear;
     uint32_t t;
 };
+
+// A batch member's per-step inputs at step k of a run: buffers and slots by
+// the parity and the step count the member descriptor holds.
+template <class S>
+__device__ __forceinline__ StepIO<S> batch_io(const BatchRep<S> *R, int k)
+{
+    const int64_t tt = R->t0 + k;
+    const bool cur = ((R->cur0 + k) & 1) != 0;
+    // (selects, not indexing: the descriptor stays in registers)
+    const int s = (int)(tt % 3);
+    int32_t *const h0 = R->hs[0], *const h1 = R->hs[1], *const h2 = R->hs[2];
+    StepIO<S> io;
+    io.fin = cur ? R->f[1] : R->f[0];
+    io.fout = cur ? R->f[0] : R->f[1];
+    io.h_prev = s == 0 ? h0 : (s == 1 ? h1 : h2);
+    io.h_next = s == 0 ? h1 : (s == 1 ? h2 : h0);
+    io.h_clear = R->device_driven ? nullptr : (s == 0 ? h2 : (s == 1 ? h0 : h1));
+    io.t = (uint32_t)tt;
+    return io;
+}
+
+// The per-step inputs of a launch: from the arguments, or (a batch member
+// stepped by its own launches in the batch's graph) from its descriptor.
+template <class S>
+__device__ __forceinline__ StepIO<S> step_io(const StepArgs<S> &a)
+{
+    if (a.clock) return batch_io(reinterpret_cast<const BatchRep<S> *>(a.clock), a.clock_k);
+    return StepIO<S>{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
+}
+
 
 template <class S, int NT, int RB, bool DIV, bool SR = false>
 __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const StepIO<S> &io, int bx,
@@ -679,8 +715,9 @@ template <class S, int NT, int RB, bool DIV, bool SR>
 __global__ __launch_bounds__(NT) void step_kernel(StepArgs<S> a)
 {
     const int nbx = gridDim.x;
-    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
-    const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
+    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows,
+                              a.strip_mul);
+    const StepIO<S> io = step_io(a);
     step_scalar_tile<S, NT, RB, DIV, SR>(a, io, lin % nbx, lin / nbx, nbx);
 }
 
@@ -1164,8 +1201,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vec_waves<S,
 void step_kernel_vec(StepArgs<S> a)
 {
     const int nbx = gridDim.x;
-    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
-    const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
+    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows,
+                              a.strip_mul);
+    const StepIO<S> io = step_io(a);
     step_vec_tile<S, NT, ND, DIV, SR>(a, io, lin % nbx, lin / nbx, nbx);
 }
 
@@ -1514,8 +1552,9 @@ __global__ __launch_bounds__(64 * StagedGeom(sizeof(S)).waves()) void step_kerne
     constexpr StagedGeom G(sizeof(S));
     __shared__ __attribute__((aligned(16))) unsigned char lds[G.waves() * G.ring() * G.stage_bytes()];
     const int nbx = gridDim.x;
-    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows);
-    const StepIO<S> io{a.fin, a.fout, a.h_prev, a.h_next, a.h_clear, a.t};
+    const int lin = xcd_order(blockIdx.y * nbx + blockIdx.x, nbx * gridDim.y, nbx * a.xcd_rows,
+                              a.strip_mul);
+    const StepIO<S> io = step_io(a);
     step_staged_tile<S, DIV>(a, io, lin % nbx, lin / nbx, nbx, lds);
 }
 
@@ -1808,24 +1847,6 @@ __global__ __launch_bounds__(kRedThreads) void finalize_kernel(FinalizeArgs<S> a
 // the solo kernels, so each member's populations come out bit for bit as in
 // a solo run.  Per-step buffers and slots follow from the member's step count.
 // ---------------------------------------------------------------------------
-template <class S>
-__device__ __forceinline__ StepIO<S> batch_io(const BatchRep<S> *R, int k)
-{
-    const int64_t tt = R->t0 + k;
-    const bool cur = ((R->cur0 + k) & 1) != 0;
-    // (selects, not indexing: the descriptor stays in registers)
-    const int s = (int)(tt % 3);
-    int32_t *const h0 = R->hs[0], *const h1 = R->hs[1], *const h2 = R->hs[2];
-    StepIO<S> io;
-    io.fin = cur ? R->f[1] : R->f[0];
-    io.fout = cur ? R->f[0] : R->f[1];
-    io.h_prev = s == 0 ? h0 : (s == 1 ? h1 : h2);
-    io.h_next = s == 0 ? h1 : (s == 1 ? h2 : h0);
-    io.h_clear = R->device_driven ? nullptr : (s == 0 ? h2 : (s == 1 ? h0 : h1));
-    io.t = (uint32_t)tt;
-    return io;
-}
-
 // A member descriptor, read through the constant address space: it does not
 // change while a step runs and its address is the same for the whole block,
 // so its fields are fetched by scalar loads into scalar registers, as kernel

@@ -1,8 +1,7 @@
 """Batched ensembles: many simulations of any size and precision advanced
 together through the library's batch API (one launch per kernel group per
-step over all members' tiles, runs of steps captured in a HIP graph).
-Large members without a sweep window are stepped by their own launches
-instead (see ``Ensemble``)."""
+step over all members' tiles, large members by their own launches, runs of
+steps captured in one HIP graph)."""
 from __future__ import annotations
 
 import ctypes
@@ -18,18 +17,20 @@ def tiles(cfg: dict) -> int:
 
 
 class Ensemble:
-    """A set of ``Sim`` members stepped together on one stream.
+    """A set of ``Sim`` members stepped together on one stream, all through
+    one batch (one graph launch per run of steps).
 
     Members are created on the ensemble's own stream (a fresh, default-
     priority torch stream unless one is given), which the graph capture needs.
 
-    Members of at least ``solo_min_sites`` sites without a sweep window are
-    stepped by their own kernel launches, one after another on the same
-    stream, and the rest through the batch: a step of such a member keeps the
-    GPU busy long enough (over 40 us) for its launch to cost nothing, and the
-    solo kernels run them faster (on MI355X 73-78% of the HBM peak against
-    67-68% in the batch for 1024 x 4096 and 2048 x 8192 members).  Results
-    are the same bit for bit either way.  None batches every member.
+    Members of at least ``solo_min_sites`` sites that do not move their wall
+    or window and do not grow by a division law are stepped inside the batch's
+    graph by their own launches of the solo kernels (LBM_FLAG_BATCH_OWN), the
+    rest through the shared tile table: a step of such a member keeps the GPU
+    busy long enough for its launch to cost nothing, and the solo kernels run
+    them faster than the table (on MI355X 73-78% of the HBM peak against
+    67-68% for 1024 x 4096 and 2048 x 8192 members).  Results are the same bit
+    for bit either way.  None steps every member through the table.
     """
 
     def __init__(self, cfgs=(), device: str = "cuda:0", stream=None, max_members: int = 1024,
@@ -54,56 +55,58 @@ class Ensemble:
         self._b = b
         self.solo_min_sites = solo_min_sites
         self.members: list[Sim] = []
-        self._solo: list[Sim] = []      # members stepped by their own launches
         for c in cfgs:
             self.add(c)
 
+    @staticmethod
+    def _can_step_alone(cfg: dict) -> bool:
+        return (not cfg.get("window", False) and cfg.get("ybc", "fixed") != "follow"
+                and not str(cfg.get("growth", "bulk")).startswith("division"))
+
+    def _placed(self, cfg: dict) -> dict:
+        """cfg with the batch placement flag the ensemble's threshold asks for."""
+        if "batch_own" in cfg or "batch_table" in cfg:
+            return cfg
+        big = (self.solo_min_sites is not None and self._can_step_alone(cfg)
+               and int(cfg["L"]) * int(cfg["H"]) >= self.solo_min_sites)
+        return dict(cfg, batch_own=True) if big else dict(cfg, batch_table=True)
+
     @property
     def stepped_alone(self) -> list[Sim]:
-        """The members stepped by their own launches."""
-        return list(self._solo)
-
-    def _steps_alone(self, sim: Sim) -> bool:
-        c = sim.cfg
-        return (self.solo_min_sites is not None and not c.get("window", False)
-                and int(c["L"]) * int(c["H"]) >= self.solo_min_sites)
+        """The members stepped by their own launches inside the batch's graph."""
+        out = []
+        for m in self.members:
+            c = m.cfg
+            if c.get("batch_table", False) or not self._can_step_alone(c):
+                continue
+            if c.get("batch_own", False) or int(c["L"]) * int(c["H"]) >= (1 << 22):
+                out.append(m)
+        return out
 
     def new_member(self, cfg: dict) -> Sim:
         """Create a Sim on the ensemble's stream (not yet a member)."""
-        return Sim(cfg, device=str(self.device), stream=self.stream)
+        return Sim(self._placed(cfg), device=str(self.device), stream=self.stream)
 
     def add(self, cfg_or_sim) -> Sim:
         sim = cfg_or_sim if isinstance(cfg_or_sim, Sim) else self.new_member(cfg_or_sim)
-        if self._steps_alone(sim):
-            self._solo.append(sim)
-        else:
-            rc = self._lib.lbm_batch_add(self._b, sim.handle)
-            if rc != 0:
-                raise _ffi.LbmError(rc, "lbm_batch_add")
+        rc = self._lib.lbm_batch_add(self._b, sim.handle)
+        if rc != 0:
+            raise _ffi.LbmError(rc, "lbm_batch_add (a member must use the ensemble's stream)")
         self.members.append(sim)
         return sim
 
     def remove(self, sim: Sim) -> None:
-        if sim in self._solo:
-            self._solo.remove(sim)
-        else:
-            rc = self._lib.lbm_batch_remove(self._b, sim.handle)
-            if rc != 0:
-                raise _ffi.LbmError(rc, "lbm_batch_remove")
+        rc = self._lib.lbm_batch_remove(self._b, sim.handle)
+        if rc != 0:
+            raise _ffi.LbmError(rc, "lbm_batch_remove")
         self.members.remove(sim)
 
     def step(self, n: int = 1) -> None:
+        """n steps of every member (LBM_E_STATE if a member has latched a
+        fault: remove it and step again)."""
         rc = self._lib.lbm_batch_step(self._b, int(n))
         if rc != 0:
             raise _ffi.LbmError(rc, "lbm_batch_step")
-        for sim in self._solo:
-            try:
-                sim.step(n)
-            except _ffi.LbmError as e:
-                # a member whose fault has been reported keeps it to itself,
-                # as a batch member does
-                if e.code != _ffi.E_STATE:
-                    raise
 
     def synchronize(self) -> None:
         self.stream.synchronize()

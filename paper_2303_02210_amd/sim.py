@@ -35,19 +35,20 @@ class Sim:
         self.device = torch.device(device)
         self._lib = _ffi.lib()
         self._p = _ffi.make_params(cfg)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
         nbytes = int(self._lib.lbm_workspace_bytes(ctypes.byref(self._p)))
         if nbytes == 0:
             raise ValueError(f"invalid parameters: {cfg}")
-        self.workspace_bytes = nbytes
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         with torch.cuda.device(self.device):
             self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        h = ctypes.c_void_p()
         rc = self._lib.lbm_create(ctypes.byref(self._p), ctypes.c_void_p(self._ws.data_ptr()),
                                   nbytes, ctypes.c_void_p(self.stream.cuda_stream),
                                   ctypes.byref(h))
+        where = "lbm_create"
+        self.workspace_bytes = nbytes
         if rc != 0:
-            raise _ffi.LbmError(rc, "lbm_create")
+            raise _ffi.LbmError(rc, where)
         self._h = h
 
     # -- life cycle ------------------------------------------------------

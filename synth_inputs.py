@@ -66,6 +66,16 @@ EDGE_2048x8192 = cfg(name="edge_2048x8192", L=2048, H=8192, tau=0.8, init_rows=1
                      growth_rate=1e-3, region="front_band", region_width=8,
                      sigma=1e-3, precision="fp32", steps=50000)
 
+# The same strip for the accuracy comparison of the storages.  The workload
+# does not state the initial tissue rows; with 1024 the front cannot advance
+# within 50000 steps (a void row above a flat front receives 1/6 of the
+# interface density, so the density near the front must reach 3 rho_init,
+# and growth in an 8-row band of 1024 rows raises the mean only by a factor
+# exp(50000 * 8/1024 * 1e-3) ~ 1.5).  With 128 rows the front starts near
+# t ~ 17600 (exp(t * 8/128 * 1e-3) ~ 3).  Only the rows that can hold mass
+# are swept (the results do not depend on it).
+EDGE_ACCURACY = dict(EDGE_2048x8192, name="edge_2048x8192_128rows", init_rows=128, window=True)
+
 # Ensemble for roughness scaling: widths and replica counts, height 4L,
 # bulk growth 1e-4, noise 1e-3, 10000 steps, FP32, seeds = replica ids.
 ENSEMBLE_WIDTHS = (128, 256, 512, 1024, 2048)

@@ -127,9 +127,16 @@ def test_large_members_step_alone_and_match():
     ens = Ensemble(MIXED[:2], solo_min_sites=1)
     assert len(ens.stepped_alone) == 2
     ens.step(4)
+    ens.step(4)                                 # the graph replayed: the steps go on
     ens.synchronize()
     for c, m in zip(MIXED[:2], ens.members):
-        _same(m, _solo(c, 4), "all alone")
+        _same(m, _solo(c, 8), "all alone")
+    # a member must use the ensemble's stream, whichever way it is stepped
+    from paper_2303_02210_amd import LbmError, Sim
+    other = Sim(dict(MIXED[0], batch_own=True))
+    with pytest.raises(LbmError):
+        ens.add(other)
+    other.close()
     ens.close()
 
 
