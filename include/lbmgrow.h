@@ -253,6 +253,33 @@ size_t lbm_workspace_bytes(const lbm_params *p);
 int lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *hip_stream,
                lbm_handle **out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): lbm_create
+ * without a workspace.  The caller passes only the population storage (two
+ * buffers, the simulation's state); everything else the kernels use (front
+ * heights, per-block tallies, device state, diagnostics record, batch
+ * descriptor; a division map if flagged) lives in a static device array of
+ * the library, 16 MiB per device, held until the process ends.  The call
+ * allocates no device memory.
+ *   dev_pops == NULL: size query, *pops_bytes = bytes the population storage
+ *                     needs for p (nothing is created).
+ *   otherwise:        dev_pops (device, 256-byte aligned, *pops_bytes bytes,
+ *                     caller owned, valid until lbm_destroy) receives the
+ *                     initial state on hip_stream; *out is a handle used
+ *                     like any other (step, front heights, diagnostics,
+ *                     populations, checkpoints, batches).
+ * One such handle may be live per device at a time, since all of them would
+ * share the device's array; lbm_destroy of it synchronizes its stream and
+ * frees the array for the next one.
+ * Errors: LBM_E_INVALID (parameters, null/unaligned pointers), LBM_E_NOMEM
+ * (*pops_bytes too small; the lattice needs more than 16 MiB of scratch, e.g.
+ * a division map of more than about 4M sites; or another live handle on the
+ * device holds the array), LBM_E_DEVICE.
+ */
+int lbm_create_static(const lbm_params *p, void *dev_pops, size_t *pops_bytes, void *hip_stream,
+                      lbm_handle **out);
+
 /* Enqueue nsteps >= 0 steps (Appendix A steps 1-7 on every site, then the
  * front heights and, in follow mode, the wall).  Does not synchronize. */
 int lbm_step(lbm_handle *h, int64_t nsteps);

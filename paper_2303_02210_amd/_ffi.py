@@ -76,6 +76,9 @@ _SIGS = [
     ("lbm_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(Params)]),
     ("lbm_create", ctypes.c_int, [ctypes.POINTER(Params), _VP, ctypes.c_size_t, _VP,
                                   ctypes.POINTER(_VP)]),
+    ("lbm_create_static", ctypes.c_int, [ctypes.POINTER(Params), _VP,
+                                         ctypes.POINTER(ctypes.c_size_t), _VP,
+                                         ctypes.POINTER(_VP)]),
     ("lbm_step", ctypes.c_int, [_VP, ctypes.c_int64]),
     ("lbm_front_heights", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_int64)]),
     ("lbm_front_heights_async", ctypes.c_int, [_VP, _VP]),

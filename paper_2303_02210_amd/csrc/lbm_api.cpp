@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -295,6 +296,7 @@ struct lbm_handle {
     char *ws = nullptr;             // the two population buffers (and, unless
     size_t ws_bytes = 0;            // static, the scratch after them)
     char *scratch = nullptr;        // front heights, tallies, device state, ...
+    int static_device = -1;         // device whose static scratch this handle holds
     Layout lay;
     int cur = 0;
     int64_t t = 0;
@@ -617,19 +619,45 @@ struct BlobHeader {
 };
 constexpr uint64_t kMagic = 0x31626C6D62676C6Cull;
 
+// One live handle per device may use that device's static scratch; the host
+// side of those handles is static too, so creating one allocates nothing.
+std::mutex g_static_mu;
+bool g_static_taken[kMaxDevices] = {};
+lbm_handle g_static_handles[kMaxDevices];
+
+bool claim_static(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (dev < 0 || dev >= kMaxDevices || g_static_taken[dev]) return false;
+    g_static_taken[dev] = true;
+    return true;
+}
+
+void release_static(int dev)
+{
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (dev >= 0 && dev < kMaxDevices) g_static_taken[dev] = false;
+}
+
 // The handle over populations `pops` (two buffers) and scratch `scr` (the
 // rest of the layout, from the first front-height slot on): initial state
 // and, for the division laws, the first step's rate.
 int create_handle(const lbm_params *p, const Layout &lay, char *pops, size_t pops_bytes,
-                  char *scr, void *hip_stream, lbm_handle **out)
+                  char *scr, int static_device, void *hip_stream, lbm_handle **out)
 {
-    lbm_handle *h = new (std::nothrow) lbm_handle();
-    if (!h) return LBM_E_NOMEM;
+    lbm_handle *h;
+    if (static_device >= 0) {
+        h = &g_static_handles[static_device];
+        *h = lbm_handle();
+    } else if (!(h = new (std::nothrow) lbm_handle())) {
+        return LBM_E_NOMEM;
+    }
     h->p = *p;
     h->stream = reinterpret_cast<hipStream_t>(hip_stream);
     h->ws = pops;
     h->ws_bytes = pops_bytes;
     h->scratch = scr;
+    h->static_device = static_device;
     h->lay = lay;
     // Work between steps: the full finalize when the wall or the window
     // moves; otherwise, under a division law, only the next rate from the
@@ -649,7 +677,7 @@ int create_handle(const lbm_params *p, const Layout &lay, char *pops, size_t pop
     if (rc == LBM_OK && p->growth >= LBM_GROWTH_DIVISION)
         rc = LBM_DISPATCH(p->precision, do_mass, h);   // the first step's division rate
     if (rc != LBM_OK) {
-        delete h;
+        if (static_device < 0) delete h;
         return rc;
     }
     *out = h;
@@ -684,7 +712,34 @@ int lbm_create(const lbm_params *p, void *dev_ws, size_t ws_bytes, void *hip_str
     const Layout lay = make_layout(p);
     if (ws_bytes < lay.total) return LBM_E_NOMEM;
     char *ws = reinterpret_cast<char *>(dev_ws);
-    return create_handle(p, lay, ws, ws_bytes, ws + lay.off_h[0], hip_stream, out);
+    return create_handle(p, lay, ws, ws_bytes, ws + lay.off_h[0], -1, hip_stream, out);
+}
+
+int lbm_create_static(const lbm_params *p, void *dev_pops, size_t *pops_bytes, void *hip_stream,
+                      lbm_handle **out)
+{
+    if (!pops_bytes) return LBM_E_INVALID;
+    if (!params_ok(p, nullptr)) return LBM_E_INVALID;
+    const Layout lay = make_layout(p);
+    const size_t need = lay.off_h[0];                 // the two population buffers
+    if (lay.total - lay.off_h[0] > kStaticScratchBytes) return LBM_E_NOMEM;
+    if (!dev_pops) {                                  // size query
+        *pops_bytes = need;
+        return LBM_OK;
+    }
+    if (!out) return LBM_E_INVALID;
+    *out = nullptr;
+    if ((reinterpret_cast<uintptr_t>(dev_pops) % kAlign) != 0) return LBM_E_INVALID;
+    if (*pops_bytes < need) return LBM_E_NOMEM;
+    int dev = -1;
+    void *scr = nullptr;
+    if (static_scratch_of(reinterpret_cast<hipStream_t>(hip_stream), &dev, &scr) != hipSuccess)
+        return LBM_E_DEVICE;
+    if (!claim_static(dev)) return LBM_E_NOMEM;       // another live handle holds it
+    const int rc = create_handle(p, lay, reinterpret_cast<char *>(dev_pops), *pops_bytes,
+                                 reinterpret_cast<char *>(scr), dev, hip_stream, out);
+    if (rc != LBM_OK) release_static(dev);
+    return rc;
 }
 
 int lbm_step(lbm_handle *h, int64_t nsteps)
@@ -969,6 +1024,15 @@ int lbm_destroy(lbm_handle *h)
 {
     if (!h) return LBM_E_INVALID;
     if (h->batch) lbm_batch_remove(h->batch, h);
+    if (h->static_device >= 0) {
+        // the next handle on this device reuses the scratch: let this
+        // handle's work finish first
+        (void)hipStreamSynchronize(h->stream);
+        const int dev = h->static_device;
+        *h = lbm_handle();
+        release_static(dev);
+        return LBM_OK;
+    }
     delete h;
     return LBM_OK;
 }

@@ -1,6 +1,9 @@
 // lbm_common.hip -- small non-templated kernels of the gfx950 library: fills,
-// device-state set-up and the diagnostics reduction.
+// device-state set-up and the diagnostics reduction; the static scratch of
+// handles created without a workspace.
 #include "lbm_step.hpp"
+
+#include <mutex>
 
 namespace lbm {
 
@@ -162,6 +165,46 @@ hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s)
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(fill_f64_kernel, dim3(blocks), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
+}
+
+// Scratch of the handle created by lbm_create_static (one live such handle
+// per device): its front-height slots, tallies, device state, diagnostics
+// record and batch descriptor.  Each device holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in: only the
+// address from hipGetSymbolAddress may reach a kernel or a copy.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch_of(hipStream_t s, int *device, void **ptr)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    int dev = cur;
+    if (s) {
+        hipDevice_t d;
+        if ((e = hipStreamGetDevice(s, &d)) != hipSuccess) return e;
+        dev = (int)d;
+    }
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        // look the array up with its device current
+        if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *device = dev;
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_state_set(DevState *st, int64_t y_wall, int64_t y_valid_top, int64_t n_rows,

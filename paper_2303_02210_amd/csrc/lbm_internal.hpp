@@ -283,6 +283,13 @@ hipError_t launch_diag(const DiagArgs &a, hipStream_t s);
 // from outside (creation, lbm_set_populations), nothing retired.
 hipError_t launch_rates(int growth, double g, double rho_cell, DevState *st, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+// The static scratch of lbm_create_static: a file-scope device array of
+// kStaticScratchBytes per device.  static_scratch_of finds the device the
+// stream belongs to and that device's address of the array (looked up once
+// per device, with the device current, and kept).
+constexpr size_t kStaticScratchBytes = (size_t)16 << 20;
+constexpr int kMaxDevices = 64;
+hipError_t static_scratch_of(hipStream_t s, int *device, void **ptr);
 // Streaming copy of n 16-byte vectors (the benchmark's bandwidth reference).
 hipError_t launch_stream_copy(void *dst, const void *src, int64_t n16, hipStream_t s);
 hipError_t launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);

@@ -24,7 +24,11 @@ class Sim:
     ``cfg`` is a workload dict (keys of ``lbm_params``; see ``synth_inputs``).
     """
 
-    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None):
+    def __init__(self, cfg: dict, device: str = "cuda:0", stream=None,
+                 static_scratch: bool = False):
+        """static_scratch: create through lbm_create_static, so that the
+        library keeps everything but the populations in its static device
+        array (at most one such Sim per device at a time)."""
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Sim needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -37,15 +41,31 @@ class Sim:
         self._p = _ffi.make_params(cfg)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
-        nbytes = int(self._lib.lbm_workspace_bytes(ctypes.byref(self._p)))
-        if nbytes == 0:
-            raise ValueError(f"invalid parameters: {cfg}")
-        with torch.cuda.device(self.device):
-            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        rc = self._lib.lbm_create(ctypes.byref(self._p), ctypes.c_void_p(self._ws.data_ptr()),
-                                  nbytes, ctypes.c_void_p(self.stream.cuda_stream),
-                                  ctypes.byref(h))
-        where = "lbm_create"
+        if static_scratch:
+            size = ctypes.c_size_t(0)
+            rc = self._lib.lbm_create_static(ctypes.byref(self._p), None, ctypes.byref(size),
+                                             None, None)
+            if rc != 0:
+                raise _ffi.LbmError(rc, "lbm_create_static (size query)")
+            nbytes = int(size.value)
+            with torch.cuda.device(self.device):
+                self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            rc = self._lib.lbm_create_static(ctypes.byref(self._p),
+                                             ctypes.c_void_p(self._ws.data_ptr()),
+                                             ctypes.byref(size),
+                                             ctypes.c_void_p(self.stream.cuda_stream),
+                                             ctypes.byref(h))
+            where = "lbm_create_static"
+        else:
+            nbytes = int(self._lib.lbm_workspace_bytes(ctypes.byref(self._p)))
+            if nbytes == 0:
+                raise ValueError(f"invalid parameters: {cfg}")
+            with torch.cuda.device(self.device):
+                self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            rc = self._lib.lbm_create(ctypes.byref(self._p), ctypes.c_void_p(self._ws.data_ptr()),
+                                      nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(h))
+            where = "lbm_create"
         self.workspace_bytes = nbytes
         if rc != 0:
             raise _ffi.LbmError(rc, where)
