@@ -345,7 +345,9 @@ def main():
         out["ensemble"] = run_ensemble(args.ensemble_steps, 10, tuned=True,
                                        sequential=not args.no_sequential)
     if args.workload == "bulk" and not args.no_served:
-        out["served"] = run_served(args.served_requests, args.served_time_limit, tuned=True,
+        # (the library's default shapes: the tuned solo shapes split the
+        # served batch into more groups and measured slower there)
+        out["served"] = run_served(args.served_requests, args.served_time_limit, tuned=False,
                                    sequential=not args.no_sequential)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_steps} steps, one thread ...")
@@ -447,7 +449,7 @@ def bench_ensemble(args):
     print(json.dumps(out), flush=True)
 
 
-def run_served(n: int, time_limit: float, tuned: bool = True, sequential: bool = True) -> dict:
+def run_served(n: int, time_limit: float, tuned: bool = False, sequential: bool = True) -> dict:
     """Poisson arrivals at 20 requests/s of runs with L in {128..4096}, H in
     [2L, 4L], 1000-50000 steps, bulk or front-band growth, FP64 / FP32 /
     FP16-offset; admitted by HBM footprint into the running batch; rear wall
@@ -487,7 +489,8 @@ def run_served(n: int, time_limit: float, tuned: bool = True, sequential: bool =
     out = {"workload": f"served_poisson20_{n}", "requests": n, "rate_hz": 20.0,
            "widths": [128, 256, 512, 1024, 2048, 4096], "steps_range": [1000, 50000],
            "wall": "follow", "sweep": "window", "hbm_budget_bytes": 200e9, "tick_steps": 100,
-           "time_limit_s": time_limit}
+           "time_limit_s": time_limit,
+           "launch_shapes": "autotuner cache" if tuned else "library defaults"}
     out.update(figures(summ))
     out["sequential"] = None if seq is None else figures(seq)
     out["speedup_vs_sequential"] = (None if seq is None or not seq["runs_per_hour"] else
@@ -506,7 +509,7 @@ def bench_served(args):
         "data": "synthetic",
         "config": {k: sv[k] for k in ("workload", "requests", "rate_hz", "widths", "steps_range",
                                       "wall", "sweep", "hbm_budget_bytes", "tick_steps",
-                                      "time_limit_s")},
+                                      "time_limit_s", "launch_shapes")},
         "cpu_baseline": None,
     }
     out.update({k: v for k, v in sv.items() if k not in out["config"]})
@@ -527,6 +530,8 @@ def _curves(sims, steps, every, stream_sync, times=None):
         sims.step(mark - done)
         done = mark
         stream_sync()
+        if len(rec["t"]) % 20 == 19:
+            log(f"  t = {done}")
         ds = [m.diagnostics() for m in sims.members]
         rec["t"].append(done)
         rec["hbar"].append([d["hbar"] for d in ds])

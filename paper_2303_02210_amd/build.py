@@ -35,11 +35,13 @@ def source_files() -> list:
     return files
 
 
-def source_hash() -> str:
+def source_hash(exclude=()) -> str:
     """First 16 hex digits of the SHA-256 of the library's sources; the
     library built from them reports it in lbm_version()."""
     h = hashlib.sha256()
     for f in source_files():
+        if os.path.basename(f) in exclude:
+            continue
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
@@ -61,14 +63,17 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
     flags = [f for f in HIPFLAGS if f != "-shared"]
     tree = source_hash()
+    # what the kernel units are compiled from (they do not include the C ABI
+    # unit, which carries the hash of everything and is always rebuilt)
+    kernels = source_hash(exclude=("lbm_api.cpp",))
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
         stamp = obj + ".src"
         extra = [f'-DLBM_SOURCE_HASH="{tree}"'] if src == "lbm_api.cpp" else []
-        if incremental and os.path.exists(obj) and os.path.exists(stamp):
+        if incremental and not extra and os.path.exists(obj) and os.path.exists(stamp):
             with open(stamp) as fh:
-                if fh.read().strip() == tree:
+                if fh.read().strip() == kernels:
                     return obj
         if os.path.exists(stamp):
             os.remove(stamp)
@@ -82,7 +87,7 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
         if err.strip() and verbose:
             print(err, flush=True)
         with open(stamp, "w") as fh:
-            fh.write(tree)
+            fh.write(kernels)
         return obj
 
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:

@@ -173,7 +173,7 @@ bool params_ok(const lbm_params *p, std::string *why)
           p->kernel_vb == 8 || p->kernel_vb == 16))
         return bad("kernel_vb must be 0, 1, 2, 4, 8 or 16");
     if (p->kernel_ty < 0 || p->kernel_ty > 64) return bad("kernel_ty must be in [0, 64]");
-    if (p->kernel_order < 0 || p->kernel_order > 2) return bad("kernel_order must be 0, 1 or 2");
+    if (p->kernel_order < 0 || p->kernel_order > 4) return bad("kernel_order must be in [0, 4]");
     if ((p->flags & LBM_FLAG_WINDOW) && p->ybc == LBM_Y_PERIODIC)
         return bad("the sweep window needs a rear wall");
     if (p->lattice == LBM_LATTICE_D2Q7 && p->kernel_vb == 2)
@@ -417,7 +417,13 @@ void fill_step_args(const lbm_handle *h, StepArgs<S> &a)
     a.noise = p.sigma > 0.0;
     a.sround = (p.flags & LBM_FLAG_STOCHASTIC_ROUND) != 0;
     a.xcd_rows = 1;   // one row strip of tiles per run (measured best)
-    a.strip_mul = (p.kernel_order == 2) ? spread_multiplier(l.gy / 8) : 0;
+    // default: two sweeps for the D2Q9 step without a division law, from the
+    // wall up otherwise (measured best on each)
+    const int order = p.kernel_order ? p.kernel_order
+                      : (l.tl.nq == 9 && p.growth < LBM_GROWTH_DIVISION) ? 4 : 1;
+    a.strip_mul = (order == 2) ? spread_multiplier(l.gy / 8)
+                  : (order == 3) ? -1
+                  : (order == 4) ? -2 : 0;
     a.seed = p.seed;
     a.replica = p.replica;
     a.omega = (R)(1.0 / p.tau);
@@ -1044,7 +1050,6 @@ int lbm_destroy(lbm_handle *h)
 namespace {
 
 constexpr int kMaxGroups = 16;
-constexpr int kWindowGrid = 8192;   // blocks of a windowed group's launch
 
 // Members of at least this many sites that neither move their wall or
 // window nor grow by a division law are stepped by their own launches inside
@@ -1072,12 +1077,19 @@ struct BatchGroup {
     void **reps = nullptr;                       // device: descriptor pointers
     int32_t *count = nullptr;                    // device: table entries to run
     TileRef *table = nullptr;                    // device: the group's tiles
+    PlanJob *job = nullptr;                      // device: its table's plan (windowed)
 };
 
 size_t batch_slot_bytes(int max_members)
 {
     return align_up((size_t)max_members * sizeof(void *), kAlign) + kAlign;
 }
+
+// Workspace: one slot per group (its descriptor pointers, then in the last
+// kAlign bytes its table's entry count and plan job), then the tile tables.
+constexpr size_t kPlanJobOffset = 64;   // within the last kAlign bytes of a slot
+static_assert(kPlanJobOffset + sizeof(PlanJob) <= kAlign, "plan job fits the slot's tail");
+size_t batch_table_offset(int max_members) { return kMaxGroups * batch_slot_bytes(max_members); }
 
 template <class S>
 int write_rep(lbm_handle *h)
@@ -1109,18 +1121,20 @@ int write_rep(lbm_handle *h)
     return LBM_OK;
 }
 
-// The members of an own-launch group: each one's solo kernel, its per-step
-// inputs read from its descriptor at step k of the run.
+// n steps of a member with its own launches: its solo kernel, the per-step
+// inputs read from its descriptor at steps 0..n-1 of the run.  The steps of
+// one member go back to back, so a member whose state is not much larger
+// than the 256 MB last-level cache finds part of it there at the next step.
 template <class S>
-hipError_t enqueue_own_steps(const BatchGroup &g, int k, hipStream_t s)
+hipError_t enqueue_own_member(lbm_handle *h, int n, hipStream_t s)
 {
-    for (lbm_handle *h : g.m) {
-        const Layout &l = h->lay;
-        StepArgs<S> a;
-        fill_step_args<S>(h, a);
-        a.clock = h->at<char>(l.off_rep);
+    const Layout &l = h->lay;
+    StepArgs<S> a;
+    fill_step_args<S>(h, a);
+    a.clock = h->at<char>(l.off_rep);
+    const dim3 grid(l.gx, l.gy);
+    for (int k = 0; k < n; ++k) {
         a.clock_k = k;
-        const dim3 grid(l.gx, l.gy);
         const hipError_t e =
             l.tl.nq == 7 ? launch_step7<S>(a, grid, l.nt, l.vec ? l.vb : 0, l.rb, s)
             : l.staged   ? launch_step_staged<S>(a, grid, s)
@@ -1131,23 +1145,24 @@ hipError_t enqueue_own_steps(const BatchGroup &g, int k, hipStream_t s)
     return hipSuccess;
 }
 
+// n steps of a table group: per step its table (windowed groups), the step,
+// and the between-step work of its device-driven members.  (Building the
+// next step's table inside the between-step launch, by its last block to
+// finish, measured slower: that hand-over needs device-wide cache write-backs.)
 template <class S>
-hipError_t enqueue_group_step(const BatchGroup &g, int k, hipStream_t s)
+hipError_t enqueue_group(const BatchGroup &g, int n, hipStream_t s)
 {
-    if (g.own) return enqueue_own_steps<S>(g, k, s);
-    hipError_t e = hipSuccess;
-    if (g.windowed)
-        e = launch_plan_batch<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps), (int)g.m.size(),
-                                 g.table, g.count, s);
-    if (e != hipSuccess) return e;
-    return launch_step_batch<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps), g.table, g.count,
-                                g.grid, g.form, g.nt, g.vbrb, g.div, g.sr, k, s);
-}
-template <class S>
-hipError_t enqueue_group_finalize(const BatchGroup &g, int k, hipStream_t s)
-{
-    return launch_finalize_batch<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps),
-                                    (int)g.m.size(), k, s);
+    BatchRep<S> *const *reps = reinterpret_cast<BatchRep<S> *const *>(g.reps);
+    for (int k = 0; k < n; ++k) {
+        hipError_t e = hipSuccess;
+        if (g.windowed && (e = launch_plan_batch<S>(g.job, 1, s)) != hipSuccess) return e;
+        e = launch_step_batch<S>(reps, g.table, g.count, g.grid, g.form, g.nt, g.vbrb, g.div, g.sr,
+                                 k, s);
+        if (e != hipSuccess) return e;
+        if (g.ndev && (e = launch_finalize_batch<S>(reps, (int)g.m.size(), k, s)) != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 template <class S>
 hipError_t enqueue_group_advance(const BatchGroup &g, int K, hipStream_t s)
@@ -1172,6 +1187,13 @@ struct lbm_batch {
     int64_t max_tiles = 0;
     std::vector<lbm_handle *> members;
     std::vector<BatchGroup> groups;
+    // The groups share no memory, so a run is a set of independent
+    // branches -- one per table group, one for the members stepped by their
+    // own launches -- forked from the batch's stream and joined back to it:
+    // side streams (default priority) carry all branches but the first.
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> joins;
+    hipEvent_t fork = nullptr;
     bool dirty = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -1222,13 +1244,14 @@ struct lbm_batch {
             g->m.push_back(h);
         }
         const size_t slot = batch_slot_bytes(max_members);
-        TileRef *table = reinterpret_cast<TileRef *>(ws + kMaxGroups * slot);
+        TileRef *table = reinterpret_cast<TileRef *>(ws + batch_table_offset(max_members));
         int64_t used = 0;
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             BatchGroup &g = groups[gi];
             char *base = ws + gi * slot;
             g.reps = reinterpret_cast<void **>(base);
             g.count = reinterpret_cast<int32_t *>(base + slot - kAlign);
+            g.job = reinterpret_cast<PlanJob *>(base + slot - kAlign + kPlanJobOffset);
             std::vector<void *> reps(g.m.size());
             g.tiles = 0;
             g.ndev = 0;
@@ -1257,8 +1280,11 @@ struct lbm_batch {
                 cnt = (int32_t)tab.size();
                 g.grid = cnt;
             }
+            const PlanJob job{g.reps, g.table, g.count, (int32_t)g.m.size(), 0};
             if (hipMemcpyAsync(g.reps, reps.data(), reps.size() * sizeof(void *),
                                hipMemcpyHostToDevice, stream) != hipSuccess ||
+                (g.windowed && hipMemcpyAsync(g.job, &job, sizeof job, hipMemcpyHostToDevice,
+                                              stream) != hipSuccess) ||
                 hipMemcpyAsync(g.count, &cnt, sizeof cnt, hipMemcpyHostToDevice, stream) != hipSuccess ||
                 (!tab.empty() && hipMemcpyAsync(g.table, tab.data(), tab.size() * sizeof(TileRef),
                                                 hipMemcpyHostToDevice, stream) != hipSuccess) ||
@@ -1270,19 +1296,100 @@ struct lbm_batch {
         return LBM_OK;
     }
 
-    hipError_t enqueue(int64_t n)
+    // Side streams and events for nb branches, on the batch stream's device.
+    hipError_t ensure_branches(int nb)
     {
         hipError_t e = hipSuccess;
-        for (int64_t k = 0; k < n && e == hipSuccess; ++k) {
-            for (const BatchGroup &g : groups) {
-                e = LBM_DISPATCH_HIP(g.prec, enqueue_group_step, g, (int)k, stream);
-                if (e != hipSuccess) return e;
+        if ((int)side.size() >= nb - 1 && fork) return e;
+        int cur = 0, dev = 0;
+        if ((e = hipGetDevice(&cur)) != hipSuccess) return e;
+        dev = cur;
+        if (stream) {
+            hipDevice_t d;
+            if ((e = hipStreamGetDevice(stream, &d)) != hipSuccess) return e;
+            dev = (int)d;
+        }
+        if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        if (!fork) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        while (e == hipSuccess && (int)side.size() < nb - 1) {
+            hipStream_t st = nullptr;
+            hipEvent_t ev = nullptr;
+            e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            if (e == hipSuccess) {
+                side.push_back(st);
+                e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                if (e == hipSuccess) joins.push_back(ev);
+                else {
+                    (void)hipStreamDestroy(st);
+                    side.pop_back();
+                }
             }
-            for (const BatchGroup &g : groups) {
-                if (g.ndev == 0) continue;
-                e = LBM_DISPATCH_HIP(g.prec, enqueue_group_finalize, g, (int)k, stream);
-                if (e != hipSuccess) return e;
-            }
+        }
+        if (dev != cur) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        return e;
+    }
+
+    void drop_branches()
+    {
+        // teardown: a failure here leaves nothing to undo
+        for (hipStream_t st : side) (void)hipStreamDestroy(st);
+        for (hipEvent_t ev : joins) (void)hipEventDestroy(ev);
+        if (fork) (void)hipEventDestroy(fork);
+        side.clear();
+        joins.clear();
+        fork = nullptr;
+    }
+
+    // One branch's n steps on stream st: a table group's, or (g == nullptr)
+    // those of every member stepped by its own launches, all n steps of one
+    // member and then the next.
+    hipError_t enqueue_branch(const BatchGroup *g, int n, hipStream_t st)
+    {
+        hipError_t e = hipSuccess;
+        if (g) return LBM_DISPATCH_HIP(g->prec, enqueue_group, *g, n, st);
+        for (const BatchGroup &o : groups) {
+            if (!o.own) continue;
+            for (lbm_handle *h : o.m)
+                if ((e = LBM_DISPATCH_HIP(o.prec, enqueue_own_member, h, n, st)) != hipSuccess)
+                    return e;
+        }
+        return e;
+    }
+
+    // The run's branches: the members stepped by their own launches first
+    // (nullptr), then one per table group.
+    std::vector<const BatchGroup *> branches() const
+    {
+        std::vector<const BatchGroup *> br;
+        bool own = false;
+        for (const BatchGroup &g : groups) {
+            if (g.own) own = true;
+            else br.push_back(&g);
+        }
+        if (own) br.insert(br.begin(), nullptr);
+        return br;
+    }
+
+    // (the side streams exist: ensure_branches ran before any capture)
+    hipError_t enqueue(int64_t n)
+    {
+        const std::vector<const BatchGroup *> br = branches();
+        hipError_t e = hipSuccess;
+        const int nb = (int)br.size();
+        if (nb > 1) {
+            if ((int)side.size() < nb - 1 || !fork) return hipErrorNotReady;
+            if ((e = hipEventRecord(fork, stream)) != hipSuccess) return e;
+        }
+        for (int b = 0; b < nb; ++b) {
+            hipStream_t st = b == 0 ? stream : side[b - 1];
+            if (b > 0 && (e = hipStreamWaitEvent(st, fork, 0)) != hipSuccess) return e;
+            if ((e = enqueue_branch(br[b], (int)n, st)) != hipSuccess) return e;
+            if (b > 0 && ((e = hipEventRecord(joins[b - 1], st)) != hipSuccess ||
+                          (e = hipStreamWaitEvent(stream, joins[b - 1], 0)) != hipSuccess))
+                return e;
         }
         for (const BatchGroup &g : groups) {
             e = LBM_DISPATCH_HIP(g.prec, enqueue_group_advance, g, (int)n, stream);
@@ -1297,7 +1404,7 @@ extern "C" {
 size_t lbm_batch_workspace_bytes(int max_members, int64_t max_tiles)
 {
     if (max_members < 1 || max_tiles < 1) return 0;
-    return kMaxGroups * batch_slot_bytes(max_members) +
+    return batch_table_offset(max_members) +
            align_up((size_t)max_tiles * sizeof(TileRef), kAlign);
 }
 
@@ -1359,6 +1466,7 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps)
     for (lbm_handle *h : b->members)
         if (!h->rep_ok || h->rep_t0 != h->t || h->rep_cur0 != h->cur)
             if ((rc = LBM_DISPATCH(h->p.precision, write_rep, h))) return rc;
+    if (b->ensure_branches((int)b->branches().size()) != hipSuccess) return LBM_E_DEVICE;
     if (b->graph_n != nsteps) {
         b->drop_graph();
         // capture the run; streams that cannot be captured (the null stream)
@@ -1396,6 +1504,7 @@ int lbm_batch_destroy(lbm_batch *b)
     if (!b) return LBM_E_INVALID;
     for (lbm_handle *h : b->members) h->batch = nullptr;
     b->drop_graph();
+    b->drop_branches();
     delete b;
     return LBM_OK;
 }

@@ -298,13 +298,14 @@ __device__ __forceinline__ void step_tile7(const StepArgs<S> &a, const StepIO<S>
 #pragma unroll
                 for (int i = 0; i < 7; ++i) rowg[i << tws] = to_mem<S>(so[i]);
                 m_acc += m_site;
-                s_acc += s_site;
-                x_acc += x_site;
                 mfx_acc += mfx_site;
                 dv.w += dv_site.w;
                 dv.n += dv_site.n;
                 if constexpr (DIV) count_divisions(a, y, x, dv_site.n);
                 if (tissue) {
+                    // (the source and the step-7 change are zero at void sites)
+                    s_acc += s_site;
+                    x_acc += x_site;
                     ymax = y;
                     if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
                 }
@@ -540,13 +541,14 @@ __device__ __forceinline__ void step_vec_tile7(const StepArgs<S> &a, const StepI
             for (int i = 0; i < 7; ++i) put_el<S, ND>(O[i], k, so[i]);
             if (active) {
                 m_acc += m_site;
-                s_acc += s_site;
-                x_acc += x_site;
                 mfx_acc += mfx_site;
                 dv.w += dv_site.w;
                 dv.n += dv_site.n;
                 if constexpr (DIV) count_divisions(a, y, x, dv_site.n);
                 if (tissue) {
+                    // (the source and the step-7 change are zero at void sites)
+                    s_acc += s_site;
+                    x_acc += x_site;
                     tmask |= 1u << k;
                     if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
                 }

@@ -121,7 +121,8 @@ struct StepArgs {
     int32_t noise;
     int32_t sround;         // 16-bit storage: stochastic rounding of tissue sites
     int32_t xcd_rows;       // row strips per run of tiles given to one XCD (0: none)
-    int32_t strip_mul;      // > 1: each XCD visits its runs in the spread order (m mul) mod M
+    int32_t strip_mul;      // > 1: each XCD visits its runs in the spread order (m mul) mod M;
+                            // -1: XCDs 4-7 visit theirs from the top down
     uint32_t t, seed, replica;
     R omega, kmu, rho_c, g, sigma;
     R w[9];
@@ -227,17 +228,21 @@ struct TileRef {
 };
 // Rows per batch run (a member's row strips are grouped to about this many).
 constexpr int kRowsPerRun = 4;
+// Blocks of a windowed group's step launch.
+constexpr int kWindowGrid = 8192;
 __host__ __device__ inline int run_strips(int ty) { return ty >= kRowsPerRun ? 1 : kRowsPerRun / ty; }
-// Runs covering the first `strips` row strips of a member gx tiles wide.
-__host__ __device__ inline int64_t run_count(int64_t strips, int gx, int ty)
+// Runs of ry strips covering the first `strips` row strips of a member gx
+// tiles wide.
+__host__ __device__ inline int64_t run_count(int64_t strips, int gx, int ty, int ry = 0)
 {
-    const int ry = run_strips(ty);
+    if (ry <= 0) ry = run_strips(ty);
     return (strips + ry - 1) / ry * gx;
 }
 // Run l of those: its lowest tile and its height in strips.
-__host__ __device__ inline TileRef run_ref(int rep, int64_t l, int64_t strips, int gx, int ty)
+__host__ __device__ inline TileRef run_ref(int rep, int64_t l, int64_t strips, int gx, int ty,
+                                           int ry = 0)
 {
-    const int ry = run_strips(ty);
+    if (ry <= 0) ry = run_strips(ty);
     const int64_t by0 = (l / gx) * ry;
     const int64_t bx = l % gx;
     const int64_t n = strips - by0 < ry ? strips - by0 : ry;
@@ -259,10 +264,21 @@ template <class S>
 hipError_t launch_step_batch(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
                              int grid, int vec, int nt, int vb_or_rb, int div, int sr, int k,
                              hipStream_t s);
-// Rebuild the table of a windowed group from its members' live rows.
+// A windowed group whose tile table is rebuilt before each step: its n
+// members' descriptors (BatchRep<S> pointers of one storage type) and where
+// its table and entry count go.
+struct PlanJob {
+    void *const *reps;
+    TileRef *table;
+    int32_t *count;
+    int32_t n;
+    int32_t pad;
+};
+// Rebuild the tables of njobs windowed groups of storage type S (one block
+// each) from their members' live rows.
 template <class S>
-hipError_t launch_plan_batch(BatchRep<S> *const *reps, int n, TileRef *table, int32_t *count,
-                             hipStream_t s);
+hipError_t launch_plan_batch(const PlanJob *jobs, int njobs, hipStream_t s);
+// Between-step work of the n members of a group (one block each).
 template <class S>
 hipError_t launch_finalize_batch(BatchRep<S> *const *reps, int n, int k, hipStream_t s);
 template <class S>

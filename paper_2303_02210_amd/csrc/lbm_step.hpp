@@ -510,7 +510,12 @@ __device__ __forceinline__ RowSrc row_sources(int mode, int j, int r0, int H, in
 // mul > 1 spreads each XCD's runs over the lattice: its m-th run is run
 // (m mul) mod M of its M runs (mul coprime to M), so that the tiles in flight
 // at any moment come from all heights -- tissue rows and empty rows are then
-// worked on side by side instead of one after the other.
+// worked on side by side instead of one after the other.  mul = -1 mirrors
+// the order on XCDs 4-7 (they start at the top), so that while half the
+// XCDs work through the tissue rows near the wall the other half stream the
+// rows above and the shared HBM stays busy.  mul = -2 runs two sweeps side
+// by side on every XCD: its even runs climb the lower half, its odd runs the
+// upper half, each in order.
 __device__ __forceinline__ int xcd_order(int lin, int nb, int ch, int mul = 0)
 {
     if (ch <= 0) return lin;
@@ -518,7 +523,10 @@ __device__ __forceinline__ int xcd_order(int lin, int nb, int ch, int mul = 0)
     if (lin >= full) return lin;
     const int k = lin >> 3;
     int m = k / ch;
-    if (mul > 1) m = (int)(((int64_t)m * mul) % (full / (8 * ch)));
+    const int M = full / (8 * ch);
+    if (mul > 1) m = (int)(((int64_t)m * mul) % M);
+    else if (mul == -1 && (lin & 4)) m = M - 1 - m;
+    else if (mul == -2) m = (m & 1) ? (M + 1) / 2 + (m >> 1) : (m >> 1);
     return (m * 8 + (lin & 7)) * ch + k % ch;
 }
 
@@ -671,13 +679,14 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
 #pragma unroll
                 for (int i = 0; i < 9; ++i) rowg[i << tws] = to_mem<S>(so[i]);
                 m_acc += m_site;
-                s_acc += s_site;
-                x_acc += x_site;
                 mfx_acc += mfx_site;
                 dv.w += dv_site.w;
                 dv.n += dv_site.n;
                 if constexpr (DIV) count_divisions(a, y, x, dv_site.n);
                 if (tissue) {
+                    // (the source and the step-7 change are zero at void sites)
+                    s_acc += s_site;
+                    x_acc += x_site;
                     ymax = y;
                     if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
                 }
@@ -1111,13 +1120,14 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
             for (int i = 0; i < 9; ++i) put_el<S, ND>(O[i], k, so[i]);
             if (active) {
                 m_acc += m_site;
-                s_acc += s_site;
-                x_acc += x_site;
                 mfx_acc += mfx_site;
                 dv.w += dv_site.w;
                 dv.n += dv_site.n;
                 if constexpr (DIV) count_divisions(a, y, x, dv_site.n);
                 if (tissue) {
+                    // (the source and the step-7 change are zero at void sites)
+                    s_acc += s_site;
+                    x_acc += x_site;
                     tmask |= 1u << k;
                     if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
                 }
@@ -1484,13 +1494,14 @@ __device__ __forceinline__ void step_staged_tile(const StepArgs<S> &a, const Ste
                                                   mfx_site, dv_site);
             if (active) {
                 m_acc += m_site;
-                s_acc += s_site;
-                x_acc += x_site;
                 mfx_acc += mfx_site;
                 dv.w += dv_site.w;
                 dv.n += dv_site.n;
                 if constexpr (DIV) count_divisions(a, y, (uint32_t)(c0 + i), dv_site.n);
                 if (tissue) {
+                    // (the source and the step-7 change are zero at void sites)
+                    s_acc += s_site;
+                    x_acc += x_site;
                     jmax[v] = j;
                     if (a.mode != kModePeriodic && j + 1 >= H) atomicOr(&a.st->status, kStDomainFull);
                 }
@@ -1894,13 +1905,37 @@ __device__ __forceinline__ int live_tiles(int32_t gx, int32_t ty, int32_t nblock
     return c < nblocks ? (int)c : nblocks;
 }
 
+// A member's live tiles, from the rows its last between-step work set.
 template <class S>
-__global__ __launch_bounds__(kRedThreads) void plan_batch(BatchRep<S> *const *reps, int n,
-                                                          TileRef *table, int32_t *count)
+__device__ __forceinline__ int member_live(const BatchRep<S> *R)
 {
+    return live_tiles(R->gx, R->ty, R->nblocks, R->window, R->a.st->n_rows);
+}
+
+// One block: the tile table of a windowed group for its next step.
+template <class S>
+__device__ void plan_group(const PlanJob &J)
+{
+    BatchRep<S> *const *reps = reinterpret_cast<BatchRep<S> *const *>(J.reps);
+    const int n = J.n;
+    TileRef *table = J.table;
+    int32_t *count = J.count;
     __shared__ int32_t pre[kRedThreads + 1];
     __shared__ int32_t live_sh[kRedThreads];
     __shared__ int32_t carry;
+    __shared__ long long tot_sh[1][kRedWaves];
+    // When every live tile of the group fits the launch's grid, each run is
+    // one tile (a block then walks the shortest chain of row loads); runs of
+    // about kRowsPerRun rows otherwise.
+    long long tot[1] = {0};
+    int live_first = 0;   // this thread's member of the first chunk
+    for (int i = threadIdx.x; i < n; i += kRedThreads) {
+        const int lv = member_live(reps[i]);
+        if (i < kRedThreads) live_first = lv;
+        tot[0] += lv;
+    }
+    block_reduce(tot, tot_sh);
+    const int ry = tot[0] <= kWindowGrid ? 1 : 0;   // 0: the default height
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int base = 0; base < n; base += kRedThreads) {
@@ -1908,8 +1943,8 @@ __global__ __launch_bounds__(kRedThreads) void plan_batch(BatchRep<S> *const *re
         int c = 0, live = 0;
         if (i < n) {
             const BatchRep<S> *R = reps[i];
-            live = live_tiles(R->gx, R->ty, R->nblocks, R->window, R->a.st->n_rows);
-            c = (int)run_count(live / R->gx, R->gx, R->ty);    // runs of this member
+            live = base == 0 ? live_first : member_live(R);
+            c = (int)run_count(live / R->gx, R->gx, R->ty, ry);    // runs of this member
         }
         live_sh[threadIdx.x] = live;
         // inclusive scan of this chunk (Hillis-Steele)
@@ -1930,7 +1965,7 @@ __global__ __launch_bounds__(kRedThreads) void plan_batch(BatchRep<S> *const *re
             const int live = live_sh[m];
             const BatchRep<S> *Rm = reps[base + m];
             for (int l = threadIdx.x; l < cm; l += kRedThreads)
-                table[s0 + l] = run_ref(base + m, l, live / Rm->gx, Rm->gx, Rm->ty);
+                table[s0 + l] = run_ref(base + m, l, live / Rm->gx, Rm->gx, Rm->ty, ry);
             // tiles that ran last step but not this one: their mass tally
             // would otherwise stay behind (a solo launch writes 0 there)
             BatchRep<S> *R = reps[base + m];
@@ -1947,6 +1982,15 @@ __global__ __launch_bounds__(kRedThreads) void plan_batch(BatchRep<S> *const *re
     if (threadIdx.x == 0) *count = carry;
 }
 
+// One block per windowed group (the first step of a run).
+template <class S>
+__global__ __launch_bounds__(kRedThreads) void plan_batch(const PlanJob *jobs)
+{
+    plan_group<S>(jobs[blockIdx.x]);
+}
+
+// One block per member of a group: the between-step work of the
+// device-driven ones.
 template <class S>
 __global__ __launch_bounds__(kRedThreads) void finalize_batch(BatchRep<S> *const *reps, int k)
 {
@@ -2137,11 +2181,10 @@ hipError_t launch_step_batch(BatchRep<S> *const *reps, const TileRef *table, con
 }
 
 template <class S>
-hipError_t launch_plan_batch(BatchRep<S> *const *reps, int n, TileRef *table, int32_t *count,
-                             hipStream_t s)
+hipError_t launch_plan_batch(const PlanJob *jobs, int njobs, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL((plan_batch<S>), dim3(1), dim3(kRedThreads), 0, s, reps, n, table, count);
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL((plan_batch<S>), dim3(njobs), dim3(kRedThreads), 0, s, jobs);
     return hipGetLastError();
 }
 
