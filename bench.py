@@ -40,9 +40,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, precision: str):
+def measured_traffic(workload: str, precision: str, launch: dict):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current kernel source and launch shape."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -51,6 +51,8 @@ def measured_traffic(workload: str, precision: str):
     key = f"{workload}/{precision}"
     e = rec.get(key)
     if not e or e.get("kernel_hash") != kernel_source_hash():
+        return None
+    if e.get("launch", launch) != launch:
         return None
     return e.get("bytes_per_launch")
 
@@ -310,7 +312,9 @@ def main():
     per_launch_s = kern_ms / 1e3 / K
     alg_bytes = L * H * bpu
     achieved = alg_bytes / per_launch_s / 1e9
-    traffic = measured_traffic(cfg["name"], args.precision)
+    launch = {"kernel_vb": cfg.get("kernel_vb", 0), "kernel_ty": cfg.get("kernel_ty", 0),
+              "kernel_order": cfg.get("kernel_order", 0)}
+    traffic = measured_traffic(cfg["name"], args.precision, launch)
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -328,9 +332,7 @@ def main():
                    "init_rows": cfg["init_rows"], "h_every": every, "sweep": "full",
                    "bytes_per_update": bpu,
                    "rounding": "stochastic" if cfg.get("stochastic_round") else "nearest",
-                   "launch": {"kernel_vb": cfg.get("kernel_vb", 0),
-                              "kernel_ty": cfg.get("kernel_ty", 0),
-                              "kernel_order": cfg.get("kernel_order", 0)}},
+                   "launch": launch},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,

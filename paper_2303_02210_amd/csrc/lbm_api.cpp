@@ -137,9 +137,10 @@ bool params_ok(const lbm_params *p, std::string *why)
     if (p->struct_size != sizeof(lbm_params)) return bad("struct_size mismatch");
     if (p->L < 2 || p->H < 4) return bad("L must be >= 2 and H >= 4");
     if (p->lattice != LBM_LATTICE_D2Q9 && p->lattice != LBM_LATTICE_D2Q7) return bad("bad lattice");
-    if ((int64_t)p->L * (int64_t)p->H * lattice_q(p) > (int64_t)1 << 31) return bad("lattice too large");
     // one padded row of populations is addressed with 32-bit byte offsets
+    // (and with L bounded first, the product below cannot overflow)
     if (p->L > (1 << 24)) return bad("L must be <= 2^24");
+    if ((int64_t)p->L * (int64_t)p->H * lattice_q(p) > (int64_t)1 << 31) return bad("lattice too large");
     if (p->precision < LBM_FP64 || p->precision > LBM_BF16_OFFSET) return bad("bad precision");
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return bad("tau must be > 1/2");
     if (!(p->mu >= 0.0 && p->mu <= 1.0)) return bad("mu must be in [0, 1]");
