@@ -182,8 +182,9 @@ typedef enum {
  *                 vector form.
  *   kernel_order  order in which a step's row strips of tiles are handed to
  *                 the GPU (results do not depend on it): 0 = library
- *                 default (4 for the D2Q9 step without a division law, 1
- *                 otherwise), 1 = from the wall up, 2 = spread over the height
+ *                 default (4 for the D2Q9 step without a division law at
+ *                 up to 4 rows per thread, 1 otherwise), 1 = from the wall
+ *                 up, 2 = spread over the height
  *                 (the tiles in flight then mix tissue and empty rows),
  *                 3 = from the wall up on half of the chip's dies and from
  *                 the top down on the other half, 4 = two sweeps side by

@@ -418,10 +418,10 @@ void fill_step_args(const lbm_handle *h, StepArgs<S> &a)
     a.noise = p.sigma > 0.0;
     a.sround = (p.flags & LBM_FLAG_STOCHASTIC_ROUND) != 0;
     a.xcd_rows = 1;   // one row strip of tiles per run (measured best)
-    // default: two sweeps for the D2Q9 step without a division law, from the
-    // wall up otherwise (measured best on each)
+    // default: two sweeps for the D2Q9 step without a division law in blocks
+    // of up to 4 rows, from the wall up otherwise (measured best on each)
     const int order = p.kernel_order ? p.kernel_order
-                      : (l.tl.nq == 9 && p.growth < LBM_GROWTH_DIVISION) ? 4 : 1;
+                      : (l.tl.nq == 9 && p.growth < LBM_GROWTH_DIVISION && l.ty <= 4) ? 4 : 1;
     a.strip_mul = (order == 2) ? spread_multiplier(l.gy / 8)
                   : (order == 3) ? -1
                   : (order == 4) ? -2 : 0;
