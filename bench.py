@@ -228,7 +228,20 @@ def main():
     ap.add_argument("--shape", default=None, help="force a launch shape: kernel_vb,kernel_ty")
     ap.add_argument("--order", type=int, default=None,
                     help="force the strip dispatch order (kernel_order: 1 wall up, 2 spread)")
+    ap.add_argument("--emit-sub", default=None, choices=["ensemble", "served"],
+                    help=argparse.SUPPRESS)
     args = ap.parse_args()
+
+    if args.emit_sub:
+        # a sub-record of the default line, in its own process
+        if args.emit_sub == "ensemble":
+            rec = run_ensemble(args.ensemble_steps, 10, tuned=True,
+                               sequential=not args.no_sequential)
+        else:
+            rec = run_served(args.served_requests, args.served_time_limit, tuned=False,
+                             sequential=not args.no_sequential)
+        print(json.dumps(rec), flush=True)
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -344,13 +357,11 @@ def main():
         "cpu_baseline": None,
     }
     if args.workload == "bulk" and not args.no_ensemble:
-        out["ensemble"] = run_ensemble(args.ensemble_steps, 10, tuned=True,
-                                       sequential=not args.no_sequential)
+        out["ensemble"] = child_record("ensemble", args)
     if args.workload == "bulk" and not args.no_served:
-        # (the library's default shapes: the tuned solo shapes split the
-        # served batch into more groups and measured slower there)
-        out["served"] = run_served(args.served_requests, args.served_time_limit, tuned=False,
-                                   sequential=not args.no_sequential)
+        # (the served runs use the library's default shapes: the tuned solo
+        # shapes split the served batch into more groups and measured slower)
+        out["served"] = child_record("served", args)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_steps} steps, one thread ...")
         single = cpu_baseline(cfg, args.cpu_steps)
@@ -359,6 +370,30 @@ def main():
         out["cpu_baseline"] = dict(cpu_baseline_all_cores(cfg, args.cpu_all_steps, procs),
                                    single_thread=single)
     print(json.dumps(out), flush=True)
+
+
+def child_record(kind: str, args) -> dict:
+    """The ensemble or served sub-record of the default line, measured in a
+    child process (after this one has released the GPU memory it used), so
+    that a failure there costs that record only; its exit status is then
+    reported in place of the figures."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--emit-sub", kind,
+           "--ensemble-steps", str(args.ensemble_steps),
+           "--served-requests", str(args.served_requests),
+           "--served-time-limit", str(args.served_time_limit)]
+    if args.no_sequential:
+        cmd.append("--no-sequential")
+    limit = 600 + 3 * args.served_time_limit
+    log(f"{kind}: measured in a child process ...")
+    try:
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=None, text=True, timeout=limit)
+    except subprocess.TimeoutExpired:
+        return {"error": f"no result within {limit:.0f} s"}
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"error": f"child exited with status {r.returncode}"}
+    return json.loads(lines[-1])
 
 
 def run_ensemble(K: int, warmup: int, tuned: bool = True, sequential: bool = True,
