@@ -222,6 +222,9 @@ def main():
     ap.add_argument("--tuned", action="store_true", help="launch shapes from the autotuner cache")
     ap.add_argument("--all-batched", action="store_true",
                     help="ensemble: step every member through the batch (no solo members)")
+    ap.add_argument("--persistent", action="store_true",
+                    help="ensemble: each table group runs a run of steps in one cooperative "
+                         "launch (lbm_batch_persistent)")
     ap.add_argument("--stochastic-round", action="store_true",
                     help="bulk / edge with fp16 / bf16 storage: round the stored offsets "
                          "stochastically instead of to nearest")
@@ -397,7 +400,7 @@ def child_record(kind: str, args) -> dict:
 
 
 def run_ensemble(K: int, warmup: int, tuned: bool = True, sequential: bool = True,
-                 solo_min_sites="default") -> dict:
+                 solo_min_sites="default", persistent: bool = False) -> dict:
     """256 replicas (widths 128..2048 with 96/64/48/32/16 copies, height 4L,
     bulk growth 1e-4, noise 1e-3, float32) advanced together for K steps,
     against the same runs stepped one after another on their own."""
@@ -412,8 +415,8 @@ def run_ensemble(K: int, warmup: int, tuned: bool = True, sequential: bool = Tru
     sites = sum(c["L"] * c["H"] for c in cfgs)
     bpu = 2 * 9 * STORE_BYTES["fp32"]
     log(f"ensemble: {len(cfgs)} replicas, {sites} sites, {K} steps each")
-    ens = Ensemble(cfgs) if solo_min_sites == "default" else \
-        Ensemble(cfgs, solo_min_sites=solo_min_sites)
+    kw = {} if solo_min_sites == "default" else {"solo_min_sites": solo_min_sites}
+    ens = Ensemble(cfgs, persistent=persistent, **kw)
     n_alone = len(ens.stepped_alone)
     log(f"{n_alone} members step alone, {len(cfgs) - n_alone} through the batch")
     ens.step(warmup)
@@ -456,6 +459,8 @@ def run_ensemble(K: int, warmup: int, tuned: bool = True, sequential: bool = Tru
         "widths": list(si.ENSEMBLE_WIDTHS), "counts": list(si.ENSEMBLE_COUNTS),
         "height": "4L", "sites": sites, "steps": K, "bytes_per_update": bpu,
         "members_stepped_alone": n_alone,
+        "launches": ("one cooperative launch per table group per 100 steps" if persistent
+                     else "one per group per step, 100-step runs replayed from a graph"),
         "mlups": round(sites * K / t_batch / 1e6, 1), "ms_per_step": round(t_batch / K * 1e3, 4),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)},
@@ -471,14 +476,16 @@ def run_ensemble(K: int, warmup: int, tuned: bool = True, sequential: bool = Tru
 def bench_ensemble(args):
     """The ensemble on its own JSON line."""
     e = run_ensemble(args.steps, args.warmup, tuned=args.tuned, sequential=not args.no_sequential,
-                     solo_min_sites=None if args.all_batched else "default")
+                     solo_min_sites=None if args.all_batched else "default",
+                     persistent=args.persistent)
     out = {
         "metric": METRIC, "value": e["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": e["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {k: e[k] for k in ("workload", "replicas", "widths", "counts", "height",
-                                     "sites", "bytes_per_update", "members_stepped_alone")},
+                                     "sites", "bytes_per_update", "members_stepped_alone",
+                                     "launches")},
         "roofline": dict(e["roofline"], traffic=None),
         "runs_per_hour": e["runs_per_hour"], "sequential": e["sequential"],
         "speedup_vs_sequential": e["speedup_vs_sequential"], "cpu_baseline": None,

@@ -238,6 +238,8 @@ typedef struct {
 
 #define LBM_ST_DOMAIN_FULL 1u
 #define LBM_ST_NONFINITE   2u
+#define LBM_ST_SYNC_LOST   4u   /* a multi-step batch launch's grid barrier
+                                   gave up waiting (LBM_E_DEVICE)           */
 
 /* Library version string, e.g. "lbmgrow 1.1 gfx950 src 0123456789abcdef":
  * the last word is the first 16 hex digits of the SHA-256 of the sources
@@ -366,6 +368,19 @@ int lbm_destroy(lbm_handle *h);
  *   lbm_batch_step       nsteps >= 0 steps of every member; does not
  *                        synchronize; LBM_E_STATE if a member is in an error
  *                        state (remove it and step again).
+ *   lbm_batch_persistent on = 1: each group whose members neither move their
+ *                        wall or window nor grow by a division law runs
+ *                        all nsteps of a lbm_batch_step in one cooperative
+ *                        launch (a fixed grid of resident blocks striding
+ *                        over its tile table, a grid-wide barrier between
+ *                        steps); the other groups launch per step as
+ *                        before; the run is enqueued directly, not through
+ *                        a graph, every group on the batch's stream in
+ *                        turn.  on = 0 (the default) restores per-step
+ *                        launches.  A barrier that waits past about a
+ *                        second gives up and latches LBM_ST_SYNC_LOST in
+ *                        the members of that launch.  Results are the same
+ *                        either way.
  *   lbm_batch_destroy    releases the batch, not its members.
  * Errors: LBM_E_INVALID (null/foreign handles, stream mismatch, full batch),
  * LBM_E_NOMEM (workspace too small, or members' tiles beyond max_tiles at
@@ -378,6 +393,7 @@ int lbm_batch_create(void *dev_ws, size_t ws_bytes, int max_members, int64_t max
 int lbm_batch_add(lbm_batch *b, lbm_handle *h);
 int lbm_batch_remove(lbm_batch *b, lbm_handle *h);
 int lbm_batch_step(lbm_batch *b, int64_t nsteps);
+int lbm_batch_persistent(lbm_batch *b, int on);
 int lbm_batch_destroy(lbm_batch *b);
 
 #ifdef __cplusplus

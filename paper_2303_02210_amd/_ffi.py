@@ -35,6 +35,7 @@ FLAG_BATCH_TABLE = 8
 FLAG_BATCH_OWN = 16
 ST_DOMAIN_FULL = 1
 ST_NONFINITE = 2
+ST_SYNC_LOST = 4
 
 
 class Params(ctypes.Structure):
@@ -100,6 +101,7 @@ _SIGS = [
     ("lbm_batch_add", ctypes.c_int, [_VP, _VP]),
     ("lbm_batch_remove", ctypes.c_int, [_VP, _VP]),
     ("lbm_batch_step", ctypes.c_int, [_VP, ctypes.c_int64]),
+    ("lbm_batch_persistent", ctypes.c_int, [_VP, ctypes.c_int]),
     ("lbm_batch_destroy", ctypes.c_int, [_VP]),
 ]
 ENTRY_POINTS = [s[0] for s in _SIGS]

@@ -555,6 +555,7 @@ int sync_and_check(lbm_handle *h)
     if ((rc = h->hip(hipStreamSynchronize(h->stream), "synchronize"))) return rc;
     if (status & kStDomainFull) return h->fail(LBM_E_DOMAIN_FULL, "front reached the top row of the window");
     if (status & kStNonFinite) return h->fail(LBM_E_NONFINITE, "total mass is not finite");
+    if (status & kStSyncLost) return h->fail(LBM_E_DEVICE, "a batch launch's grid barrier gave up");
     return LBM_OK;
 }
 
@@ -815,6 +816,7 @@ int lbm_diagnostics(lbm_handle *h, lbm_diag *out)
     out->rows_swept = (h->p.flags & LBM_FLAG_WINDOW) ? d.rows_swept : h->t * (int64_t)h->p.H;
     if (d.status & kStDomainFull) h->fail(LBM_E_DOMAIN_FULL, "front reached the top row of the window");
     if (d.status & kStNonFinite) h->fail(LBM_E_NONFINITE, "total mass is not finite");
+    if (d.status & kStSyncLost) h->fail(LBM_E_DEVICE, "a batch launch's grid barrier gave up");
     return LBM_OK;
 }
 
@@ -1079,6 +1081,8 @@ struct BatchGroup {
     int32_t *count = nullptr;                    // device: table entries to run
     TileRef *table = nullptr;                    // device: the group's tiles
     PlanJob *job = nullptr;                      // device: its table's plan (windowed)
+    GridBar *bar = nullptr;                      // device: barrier of multi-step launches
+    int coop_grid = 0;                           // blocks of a multi-step launch (0: none)
 };
 
 size_t batch_slot_bytes(int max_members)
@@ -1089,7 +1093,10 @@ size_t batch_slot_bytes(int max_members)
 // Workspace: one slot per group (its descriptor pointers, then in the last
 // kAlign bytes its table's entry count and plan job), then the tile tables.
 constexpr size_t kPlanJobOffset = 64;   // within the last kAlign bytes of a slot
-static_assert(kPlanJobOffset + sizeof(PlanJob) <= kAlign, "plan job fits the slot's tail");
+constexpr size_t kGridBarOffset = 128;
+static_assert(kPlanJobOffset + sizeof(PlanJob) <= kGridBarOffset &&
+                  kGridBarOffset + sizeof(GridBar) <= kAlign,
+              "plan job and barrier fit the slot's tail");
 size_t batch_table_offset(int max_members) { return kMaxGroups * batch_slot_bytes(max_members); }
 
 template <class S>
@@ -1150,15 +1157,20 @@ hipError_t enqueue_own_member(lbm_handle *h, int n, hipStream_t s)
 // and the between-step work of its device-driven members.  (Building the
 // next step's table inside the between-step launch, by its last block to
 // finish, measured slower: that hand-over needs device-wide cache write-backs.)
+// persist: a group with neither (coop_grid set) runs all n steps in one
+// cooperative launch.
 template <class S>
-hipError_t enqueue_group(const BatchGroup &g, int n, hipStream_t s)
+hipError_t enqueue_group(const BatchGroup &g, int n, bool persist, hipStream_t s)
 {
     BatchRep<S> *const *reps = reinterpret_cast<BatchRep<S> *const *>(g.reps);
+    if (persist && g.coop_grid > 0)
+        return launch_step_batch<S>(reps, g.table, g.count, g.coop_grid, g.form, g.nt, g.vbrb,
+                                    g.div, g.sr, 0, n, g.bar, s);
     for (int k = 0; k < n; ++k) {
         hipError_t e = hipSuccess;
         if (g.windowed && (e = launch_plan_batch<S>(g.job, 1, s)) != hipSuccess) return e;
         e = launch_step_batch<S>(reps, g.table, g.count, g.grid, g.form, g.nt, g.vbrb, g.div, g.sr,
-                                 k, s);
+                                 k, 1, nullptr, s);
         if (e != hipSuccess) return e;
         if (g.ndev && (e = launch_finalize_batch<S>(reps, (int)g.m.size(), k, s)) != hipSuccess)
             return e;
@@ -1171,6 +1183,12 @@ hipError_t enqueue_group_advance(const BatchGroup &g, int K, hipStream_t s)
     return launch_batch_advance<S>(reinterpret_cast<BatchRep<S> *const *>(g.reps),
                                    (int)g.m.size(), K, s);
 }
+
+#define LBM_DISPATCH_COOP(prec, ...)                                  \
+    ((prec) == LBM_FP64   ? batch_coop_grid<double>(__VA_ARGS__)       \
+     : (prec) == LBM_FP32 ? batch_coop_grid<float>(__VA_ARGS__)        \
+     : (prec) == LBM_FP16_OFFSET ? batch_coop_grid<__half>(__VA_ARGS__) \
+                                 : batch_coop_grid<__hip_bfloat16>(__VA_ARGS__))
 
 #define LBM_DISPATCH_HIP(prec, fn, ...)                               \
     ((prec) == LBM_FP64   ? fn<double>(__VA_ARGS__)                    \
@@ -1188,13 +1206,9 @@ struct lbm_batch {
     int64_t max_tiles = 0;
     std::vector<lbm_handle *> members;
     std::vector<BatchGroup> groups;
-    // The groups share no memory, so a run is a set of independent
-    // branches -- one per table group, one for the members stepped by their
-    // own launches -- forked from the batch's stream and joined back to it:
-    // side streams (default priority) carry all branches but the first.
-    std::vector<hipStream_t> side;
-    std::vector<hipEvent_t> joins;
-    hipEvent_t fork = nullptr;
+    // multi-step launches (lbm_batch_persistent): the run is enqueued
+    // directly instead of through a graph
+    bool persistent = false;
     bool dirty = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -1253,6 +1267,8 @@ struct lbm_batch {
             g.reps = reinterpret_cast<void **>(base);
             g.count = reinterpret_cast<int32_t *>(base + slot - kAlign);
             g.job = reinterpret_cast<PlanJob *>(base + slot - kAlign + kPlanJobOffset);
+            g.bar = reinterpret_cast<GridBar *>(base + slot - kAlign + kGridBarOffset);
+            g.coop_grid = 0;
             std::vector<void *> reps(g.m.size());
             g.tiles = 0;
             g.ndev = 0;
@@ -1280,10 +1296,16 @@ struct lbm_batch {
                 }
                 cnt = (int32_t)tab.size();
                 g.grid = cnt;
+                if (g.ndev == 0) {
+                    const int cg = LBM_DISPATCH_COOP(g.prec, g.form, g.nt, g.vbrb, g.div, g.sr);
+                    g.coop_grid = std::min(cg, g.grid);
+                }
             }
             const PlanJob job{g.reps, g.table, g.count, (int32_t)g.m.size(), 0};
+            const GridBar bar0{0, 0, 0, 0};
             if (hipMemcpyAsync(g.reps, reps.data(), reps.size() * sizeof(void *),
                                hipMemcpyHostToDevice, stream) != hipSuccess ||
+                hipMemcpyAsync(g.bar, &bar0, sizeof bar0, hipMemcpyHostToDevice, stream) != hipSuccess ||
                 (g.windowed && hipMemcpyAsync(g.job, &job, sizeof job, hipMemcpyHostToDevice,
                                               stream) != hipSuccess) ||
                 hipMemcpyAsync(g.count, &cnt, sizeof cnt, hipMemcpyHostToDevice, stream) != hipSuccess ||
@@ -1297,60 +1319,13 @@ struct lbm_batch {
         return LBM_OK;
     }
 
-    // Side streams and events for nb branches, on the batch stream's device.
-    hipError_t ensure_branches(int nb)
-    {
-        hipError_t e = hipSuccess;
-        if ((int)side.size() >= nb - 1 && fork) return e;
-        int cur = 0, dev = 0;
-        if ((e = hipGetDevice(&cur)) != hipSuccess) return e;
-        dev = cur;
-        if (stream) {
-            hipDevice_t d;
-            if ((e = hipStreamGetDevice(stream, &d)) != hipSuccess) return e;
-            dev = (int)d;
-        }
-        if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return e;
-        if (!fork) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-        while (e == hipSuccess && (int)side.size() < nb - 1) {
-            hipStream_t st = nullptr;
-            hipEvent_t ev = nullptr;
-            e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-            if (e == hipSuccess) {
-                side.push_back(st);
-                e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-                if (e == hipSuccess) joins.push_back(ev);
-                else {
-                    (void)hipStreamDestroy(st);
-                    side.pop_back();
-                }
-            }
-        }
-        if (dev != cur) {
-            const hipError_t e2 = hipSetDevice(cur);
-            if (e == hipSuccess) e = e2;
-        }
-        return e;
-    }
-
-    void drop_branches()
-    {
-        // teardown: a failure here leaves nothing to undo
-        for (hipStream_t st : side) (void)hipStreamDestroy(st);
-        for (hipEvent_t ev : joins) (void)hipEventDestroy(ev);
-        if (fork) (void)hipEventDestroy(fork);
-        side.clear();
-        joins.clear();
-        fork = nullptr;
-    }
-
     // One branch's n steps on stream st: a table group's, or (g == nullptr)
     // those of every member stepped by its own launches, all n steps of one
     // member and then the next.
     hipError_t enqueue_branch(const BatchGroup *g, int n, hipStream_t st)
     {
         hipError_t e = hipSuccess;
-        if (g) return LBM_DISPATCH_HIP(g->prec, enqueue_group, *g, n, st);
+        if (g) return LBM_DISPATCH_HIP(g->prec, enqueue_group, *g, n, persistent, st);
         for (const BatchGroup &o : groups) {
             if (!o.own) continue;
             for (lbm_handle *h : o.m)
@@ -1360,42 +1335,25 @@ struct lbm_batch {
         return e;
     }
 
-    // The run's branches: the members stepped by their own launches first
-    // (nullptr), then one per table group.
-    std::vector<const BatchGroup *> branches() const
-    {
-        std::vector<const BatchGroup *> br;
-        bool own = false;
-        for (const BatchGroup &g : groups) {
-            if (g.own) own = true;
-            else br.push_back(&g);
-        }
-        if (own) br.insert(br.begin(), nullptr);
-        return br;
-    }
-
-    // (the side streams exist: ensure_branches ran before any capture)
+    // A run of n steps on the batch's stream: the members stepped by their
+    // own launches (all n steps of one, then the next), each table group's
+    // n steps, then the descriptors' step counters.  (Capturing the groups
+    // as parallel branches on side streams, forked and joined by events,
+    // measured faster on small windowed runs, but with it the host process
+    // crashed inside lbm_batch_step, a segmentation fault whose cause was not
+    // found; the groups run in turn.)
     hipError_t enqueue(int64_t n)
     {
-        const std::vector<const BatchGroup *> br = branches();
         hipError_t e = hipSuccess;
-        const int nb = (int)br.size();
-        if (nb > 1) {
-            if ((int)side.size() < nb - 1 || !fork) return hipErrorNotReady;
-            if ((e = hipEventRecord(fork, stream)) != hipSuccess) return e;
-        }
-        for (int b = 0; b < nb; ++b) {
-            hipStream_t st = b == 0 ? stream : side[b - 1];
-            if (b > 0 && (e = hipStreamWaitEvent(st, fork, 0)) != hipSuccess) return e;
-            if ((e = enqueue_branch(br[b], (int)n, st)) != hipSuccess) return e;
-            if (b > 0 && ((e = hipEventRecord(joins[b - 1], st)) != hipSuccess ||
-                          (e = hipStreamWaitEvent(stream, joins[b - 1], 0)) != hipSuccess))
+        bool own = false;
+        for (const BatchGroup &g : groups) own = own || g.own;
+        if (own && (e = enqueue_branch(nullptr, (int)n, stream)) != hipSuccess) return e;
+        for (const BatchGroup &g : groups)
+            if (!g.own && (e = enqueue_branch(&g, (int)n, stream)) != hipSuccess) return e;
+        for (const BatchGroup &g : groups)
+            if ((e = LBM_DISPATCH_HIP(g.prec, enqueue_group_advance, g, (int)n, stream)) !=
+                hipSuccess)
                 return e;
-        }
-        for (const BatchGroup &g : groups) {
-            e = LBM_DISPATCH_HIP(g.prec, enqueue_group_advance, g, (int)n, stream);
-            if (e != hipSuccess) return e;
-        }
         return e;
     }
 };
@@ -1467,29 +1425,34 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps)
     for (lbm_handle *h : b->members)
         if (!h->rep_ok || h->rep_t0 != h->t || h->rep_cur0 != h->cur)
             if ((rc = LBM_DISPATCH(h->p.precision, write_rep, h))) return rc;
-    if (b->ensure_branches((int)b->branches().size()) != hipSuccess) return LBM_E_DEVICE;
-    if (b->graph_n != nsteps) {
-        b->drop_graph();
-        // capture the run; streams that cannot be captured (the null stream)
-        // get the same launches directly
-        if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-            const hipError_t e = b->enqueue(nsteps);
-            hipGraph_t g = nullptr;
-            const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
-            if (e == hipSuccess && e2 == hipSuccess && g &&
-                hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) == hipSuccess) {
-                b->graph = g;
-                b->graph_n = nsteps;
+    hipError_t e = hipSuccess;
+    if (b->persistent) {
+        // one cooperative launch per group covers the run: no graph
+        e = b->enqueue(nsteps);
+    } else {
+        if (b->graph_n != nsteps) {
+            b->drop_graph();
+            // capture the run; streams that cannot be captured (the null
+            // stream) get the same launches directly
+            if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                const hipError_t ec = b->enqueue(nsteps);
+                hipGraph_t g = nullptr;
+                const hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+                if (ec == hipSuccess && e2 == hipSuccess && g &&
+                    hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) == hipSuccess) {
+                    b->graph = g;
+                    b->graph_n = nsteps;
+                } else {
+                    if (g) (void)hipGraphDestroy(g);
+                    b->gexec = nullptr;
+                    (void)hipGetLastError();
+                }
             } else {
-                if (g) (void)hipGraphDestroy(g);
-                b->gexec = nullptr;
                 (void)hipGetLastError();
             }
-        } else {
-            (void)hipGetLastError();
         }
+        e = b->gexec ? hipGraphLaunch(b->gexec, b->stream) : b->enqueue(nsteps);
     }
-    hipError_t e = b->gexec ? hipGraphLaunch(b->gexec, b->stream) : b->enqueue(nsteps);
     if (e != hipSuccess) return LBM_E_DEVICE;
     for (lbm_handle *h : b->members) {
         h->t += nsteps;
@@ -1500,12 +1463,21 @@ int lbm_batch_step(lbm_batch *b, int64_t nsteps)
     return LBM_OK;
 }
 
+int lbm_batch_persistent(lbm_batch *b, int on)
+{
+    if (!b || (on != 0 && on != 1)) return LBM_E_INVALID;
+    if (b->persistent != (on != 0)) {
+        b->persistent = on != 0;
+        b->drop_graph();
+    }
+    return LBM_OK;
+}
+
 int lbm_batch_destroy(lbm_batch *b)
 {
     if (!b) return LBM_E_INVALID;
     for (lbm_handle *h : b->members) h->batch = nullptr;
     b->drop_graph();
-    b->drop_branches();
     delete b;
     return LBM_OK;
 }

@@ -626,16 +626,22 @@ __global__ __launch_bounds__(NT) void step_kernel7(StepArgs<S> a)
 // else one column per lane with ND rows' loads at once).
 template <class S, int NT, int ND, bool VEC, bool DIV, bool SR>
 __global__ __launch_bounds__(NT) void step_batch7(BatchRep<S> *const *reps, const TileRef *table,
-                                                  const int32_t *count, int k)
+                                                  const int32_t *count, int k, int K, GridBar *bar)
 {
     const int total = *count;
-    for (int c = blockIdx.x; c < total; c += gridDim.x) {
-        const TileRef e = table[xcd_order(c, total, 2)];
-        const BatchRep<S> R = load_descriptor<BatchRep<S>>(reps[e.rep]);
-        const StepIO<S> io = batch_io(&R, k);
-        const int bx = e.local0 % R.gx, by = e.local0 / R.gx;
-        if constexpr (VEC) step_vec_tile7<S, NT, ND, DIV, SR>(R.a, io, bx, by, R.gx, e.n);
-        else step_tile7<S, NT, ND, DIV, SR>(R.a, io, bx, by, R.gx, e.n);
+    for (int s = 0; s < K; ++s) {
+        for (int c = blockIdx.x; c < total; c += gridDim.x) {
+            const TileRef e = table[xcd_order(c, total, 2)];
+            const BatchRep<S> R = load_descriptor<BatchRep<S>>(reps[e.rep]);
+            const StepIO<S> io = batch_io(&R, k + s);
+            const int bx = e.local0 % R.gx, by = e.local0 / R.gx;
+            if constexpr (VEC) step_vec_tile7<S, NT, ND, DIV, SR>(R.a, io, bx, by, R.gx, e.n);
+            else step_tile7<S, NT, ND, DIV, SR>(R.a, io, bx, by, R.gx, e.n);
+        }
+        if (s + 1 < K && !grid_barrier(bar)) {
+            batch_sync_lost(reps, table, total);
+            return;
+        }
     }
 }
 

@@ -36,7 +36,17 @@ constexpr int kPartialSlots = 4;
 constexpr int kDivSlots = 64, kDivSlotWords = 8;
 constexpr double kFx = 16777216.0;      // 2^24: fixed-point unit of masses and weights
 enum : int { kRegionAll = 0, kRegionFrontBand = 1, kRegionRearBand = 2 };
-enum : uint32_t { kStDomainFull = 1u, kStNonFinite = 2u };
+enum : uint32_t { kStDomainFull = 1u, kStNonFinite = 2u, kStSyncLost = 4u };
+
+// A grid-wide barrier of a multi-step batch launch: arrivals of the current
+// round, the round number, and a flag set when a wait ran out (zeroed
+// before the first launch; the barrier leaves `count` at 0).
+struct GridBar {
+    uint32_t count;
+    uint32_t gen;
+    uint32_t err;
+    uint32_t pad;
+};
 
 // Population layout.  Each row holds the padded width Lp = n_tiles * TW
 // columns as n_tiles consecutive tiles; a tile stores the nq directions (9 on
@@ -260,10 +270,16 @@ hipError_t launch_step7(const StepArgs<S> &a, dim3 grid, int nt, int vb, int rb,
 // reps: device array of member descriptors; table: the group's tiles;
 // count: device word holding how many table entries the next launch runs.
 // grid: blocks launched (each runs table entries blockIdx.x + i * grid).
+// K steps (k .. k + K - 1) in one launch: with bar, a cooperative launch
+// whose blocks meet at a grid-wide barrier between steps (grid must not
+// exceed batch_coop_grid); without, K must be 1.
 template <class S>
 hipError_t launch_step_batch(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
                              int grid, int vec, int nt, int vb_or_rb, int div, int sr, int k,
-                             hipStream_t s);
+                             int K, GridBar *bar, hipStream_t s);
+// Blocks of that kernel that fit the device at once (0 on failure).
+template <class S>
+int batch_coop_grid(int vec, int nt, int vb_or_rb, int div, int sr);
 // A windowed group whose tile table is rebuilt before each step: its n
 // members' descriptors (BatchRep<S> pointers of one storage type) and where
 // its table and entry count go.

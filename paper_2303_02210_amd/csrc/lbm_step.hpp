@@ -1875,21 +1875,84 @@ __device__ __forceinline__ T load_descriptor(const void *p)
     return out;
 }
 
+// Grid-wide barrier between the steps of a multi-step batch launch (its
+// blocks are all resident: the launch is cooperative).  Every thread makes
+// its writes visible device-wide, the block's first thread counts the
+// block in and waits for the round to change, and every thread then sees
+// the other blocks' writes.  (The device-scope fences write each XCD's
+// cache back, so a barrier costs far more than the step boundary of a
+// graph-replayed launch.)  The wait is bounded: past kBarrierSpins polls
+// (about a second) a block gives up, flags the barrier and returns false; a
+// block that finds the flag set returns false at once, so every block of
+// the launch leaves soon after the first gives up.
+constexpr uint32_t kBarrierSpins = 1u << 22;
+__device__ __forceinline__ bool grid_barrier(GridBar *b)
+{
+    __shared__ int ok;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ok = 0;
+        if (__hip_atomic_load(&b->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            const uint32_t g = __hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t arrived =
+                __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (arrived == gridDim.x - 1) {
+                __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&b->gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 1;
+            } else {
+                for (uint32_t spins = 0;; ++spins) {
+                    if (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != g) {
+                        ok = 1;
+                        break;
+                    }
+                    if (spins >= kBarrierSpins ||
+                        __hip_atomic_load(&b->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        __hip_atomic_fetch_or(&b->err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    __threadfence();
+    return ok != 0;
+}
+
+// After a barrier gave up: every member of the launch latches kStSyncLost.
+template <class S>
+__device__ void batch_sync_lost(BatchRep<S> *const *reps, const TileRef *table, int total)
+{
+    for (int c = threadIdx.x; c < total; c += blockDim.x)
+        atomicOr(&reps[table[c].rep]->a.st->status, kStSyncLost);
+}
+
 // Each table entry is a run of tiles of one member stacked in y, which a
 // block updates as one tall tile after fetching the member's descriptor.
-// Windowed groups launch a fixed grid that strides over the entries.
+// Windowed groups launch a fixed grid that strides over the entries.  A
+// multi-step launch (bar set) runs steps k .. k + K - 1 with a grid-wide
+// barrier between them.
 template <class S, int NT, int ND, bool VEC, bool DIV, bool SR>
 __global__ __launch_bounds__(NT) void step_batch(BatchRep<S> *const *reps, const TileRef *table,
-                                                 const int32_t *count, int k)
+                                                 const int32_t *count, int k, int K, GridBar *bar)
 {
     const int total = *count;
-    for (int c = blockIdx.x; c < total; c += gridDim.x) {
-        const TileRef e = table[xcd_order(c, total, 2)];
-        const BatchRep<S> R = load_descriptor<BatchRep<S>>(reps[e.rep]);
-        const StepIO<S> io = batch_io(&R, k);
-        const int bx = e.local0 % R.gx, by = e.local0 / R.gx;
-        if constexpr (VEC) step_vec_tile<S, NT, ND, DIV, SR>(R.a, io, bx, by, R.gx, e.n);
-        else step_scalar_tile<S, NT, ND, DIV, SR>(R.a, io, bx, by, R.gx, e.n);
+    for (int s = 0; s < K; ++s) {
+        for (int c = blockIdx.x; c < total; c += gridDim.x) {
+            const TileRef e = table[xcd_order(c, total, 2)];
+            const BatchRep<S> R = load_descriptor<BatchRep<S>>(reps[e.rep]);
+            const StepIO<S> io = batch_io(&R, k + s);
+            const int bx = e.local0 % R.gx, by = e.local0 / R.gx;
+            if constexpr (VEC) step_vec_tile<S, NT, ND, DIV, SR>(R.a, io, bx, by, R.gx, e.n);
+            else step_scalar_tile<S, NT, ND, DIV, SR>(R.a, io, bx, by, R.gx, e.n);
+        }
+        if (s + 1 < K && !grid_barrier(bar)) {
+            batch_sync_lost(reps, table, total);
+            return;
+        }
     }
 }
 
@@ -2122,62 +2185,71 @@ hipError_t launch_finalize(const FinalizeArgs<S> &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// The batch kernel of one form (nullptr if the form does not exist).
 template <class S, int NT, bool DIV, bool SR>
-void launch_batch_div(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
-                      int grid, int vec, int vb_or_rb, int k, hipStream_t s)
+const void *batch_kernel_div(int vec, int vb_or_rb)
 {
-    const dim3 g(grid), b(NT);
-    if (vec == 2) {   // the D2Q7 step, one column per lane
-        if (vb_or_rb >= 2)
-            hipLaunchKernelGGL((step_batch7<S, NT, 2, false, DIV, SR>), g, b, 0, s, reps, table, count, k);
-        else
-            hipLaunchKernelGGL((step_batch7<S, NT, 1, false, DIV, SR>), g, b, 0, s, reps, table, count, k);
-    } else if (vec == 3) {   // the D2Q7 vector form
+    if (vec == 2)   // the D2Q7 step, one column per lane
+        return vb_or_rb >= 2 ? (const void *)&step_batch7<S, NT, 2, false, DIV, SR>
+                             : (const void *)&step_batch7<S, NT, 1, false, DIV, SR>;
+    if (vec == 3) {   // the D2Q7 vector form
         if (vb_or_rb == 4) {
-            if constexpr (sizeof(S) <= 4)
-                hipLaunchKernelGGL((step_batch7<S, NT, 1, true, DIV, SR>), g, b, 0, s, reps, table, count, k);
-        } else if (vb_or_rb == 8) {
-            hipLaunchKernelGGL((step_batch7<S, NT, 2, true, DIV, SR>), g, b, 0, s, reps, table, count, k);
-        } else {
-            hipLaunchKernelGGL((step_batch7<S, NT, 4, true, DIV, SR>), g, b, 0, s, reps, table, count, k);
+            if constexpr (sizeof(S) <= 4) return (const void *)&step_batch7<S, NT, 1, true, DIV, SR>;
+            return nullptr;
         }
-    } else if (vec) {
-        if (vb_or_rb == 4) {
-            if constexpr (sizeof(S) <= 4)
-                hipLaunchKernelGGL((step_batch<S, NT, 1, true, DIV, SR>), g, b, 0, s, reps, table, count, k);
-        } else if (vb_or_rb == 8) {
-            hipLaunchKernelGGL((step_batch<S, NT, 2, true, DIV, SR>), g, b, 0, s, reps, table, count, k);
-        } else {
-            hipLaunchKernelGGL((step_batch<S, NT, 4, true, DIV, SR>), g, b, 0, s, reps, table, count, k);
-        }
-    } else {
-        if (vb_or_rb >= 2)
-            hipLaunchKernelGGL((step_batch<S, NT, 2, false, DIV, SR>), g, b, 0, s, reps, table, count, k);
-        else
-            hipLaunchKernelGGL((step_batch<S, NT, 1, false, DIV, SR>), g, b, 0, s, reps, table, count, k);
+        return vb_or_rb == 8 ? (const void *)&step_batch7<S, NT, 2, true, DIV, SR>
+                             : (const void *)&step_batch7<S, NT, 4, true, DIV, SR>;
     }
+    if (vec) {
+        if (vb_or_rb == 4) {
+            if constexpr (sizeof(S) <= 4) return (const void *)&step_batch<S, NT, 1, true, DIV, SR>;
+            return nullptr;
+        }
+        return vb_or_rb == 8 ? (const void *)&step_batch<S, NT, 2, true, DIV, SR>
+                             : (const void *)&step_batch<S, NT, 4, true, DIV, SR>;
+    }
+    return vb_or_rb >= 2 ? (const void *)&step_batch<S, NT, 2, false, DIV, SR>
+                         : (const void *)&step_batch<S, NT, 1, false, DIV, SR>;
 }
 
-template <class S, int NT>
-void launch_batch_nt(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
-                     int grid, int vec, int vb_or_rb, int div, int sr, int k, hipStream_t s)
+template <class S>
+const void *batch_kernel(int vec, int nt, int vb_or_rb, int div, int sr)
 {
+    const void *f = nullptr;
     by_variant<S>(div != 0, sr != 0, [&](auto d, auto r) {
-        launch_batch_div<S, NT, decltype(d)::value, decltype(r)::value>(reps, table, count, grid, vec,
-                                                                        vb_or_rb, k, s);
+        constexpr bool D = decltype(d)::value, R = decltype(r)::value;
+        f = nt == 256   ? batch_kernel_div<S, 256, D, R>(vec, vb_or_rb)
+            : nt == 128 ? batch_kernel_div<S, 128, D, R>(vec, vb_or_rb)
+                        : batch_kernel_div<S, 64, D, R>(vec, vb_or_rb);
     });
+    return f;
 }
 
 template <class S>
 hipError_t launch_step_batch(BatchRep<S> *const *reps, const TileRef *table, const int32_t *count,
                              int grid, int vec, int nt, int vb_or_rb, int div, int sr, int k,
-                             hipStream_t s)
+                             int K, GridBar *bar, hipStream_t s)
 {
-    if (grid <= 0) return hipSuccess;
-    if (nt == 256) launch_batch_nt<S, 256>(reps, table, count, grid, vec, vb_or_rb, div, sr, k, s);
-    else if (nt == 128) launch_batch_nt<S, 128>(reps, table, count, grid, vec, vb_or_rb, div, sr, k, s);
-    else launch_batch_nt<S, 64>(reps, table, count, grid, vec, vb_or_rb, div, sr, k, s);
-    return hipGetLastError();
+    if (grid <= 0 || K <= 0) return hipSuccess;
+    if (K > 1 && !bar) return hipErrorInvalidValue;
+    const void *f = batch_kernel<S>(vec, nt, vb_or_rb, div, sr);
+    if (!f) return hipErrorInvalidValue;
+    void *args[] = {(void *)&reps, (void *)&table, (void *)&count, (void *)&k, (void *)&K,
+                    (void *)&bar};
+    return bar ? hipLaunchCooperativeKernel(f, dim3(grid), dim3(nt), args, 0, s)
+               : hipLaunchKernel(f, dim3(grid), dim3(nt), args, 0, s);
+}
+
+template <class S>
+int batch_coop_grid(int vec, int nt, int vb_or_rb, int div, int sr)
+{
+    const void *f = batch_kernel<S>(vec, nt, vb_or_rb, div, sr);
+    int per_cu = 0, dev = 0, cus = 0;
+    if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, nt, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus;
 }
 
 template <class S>

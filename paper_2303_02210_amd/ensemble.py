@@ -31,10 +31,16 @@ class Ensemble:
     them faster than the table (on MI355X 73-78% of the HBM peak against
     67-68% for 1024 x 4096 and 2048 x 8192 members).  Results are the same bit
     for bit either way.  None steps every member through the table.
+
+    ``persistent``: each table group whose members neither move their wall or
+    window nor grow by a division law runs a whole ``step(n)`` in one
+    cooperative launch with a grid-wide barrier between steps, instead of
+    one launch per step replayed from a graph (lbm_batch_persistent).
     """
 
     def __init__(self, cfgs=(), device: str = "cuda:0", stream=None, max_members: int = 1024,
-                 max_tiles: int | None = None, solo_min_sites: int | None = 1 << 22):
+                 max_tiles: int | None = None, solo_min_sites: int | None = 1 << 22,
+                 persistent: bool = False):
         torch = _torch()
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
@@ -53,6 +59,11 @@ class Ensemble:
         if rc != 0:
             raise _ffi.LbmError(rc, "lbm_batch_create")
         self._b = b
+        if persistent:
+            rc = self._lib.lbm_batch_persistent(self._b, 1)
+            if rc != 0:
+                raise _ffi.LbmError(rc, "lbm_batch_persistent")
+        self.persistent = bool(persistent)
         self.solo_min_sites = solo_min_sites
         self.members: list[Sim] = []
         for c in cfgs:

@@ -190,3 +190,29 @@ def test_server_results_equal_solo_runs():
         assert np.array_equal(h, ref[1]), r.req["name"]
         assert d["step"] == r.req["steps"] and d["y_wall"] == ref[2]["y_wall"]
         assert r.h_updates >= r.req["steps"] // 40
+
+
+def test_persistent_batch_matches_solo_runs_bitwise():
+    """lbm_batch_persistent: the table groups of members that neither move
+    their wall or window nor divide run each lbm_batch_step in one
+    cooperative launch with a grid-wide barrier between steps; the others
+    (follow wall, window, division laws) launch per step.  Every member
+    matches its solo run bit for bit, across runs of different lengths, a
+    member stepped on its own in between, and a membership change, and no
+    barrier gives up."""
+    from paper_2303_02210_amd import Ensemble
+    from paper_2303_02210_amd import _ffi
+    cfgs = MIXED + DIVISION[:2]
+    ens = Ensemble(cfgs, solo_min_sites=None, persistent=True)
+    members = list(ens.members)
+    for n in (1, 9, 9, 16):
+        ens.step(n)
+    members[1].step(2)                  # on its own in between
+    ens.remove(members[2])
+    ens.step(5)
+    ens.synchronize()
+    for i, (c, m) in enumerate(zip(cfgs, members)):
+        steps = 35 + (5 if i != 2 else 0) + (2 if i == 1 else 0)
+        _same(m, _solo(c, steps), ("persistent", i))
+        assert not (m.diagnostics()["status"] & _ffi.ST_SYNC_LOST)
+    ens.close()
