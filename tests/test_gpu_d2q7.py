@@ -175,7 +175,8 @@ def test_d2q7_populations_round_trip():
 
 
 def test_d2q7_batch_members_match_solo_runs_bitwise():
-    """D2Q7 members (their own step kernel) batched beside D2Q9 members."""
+    """D2Q7 members (their own step kernel) batched beside D2Q9 members, with
+    per-step launches and with multi-step cooperative launches."""
     from paper_2303_02210_amd import Ensemble
     from tests.test_gpu_batch import _same, _solo
     cfgs = [cfg7(L=128, H=192, init_rows=48, growth_rate=5e-3, sigma=1e-3, precision="fp32", seed=1),
@@ -188,12 +189,14 @@ def test_d2q7_batch_members_match_solo_runs_bitwise():
                  seed=4, kernel_vb=4, kernel_ty=4),
             cfg7(L=128, H=96, init_rows=40, growth="division", growth_rate=1e-2, sigma=1e-2,
                  precision="fp64", seed=5, kernel_vb=16)]
-    ens = Ensemble(cfgs)
-    for n in (8, 8, 13):
-        ens.step(n)
-    ens.synchronize()
-    for i, (c, m) in enumerate(zip(cfgs, ens.members)):
-        _same(m, _solo(c, 29), i)
+    for persistent in (False, True):     # per-step launches; one launch per run
+        ens = Ensemble(cfgs, persistent=persistent)
+        for n in (8, 8, 13):
+            ens.step(n)
+        ens.synchronize()
+        for i, (c, m) in enumerate(zip(cfgs, ens.members)):
+            _same(m, _solo(c, 29), (persistent, i))
+        ens.close()
 
 
 def test_full_size_4096_d2q7_fp32_whole_lattice_parity():
