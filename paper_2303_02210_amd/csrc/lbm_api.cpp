@@ -1297,7 +1297,12 @@ struct lbm_batch {
                 cnt = (int32_t)tab.size();
                 g.grid = cnt;
                 if (g.ndev == 0) {
-                    const int cg = LBM_DISPATCH_COOP(g.prec, g.form, g.nt, g.vbrb, g.div, g.sr);
+                    // (on the device of the batch's stream)
+                    int dev = 0;
+                    hipDevice_t d;
+                    if (stream && hipStreamGetDevice(stream, &d) == hipSuccess) dev = (int)d;
+                    else if (hipGetDevice(&dev) != hipSuccess) return LBM_E_DEVICE;
+                    const int cg = LBM_DISPATCH_COOP(g.prec, g.form, g.nt, g.vbrb, g.div, g.sr, dev);
                     g.coop_grid = std::min(cg, g.grid);
                 }
             }
@@ -1319,10 +1324,10 @@ struct lbm_batch {
         return LBM_OK;
     }
 
-    // One branch's n steps on stream st: a table group's, or (g == nullptr)
-    // those of every member stepped by its own launches, all n steps of one
-    // member and then the next.
-    hipError_t enqueue_branch(const BatchGroup *g, int n, hipStream_t st)
+    // n steps on stream st of a table group, or (g == nullptr) of every
+    // member stepped by its own launches, all n steps of one member and then
+    // the next.
+    hipError_t enqueue_part(const BatchGroup *g, int n, hipStream_t st)
     {
         hipError_t e = hipSuccess;
         if (g) return LBM_DISPATCH_HIP(g->prec, enqueue_group, *g, n, persistent, st);
@@ -1347,9 +1352,9 @@ struct lbm_batch {
         hipError_t e = hipSuccess;
         bool own = false;
         for (const BatchGroup &g : groups) own = own || g.own;
-        if (own && (e = enqueue_branch(nullptr, (int)n, stream)) != hipSuccess) return e;
+        if (own && (e = enqueue_part(nullptr, (int)n, stream)) != hipSuccess) return e;
         for (const BatchGroup &g : groups)
-            if (!g.own && (e = enqueue_branch(&g, (int)n, stream)) != hipSuccess) return e;
+            if (!g.own && (e = enqueue_part(&g, (int)n, stream)) != hipSuccess) return e;
         for (const BatchGroup &g : groups)
             if ((e = LBM_DISPATCH_HIP(g.prec, enqueue_group_advance, g, (int)n, stream)) !=
                 hipSuccess)

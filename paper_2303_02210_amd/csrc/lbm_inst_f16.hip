@@ -16,7 +16,7 @@ namespace lbm {
     template hipError_t launch_step_batch<S>(BatchRep<S> *const *, const TileRef *,           \
                                              const int32_t *, int, int, int, int, int, int, int, \
                                              int, GridBar *, hipStream_t);                  \
-    template int batch_coop_grid<S>(int, int, int, int, int);                                \
+    template int batch_coop_grid<S>(int, int, int, int, int, int);                           \
     template hipError_t launch_plan_batch<S>(const PlanJob *, int, hipStream_t);             \
     template hipError_t launch_finalize_batch<S>(BatchRep<S> *const *, int, int, hipStream_t); \
     template hipError_t launch_batch_advance<S>(BatchRep<S> *const *, int, int, hipStream_t);

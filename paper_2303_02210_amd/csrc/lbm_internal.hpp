@@ -279,7 +279,7 @@ hipError_t launch_step_batch(BatchRep<S> *const *reps, const TileRef *table, con
                              int K, GridBar *bar, hipStream_t s);
 // Blocks of that kernel that fit the device at once (0 on failure).
 template <class S>
-int batch_coop_grid(int vec, int nt, int vb_or_rb, int div, int sr);
+int batch_coop_grid(int vec, int nt, int vb_or_rb, int div, int sr, int device);
 // A windowed group whose tile table is rebuilt before each step: its n
 // members' descriptors (BatchRep<S> pointers of one storage type) and where
 // its table and entry count go.

@@ -2241,13 +2241,12 @@ hipError_t launch_step_batch(BatchRep<S> *const *reps, const TileRef *table, con
 }
 
 template <class S>
-int batch_coop_grid(int vec, int nt, int vb_or_rb, int div, int sr)
+int batch_coop_grid(int vec, int nt, int vb_or_rb, int div, int sr, int device)
 {
     const void *f = batch_kernel<S>(vec, nt, vb_or_rb, div, sr);
-    int per_cu = 0, dev = 0, cus = 0;
+    int per_cu = 0, cus = 0;
     if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, nt, 0) != hipSuccess ||
-        hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         return 0;
     return per_cu * cus;
 }
