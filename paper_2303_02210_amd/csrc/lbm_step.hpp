@@ -2045,11 +2045,57 @@ __device__ void plan_group(const PlanJob &J)
     if (threadIdx.x == 0) *count = carry;
 }
 
+// The same table for a group of at most 64 members, by one wavefront (one
+// lane per member): no block-wide barriers, which dominate the latency of
+// the block-wide form on the small groups of a served trace.
+template <class S>
+__device__ void plan_group_wave(const PlanJob &J)
+{
+    BatchRep<S> *const *reps = reinterpret_cast<BatchRep<S> *const *>(J.reps);
+    const int n = J.n;
+    const int lane = threadIdx.x;
+    int live = 0, gx = 1, ty = 1;
+    if (lane < n) {
+        const BatchRep<S> *R = reps[lane];
+        live = member_live(R);
+        gx = R->gx;
+        ty = R->ty;
+    }
+    const long long tot = wave_reduce((long long)live);
+    const int ry = tot <= kWindowGrid ? 1 : 0;   // as in plan_group
+    const int c = lane < n ? (int)run_count(live / gx, gx, ty, ry) : 0;
+    int incl = c;   // inclusive scan over the lanes
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    const int excl = incl - c;
+    for (int m = 0; m < n; ++m) {
+        const int cm = __shfl(c, m, 64), s0 = __shfl(excl, m, 64), lv = __shfl(live, m, 64);
+        const int gm = __shfl(gx, m, 64), tm = __shfl(ty, m, 64);
+        for (int l = lane; l < cm; l += 64) J.table[s0 + l] = run_ref(m, l, lv / gm, gm, tm, ry);
+        // tiles that ran last step but not this one (as in plan_group)
+        BatchRep<S> *R = reps[m];
+        const int last = R->last_live;
+        for (int b = lv + lane; b < last; b += 64) R->a.partials[kPartialSlots * b] = 0.0;
+        if (lane == 0) R->last_live = lv;
+    }
+    // (the cross-lane read with every lane active: lane 63 must take part)
+    const int total = __shfl(incl, 63, 64);
+    if (lane == 0) *J.count = total;
+}
+
 // One block per windowed group (the first step of a run).
 template <class S>
 __global__ __launch_bounds__(kRedThreads) void plan_batch(const PlanJob *jobs)
 {
-    plan_group<S>(jobs[blockIdx.x]);
+    const PlanJob &J = jobs[blockIdx.x];
+    if (J.n <= 64) {
+        if (threadIdx.x < 64) plan_group_wave<S>(J);
+        return;
+    }
+    plan_group<S>(J);
 }
 
 // One block per member of a group: the between-step work of the
