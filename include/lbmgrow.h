@@ -348,11 +348,12 @@ int lbm_destroy(lbm_handle *h);
  * Batches: many handles of any size and precision advanced together.  Per
  * step there is one kernel launch per group of members sharing a storage
  * type and kernel form, over the flattened table of all their tiles (plus,
- * when any member follows the front or sweeps a window, one launch of the
- * between-step bookkeeping for all of them); large members that do neither
- * are stepped by their own kernels instead (LBM_FLAG_BATCH_OWN), inside the
- * same graph; a run of K steps is captured in a HIP graph and replayed while
- * the membership stays the same.  Every
+ * for a group whose members follow the front, sweep a window or divide, a
+ * launch of their between-step bookkeeping, and for a windowed group one
+ * that rebuilds its table from the members' live rows); large members that
+ * do none of that are stepped by their own kernels instead
+ * (LBM_FLAG_BATCH_OWN), inside the same graph; a run of K steps is captured
+ * in a HIP graph and replayed while the membership stays the same.  Every
  * member keeps its own workspace, state and status, and its populations come
  * out bit for bit as with lbm_step on the handle alone.
  *   lbm_tiles            tiles (thread blocks per step) of a simulation
