@@ -1216,8 +1216,13 @@ struct lbm_batch {
 
     void drop_graph()
     {
-        // teardown: a failure here leaves nothing to undo
-        if (gexec) (void)hipGraphExecDestroy(gexec);
+        // An executable graph may still be running from the last
+        // lbm_batch_step (which does not synchronize): let it finish before
+        // destroying it.  (teardown: a failure here leaves nothing to undo)
+        if (gexec) {
+            (void)hipStreamSynchronize(stream);
+            (void)hipGraphExecDestroy(gexec);
+        }
         if (graph) (void)hipGraphDestroy(graph);
         gexec = nullptr;
         graph = nullptr;
