@@ -200,6 +200,8 @@ def main():
                     help="bulk: wall-clock limit of each served-trace run (s)")
     ap.add_argument("--requests", type=int, default=600, help="served: trace length")
     ap.add_argument("--time-limit", type=float, default=300.0, help="served: wall-clock limit (s)")
+    ap.add_argument("--lanes", type=int, default=6,
+                    help="served: batches by storage type, each on its own stream")
     ap.add_argument("--no-sequential", action="store_true",
                     help="ensemble/served: skip the one-run-at-a-time comparison")
     ap.add_argument("--out", default=None, help="precision: write the curves to this JSON file")
@@ -242,7 +244,7 @@ def main():
                                sequential=not args.no_sequential)
         else:
             rec = run_served(args.served_requests, args.served_time_limit, tuned=False,
-                             sequential=not args.no_sequential)
+                             sequential=not args.no_sequential, lanes=args.lanes)
         print(json.dumps(rec), flush=True)
         return
 
@@ -384,7 +386,7 @@ def child_record(kind: str, args) -> dict:
     cmd = [sys.executable, os.path.abspath(__file__), "--emit-sub", kind,
            "--ensemble-steps", str(args.ensemble_steps),
            "--served-requests", str(args.served_requests),
-           "--served-time-limit", str(args.served_time_limit)]
+           "--served-time-limit", str(args.served_time_limit), "--lanes", str(args.lanes)]
     if args.no_sequential:
         cmd.append("--no-sequential")
     limit = 600 + 3 * args.served_time_limit
@@ -493,13 +495,15 @@ def bench_ensemble(args):
     print(json.dumps(out), flush=True)
 
 
-def run_served(n: int, time_limit: float, tuned: bool = False, sequential: bool = True) -> dict:
+def run_served(n: int, time_limit: float, tuned: bool = False, sequential: bool = True,
+               lanes: int = 6) -> dict:
     """Poisson arrivals at 20 requests/s of runs with L in {128..4096}, H in
     [2L, 4L], 1000-50000 steps, bulk or front-band growth, FP64 / FP32 /
     FP16-offset; admitted by HBM footprint into the running batch; rear wall
     following the front; only live rows swept; front heights streamed back
-    every tick.  Throughput counts the rows actually swept (active MLUPS);
-    its roofline fraction is their algorithmic bytes over the GPU-busy time."""
+    every tick; one batch per storage-type lane, each on its own stream.
+    Throughput counts the rows actually swept (active MLUPS); its roofline
+    fraction is their algorithmic bytes over the GPU-busy time."""
     import torch
     import synth_inputs as si
     from paper_2303_02210_amd.serve import Server, serve_sequential
@@ -508,7 +512,7 @@ def run_served(n: int, time_limit: float, tuned: bool = False, sequential: bool 
     if tuned:
         from paper_2303_02210_amd import autotune
         reqs = [autotune.apply(c) for c in reqs]
-    srv = Server(hbm_budget=200e9, tick_steps=100)
+    srv = Server(hbm_budget=200e9, tick_steps=100, lanes=lanes)
     summ = srv.serve(reqs, time_limit=time_limit, log=log)
     srv.close()
     log(json.dumps(summ))
@@ -533,7 +537,7 @@ def run_served(n: int, time_limit: float, tuned: bool = False, sequential: bool 
     out = {"workload": f"served_poisson20_{n}", "requests": n, "rate_hz": 20.0,
            "widths": [128, 256, 512, 1024, 2048, 4096], "steps_range": [1000, 50000],
            "wall": "follow", "sweep": "window", "hbm_budget_bytes": 200e9, "tick_steps": 100,
-           "time_limit_s": time_limit,
+           "time_limit_s": time_limit, "lanes": lanes,
            "launch_shapes": "autotuner cache" if tuned else "library defaults"}
     out.update(figures(summ))
     out["sequential"] = None if seq is None else figures(seq)
@@ -545,7 +549,7 @@ def run_served(n: int, time_limit: float, tuned: bool = False, sequential: bool 
 def bench_served(args):
     """The served trace on its own JSON line."""
     sv = run_served(args.requests, args.time_limit, tuned=args.tuned,
-                    sequential=not args.no_sequential)
+                    sequential=not args.no_sequential, lanes=args.lanes)
     out = {
         "metric": METRIC, "value": sv["runs_per_hour"], "unit": "runs/hour",
         "n_gpus": 1, "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
@@ -553,7 +557,7 @@ def bench_served(args):
         "data": "synthetic",
         "config": {k: sv[k] for k in ("workload", "requests", "rate_hz", "widths", "steps_range",
                                       "wall", "sweep", "hbm_budget_bytes", "tick_steps",
-                                      "time_limit_s", "launch_shapes")},
+                                      "time_limit_s", "lanes", "launch_shapes")},
         "cpu_baseline": None,
     }
     out.update({k: v for k, v in sv.items() if k not in out["config"]})

@@ -9,6 +9,11 @@ number of steps (at most ``tick_steps``, never past a run's end) through the
 batch API and copies every run's front heights h(x) back to pinned host
 memory.  Results are those of the run stepped alone: the batch changes only
 how tiles are grouped into launches.
+
+The resident runs are split into ``lanes`` batches by storage type and lattice
+width, each on a stream of its own: a served run's step is a chain of short
+launches whose latency sets the pace, and the lanes' chains run side by side
+on the GPU.
 """
 from __future__ import annotations
 
@@ -42,12 +47,26 @@ def active_work(cfg: dict, diag: dict) -> tuple:
     return n, n * bytes_per_update(cfg)
 
 
+_TYPE_CLASS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 2}
+
+
+def lane_index(req: dict, lanes: int) -> int:
+    """The lane of a request: one class per storage type (16-bit types
+    together), split further by lattice width (below 1024 columns or not)
+    when there are at least six lanes; classes beyond the lanes wrap."""
+    c = _TYPE_CLASS.get(req.get("precision", "fp64"), 0)
+    if lanes >= 6 and int(req["L"]) >= 1024:
+        c += 3
+    return c % lanes
+
+
 class Run:
     """One admitted request."""
 
-    def __init__(self, req: dict, sim, arrival: float, admitted: float, pinned):
+    def __init__(self, req: dict, sim, arrival: float, admitted: float, pinned, lane=None):
         self.req = req
         self.sim = sim
+        self.lane = lane
         self.arrival = arrival
         self.admitted = admitted
         self.remaining = int(req["steps"])
@@ -60,10 +79,12 @@ class Run:
 class Server:
     def __init__(self, hbm_budget: float = 200e9, tick_steps: int = 100, device: str = "cuda:0",
                  max_members: int = 1024, max_tiles: int = 1 << 23, keep_results: bool = False,
-                 clock=time.perf_counter):
+                 clock=time.perf_counter, lanes: int = 6):
         torch = _torch()
         self.torch = torch
-        self.ens = Ensemble(device=device, max_members=max_members, max_tiles=max_tiles)
+        # one batch per lane, each on its own (default-priority) stream
+        self.lanes = [Ensemble(device=device, max_members=max_members, max_tiles=max_tiles)
+                      for _ in range(max(1, int(lanes)))]
         self.budget = float(hbm_budget)
         self.used = 0.0
         self.tick_steps = int(tick_steps)
@@ -96,9 +117,10 @@ class Server:
             if self.used + need > self.budget or len(self.running) >= self.max_members:
                 break
             self.queue.popleft()
-            sim = self.ens.add(req)
+            lane = self.lanes[lane_index(req, len(self.lanes))]
+            sim = lane.add(req)
             pinned = self.torch.empty(int(req["L"]), dtype=self.torch.int32).pin_memory()
-            self.running.append(Run(req, sim, req.get("arrival_s", 0.0), now, pinned))
+            self.running.append(Run(req, sim, req.get("arrival_s", 0.0), now, pinned, lane))
             self.used += need
             n += 1
         return n
@@ -106,14 +128,28 @@ class Server:
     # -- one tick ---------------------------------------------------------------
     def tick(self) -> None:
         k = min([self.tick_steps] + [r.remaining for r in self.running])
-        ev0 = self.torch.cuda.Event(enable_timing=True)
-        ev1 = self.torch.cuda.Event(enable_timing=True)
-        ev0.record(self.ens.stream)
-        self.ens.step(k)
-        ev1.record(self.ens.stream)
+        torch = self.torch
+        # GPU-busy time of the tick: from an event every lane waits for to
+        # one recorded after every lane's work
+        first = self.lanes[0].stream
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(first)
+        active = [e for e in self.lanes if e.members]
+        for e in active:
+            if e is not self.lanes[0]:
+                e.stream.wait_event(ev0)
+            e.step(k)
         for r in self.running:
             r.sim.front_heights_async(r.h)
-        self.ens.synchronize()
+        for e in active:
+            if e is not self.lanes[0]:
+                done = torch.cuda.Event()
+                done.record(e.stream)
+                first.wait_event(done)
+        ev1.record(first)
+        for e in self.lanes:
+            e.synchronize()
         self.gpu_busy += ev0.elapsed_time(ev1) / 1e3
         self.ticks += 1
         now = self.now()
@@ -129,7 +165,7 @@ class Server:
                 self.active_bytes += b
                 if self.keep_results:
                     r.result = (r.sim.populations(), r.sim.front_heights(), r.diag)
-                self.ens.remove(r.sim)
+                r.lane.remove(r.sim)
                 r.sim.close()
                 r.sim = None
                 self.used -= workspace_bytes(r.req)
@@ -188,10 +224,11 @@ class Server:
     def close(self) -> None:
         for r in self.running:
             if r.sim is not None:
-                self.ens.remove(r.sim)
+                r.lane.remove(r.sim)
                 r.sim.close()
         self.running = []
-        self.ens.close()
+        for e in self.lanes:
+            e.close()
 
 
 def serve_sequential(requests, time_limit: float | None = None, tick_steps: int = 100,
