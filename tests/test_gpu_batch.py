@@ -169,13 +169,15 @@ def test_batch_member_fault_is_its_own():
 
 
 def test_server_results_equal_solo_runs():
-    """Continuous batching: requests join and leave the running batch at
+    """Continuous batching: requests join and leave the running batches (one
+    per lane: storage type and width class, each on its own stream) at
     different times; each finished run equals the same run stepped alone."""
-    from paper_2303_02210_amd.serve import Server
+    from paper_2303_02210_amd.serve import Server, lane_index
     reqs = []
     for k, (L, H, prec, steps, t) in enumerate([
             (128, 256, "fp32", 230, 0.0), (64, 192, "fp64", 150, 0.0), (256, 512, "fp16", 310, 0.0),
-            (128, 384, "fp32", 120, 0.05), (192, 256, "bf16", 90, 0.1), (64, 128, "fp64", 260, 0.1)]):
+            (128, 384, "fp32", 120, 0.05), (192, 256, "bf16", 90, 0.1), (64, 128, "fp64", 260, 0.1),
+            (1024, 192, "fp16", 70, 0.05), (1024, 160, "fp32", 110, 0.1)]):
         reqs.append(si.cfg(name=f"r{k}", L=L, H=H, init_rows=100, sigma=1e-3, growth_rate=2e-3,
                            ybc="follow", wall_min_gap=20, window=True, precision=prec,
                            steps=steps, seed=k, arrival_s=t))
@@ -190,6 +192,9 @@ def test_server_results_equal_solo_runs():
         assert np.array_equal(h, ref[1]), r.req["name"]
         assert d["step"] == r.req["steps"] and d["y_wall"] == ref[2]["y_wall"]
         assert r.h_updates >= r.req["steps"] // 40
+    # the runs were spread over five of the six lanes
+    assert len({lane_index(q, 6) for q in reqs}) == 5
+    assert len({id(r.lane) for r in srv.done}) == 5
 
 
 def test_persistent_batch_matches_solo_runs_bitwise():
