@@ -19,16 +19,28 @@ namespace lbm {
 // as 1, 2, 3", SC'11).  Ten rounds of: two 32x32->64 multiplications of
 // counter words 0 and 2, halves swapped and xored with counter words 1, 3 and
 // the key; the key advances by the two Weyl increments between rounds.
+//
+// SCALAR_KEYS: the key (seed, replica) is wave-uniform at every call site, a
+// run's constant; pinning it to two scalar registers at the call makes each
+// round's key a scalar add there, where the compiler would otherwise keep all
+// twenty round keys of a kernel live across its row loop.  In the float
+// kernels those twenty ran out of scalar registers (spilled to vector lanes
+// and reloaded at every call, with a few vector spills to scratch); pinned,
+// they measured 1-1.6 points of 8 TB/s faster on every 16-bit form and level
+// on float32, but 2.5 points slower on the float64 step, which keeps the
+// unpinned form.
 // ---------------------------------------------------------------------------
 struct U4 {
     uint32_t v[4];
 };
 
+template <bool SCALAR_KEYS = false>
 __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                        uint32_t k0, uint32_t k1)
 {
     constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
     constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+    if constexpr (SCALAR_KEYS) asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)kMulA * c0;
@@ -58,8 +70,9 @@ template <class R>
 __device__ __forceinline__ void noise_factors(uint32_t seed, uint32_t replica, uint32_t t,
                                               uint32_t x, uint32_t y, R v[9])
 {
-    const U4 a = philox10(x, y, t, 4u * kStreamNoise + 0u, seed, replica);
-    const U4 b = philox10(x, y, t, 4u * kStreamNoise + 1u, seed, replica);
+    constexpr bool pin = sizeof(R) == 4;     // float arithmetic (see philox10)
+    const U4 a = philox10<pin>(x, y, t, 4u * kStreamNoise + 0u, seed, replica);
+    const U4 b = philox10<pin>(x, y, t, 4u * kStreamNoise + 1u, seed, replica);
     uint32_t k[9];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -215,7 +228,7 @@ __device__ __forceinline__ float sround_f16(float o, uint32_t r)
 __device__ __forceinline__ void round_bits(uint32_t seed, uint32_t replica, uint32_t t,
                                            uint32_t x, uint32_t y, uint32_t r[9])
 {
-    const U4 a = philox10(x, y, t, 4u * kStreamRound + 0u, seed, replica);
+    const U4 a = philox10<true>(x, y, t, 4u * kStreamRound + 0u, seed, replica);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         r[2 * k] = a.v[k] & 0x3FFFu;
