@@ -112,7 +112,7 @@ __device__ __forceinline__ void tissue_update7(const StepArgs<S> &a, uint32_t t,
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
         const R c = cu[i];
-        const R fss = (a.w[i] * rho) * (((R(1) + R(4) * c) + R(8) * (c * c)) - u2);
+        const R fss = (a.w[dclass7(i)] * rho) * (((R(1) + R(4) * c) + R(8) * (c * c)) - u2);
         out[i] = fs[i] - a.omega * (fs[i] - fss);
     }
     // ---- step 6: zero-sum noise where rho > rho_c (Eq. 4), seven draws -------
@@ -221,7 +221,7 @@ __device__ __forceinline__ void step_tile7(const StepArgs<S> &a, const StepIO<S>
     const int32_t hp = (a.region == kRegionFrontBand) ? io.h_prev[x] : 0;
     R Wd[7];
 #pragma unroll
-    for (int i = 0; i < 7; ++i) Wd[i] = a.Wd[i];
+    for (int i = 0; i < 7; ++i) Wd[i] = a.Wd[dclass7(i)];
 
     const Tiles tl = a.tl;
     const int64_t cx = tl.col(x), cxm = tl.col(xm), cxp = tl.col(xp);
@@ -385,7 +385,7 @@ __device__ __forceinline__ void step_vec_tile7(const StepArgs<S> &a, const StepI
     }
     R Wd[7];
 #pragma unroll
-    for (int i = 0; i < 7; ++i) Wd[i] = a.Wd[i];
+    for (int i = 0; i < 7; ++i) Wd[i] = a.Wd[dclass7(i)];
     uint32_t epat[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i) {

@@ -14,6 +14,14 @@
 
 namespace lbm {
 
+// Direction classes: the directions of a class share their weight, so their
+// storage offsets and empty patterns are equal too.  Kernels read one value
+// per class (D2Q9: rest 0, axes 1, diagonals 5; D2Q7: rest 0, the six
+// neighbours 1), which keeps three (two) scalar registers live instead of
+// nine (seven).
+__host__ __device__ constexpr int dclass9(int i) { return i == 0 ? 0 : (i <= 4 ? 1 : 5); }
+__host__ __device__ constexpr int dclass7(int i) { return i == 0 ? 0 : 1; }
+
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
 // as 1, 2, 3", SC'11).  Ten rounds of: two 32x32->64 multiplications of

@@ -344,7 +344,7 @@ __device__ __forceinline__ void tissue_update(const StepArgs<S> &a, uint32_t t, 
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const R c = cu[i];
-        const R fss = (a.w[i] * rho) * (((R(1) + R(3) * c) + R(4.5) * (c * c)) - u15);
+        const R fss = (a.w[dclass9(i)] * rho) * (((R(1) + R(3) * c) + R(4.5) * (c * c)) - u15);
         out[i] = fs[i] - a.omega * (fs[i] - fss);
     }
     // ---- step 6: zero-sum noise where rho > rho_c (Eq. 4) ----------------------
@@ -602,7 +602,7 @@ __device__ __forceinline__ void step_scalar_tile(const StepArgs<S> &a, const Ste
     const int32_t hp = (a.region == kRegionFrontBand) ? io.h_prev[x] : 0;
     R Wd[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Wd[i] = a.Wd[i];
+    for (int i = 0; i < 9; ++i) Wd[i] = a.Wd[dclass9(i)];
 
     const Tiles tl = a.tl;
     const int64_t cx = tl.col(x), cxm = tl.col(xm), cxp = tl.col(xp);
@@ -963,7 +963,7 @@ __device__ __forceinline__ void step_vec_tile(const StepArgs<S> &a, const StepIO
     }
     R Wd[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Wd[i] = a.Wd[i];
+    for (int i = 0; i < 9; ++i) Wd[i] = a.Wd[dclass9(i)];
     // bits of an exactly empty population of each direction (0 for float64
     // and float32, -W_i for the 16-bit offsets), as one dword of a vector
     uint32_t epat[9];
@@ -1423,7 +1423,7 @@ __device__ __forceinline__ void step_staged_tile(const StepArgs<S> &a, const Ste
     }
     R Wd[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) Wd[i] = a.Wd[i];
+    for (int i = 0; i < 9; ++i) Wd[i] = a.Wd[dclass9(i)];
 
     const unsigned char *Fb = reinterpret_cast<const unsigned char *>(io.fin);
     unsigned char LBM_GLOBAL *Gb = as_global(reinterpret_cast<unsigned char *>(io.fout));
