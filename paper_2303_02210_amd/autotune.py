@@ -33,12 +33,15 @@ def _pow2(n: int) -> int:
 def key(cfg: dict) -> str:
     """Storage, width and height rounded up to powers of two, and whether a
     division law runs or the 16-bit storage rounds stochastically (those
-    kernels hold more registers)."""
+    kernels hold more registers), and whether growth is confined to a band
+    at the front (the tissue rows then sit in one part of the lattice, and
+    the best shape of the same lattice differs)."""
     div = "/div" if str(cfg.get("growth", "bulk")).startswith("division") else ""
     lat = "/d2q7" if cfg.get("lattice", "d2q9") == "d2q7" else ""
+    band = "/band" if cfg.get("region", "all") == "front_band" else ""
     sr = "/sr" if cfg.get("stochastic_round", False) else ""
     return (f"{cfg.get('precision', 'fp64')}/L{_pow2(int(cfg['L']))}/H{_pow2(int(cfg['H']))}"
-            f"{div}{lat}{sr}")
+            f"{div}{lat}{band}{sr}")
 
 
 def candidates(cfg: dict):

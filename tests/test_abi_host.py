@@ -163,3 +163,21 @@ def test_autotune_keys_and_candidates_for_stochastic_rounding(monkeypatch):
     assert autotune.apply(sr)["kernel_vb"] == 4
     monkeypatch.setattr(autotune, "cache", lambda: {autotune.key(c): {"kernel_vb": 2, "kernel_ty": 32}})
     assert "kernel_vb" not in autotune.apply(sr)
+
+
+def test_autotune_key_separates_front_band_growth():
+    """The edge strip (growth in a band at the front) and a bulk-grown lattice
+    of the same size have different best shapes, so their keys differ; the
+    shipped table holds an entry for each standard workload."""
+    from paper_2303_02210_amd import autotune
+    edge = dict(si.EDGE_2048x8192, precision="fp32")
+    bulk = dict(edge, region="all")
+    assert autotune.key(edge) == autotune.key(bulk) + "/band"
+    assert autotune.key(dict(edge, precision="fp16", stochastic_round=True)).endswith("/band/sr")
+    shipped = autotune._load(autotune.SHIPPED)
+    for p in ("fp32", "fp16", "bf16"):
+        assert autotune.key(dict(edge, precision=p)) in shipped, p
+    for p in ("fp16", "bf16"):
+        assert autotune.key(dict(edge, precision=p, stochastic_round=True)) in shipped, p
+    for c in si.ensemble():
+        assert autotune.key(c) in shipped, c["L"]
