@@ -4,10 +4,10 @@ Requests (workload dicts with a step count and an arrival time) are admitted
 in arrival order whenever their device workspace fits the HBM budget, join the
 running ensemble at the next tick, and leave it as soon as their own step
 count is reached; runs that arrive while others are on the GPU therefore share
-every launch with them.  Each tick advances all resident runs by the same
-number of steps (at most ``tick_steps``, never past a run's end) through the
-batch API and copies every run's front heights h(x) back to pinned host
-memory.  Results are those of the run stepped alone: the batch changes only
+every launch with them.  Each tick advances the resident runs of a lane by
+the same number of steps (at most ``tick_steps``, never past the end of any
+of that lane's runs) through the batch API and copies every run's front
+heights h(x) back to pinned host memory.  Results are those of the run stepped alone: the batch changes only
 how tiles are grouped into launches.
 
 The resident runs are split into ``lanes`` batches by storage type and lattice
@@ -127,7 +127,10 @@ class Server:
 
     # -- one tick ---------------------------------------------------------------
     def tick(self) -> None:
-        k = min([self.tick_steps] + [r.remaining for r in self.running])
+        # each lane advances by its own count: a run about to finish in one
+        # lane does not shorten the others' ticks (nor re-capture their graphs)
+        ks = {id(e): min([self.tick_steps] + [r.remaining for r in self.running if r.lane is e])
+              for e in self.lanes if e.members}
         torch = self.torch
         # GPU-busy time of the tick: from an event every lane waits for to
         # one recorded after every lane's work
@@ -139,7 +142,7 @@ class Server:
         for e in active:
             if e is not self.lanes[0]:
                 e.stream.wait_event(ev0)
-            e.step(k)
+            e.step(ks[id(e)])
         for r in self.running:
             r.sim.front_heights_async(r.h)
         for e in active:
@@ -155,7 +158,7 @@ class Server:
         now = self.now()
         still = []
         for r in self.running:
-            r.remaining -= k
+            r.remaining -= ks[id(r.lane)]
             r.h_updates += 1
             if r.remaining == 0:
                 r.finished = now
